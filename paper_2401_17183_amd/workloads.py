@@ -1,0 +1,257 @@
+"""Seeded synthetic workloads: body-fitted mesh coordinates and initial fields.
+
+This module only generates inputs (node positions from analytic mappings and
+seeded random initial velocities).  It contains none of the method's
+arithmetic and is shared by the HIP path, the tests and the oracle-based
+checks, which is its only purpose.
+
+Every workload is a plain dict:
+  lattice   "D2Q9" | "D3Q19"
+  n         (n_1, .., n_d) real cells per index axis (q^1 fastest in memory)
+  coords    float64 (m_d, .., m_1, d); m_i = n_i + 4 on non-periodic axes
+  faces     per axis (low, high) in {PERIODIC, WALL, FARFIELD}
+  wrap      per axis translation vector (periodic axes)
+  dx        representative spacing (the Delta x of the tangent-vector formula)
+  tau, body_force, rho_inf, u_inf, and optional init fields rho (*n), u (d, *n)
+"""
+import numpy as np
+
+PERIODIC, WALL, FARFIELD = 0, 1, 2
+NGHOST = 2
+SEED = 2401
+
+
+def _cell_eta(n, lo=-1.0, hi=1.0):
+    """Cell-centred parameter values, two ghost layers each side."""
+    j = np.arange(-NGHOST, n + NGHOST)
+    return lo + (j + 0.5) * (hi - lo) / n
+
+
+def _central_min(y):
+    """Smallest central spacing (y_{j+1} - y_{j-1}) / 2 over real nodes."""
+    yr = y[NGHOST - 1: len(y) - NGHOST + 1]
+    return float(np.min((yr[2:] - yr[:-2]) / 2.0))
+
+
+def tanh_channel_2d(n1=64, n2=32, strength=2.0, tau=0.8, G=1e-6):
+    """Plane channel, periodic x, walls at y = +-1, y = tanh(s eta)/tanh(s).
+
+    dx = sqrt(3) * (smallest central wall-normal spacing), streamwise spacing dx.
+    """
+    eta = _cell_eta(n2)
+    y = np.tanh(strength * eta) / np.tanh(strength)
+    dx = np.sqrt(3.0) * _central_min(y)
+    x = np.arange(n1) * dx
+    X = np.empty((len(y), n1, 2))
+    X[..., 0] = x[None, :]
+    X[..., 1] = y[:, None]
+    return {
+        "name": f"D2Q9 tanh({strength}) channel {n1}x{n2}",
+        "lattice": "D2Q9", "n": (n1, n2), "coords": X,
+        "faces": [(PERIODIC, PERIODIC), (WALL, WALL)],
+        "wrap": [(n1 * dx, 0.0), (0.0, 0.0)], "dx": dx,
+        "tau": tau, "body_force": (G, 0.0), "half_height": 1.0 / dx,
+    }
+
+
+def poiseuille_fields(w):
+    """Analytic plane Poiseuille profile u = G (H^2 - Y^2) / (2 nu) in lattice
+    units (Y, H in units of dx), rho = 1; used as the initial state."""
+    n1, n2 = w["n"]
+    nu = (w["tau"] - 0.5) / 3.0
+    y = w["coords"][NGHOST:NGHOST + n2, 0, 1] / w["dx"]
+    H = w["half_height"]
+    G = w["body_force"][0]
+    ux = G * (H * H - y * y) / (2.0 * nu)
+    u = np.zeros((2, n2, n1))
+    u[0] = ux[:, None]
+    return np.ones((n2, n1)), u
+
+
+def tanh_channel_3d(n1=256, n2=128, n3=128, strength=2.5, tau=0.52, G=1e-6,
+                    noise=1e-3, seed=SEED):
+    """Channel: x, z periodic, walls at y = +-1, y = tanh(s eta)/tanh(s);
+    initial rho = 1, u ~ U(-noise, noise) per component (seeded)."""
+    eta = _cell_eta(n2)
+    y = np.tanh(strength * eta) / np.tanh(strength)
+    dx = np.sqrt(3.0) * _central_min(y)
+    X = np.empty((n3, len(y), n1, 3))
+    X[..., 0] = (np.arange(n1) * dx)[None, None, :]
+    X[..., 1] = y[None, :, None]
+    X[..., 2] = (np.arange(n3) * dx)[:, None, None]
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-noise, noise, size=(3, n3, n2, n1))
+    return {
+        "name": f"D3Q19 tanh({strength}) channel {n1}x{n2}x{n3}",
+        "lattice": "D3Q19", "n": (n1, n2, n3), "coords": X,
+        "faces": [(PERIODIC, PERIODIC), (WALL, WALL), (PERIODIC, PERIODIC)],
+        "wrap": [(n1 * dx, 0, 0), (0, 0, 0), (0, 0, n3 * dx)], "dx": dx,
+        "tau": tau, "body_force": (G, 0.0, 0.0),
+        "rho": np.ones((n3, n2, n1)), "u": u,
+    }
+
+
+def ogrid_3d(nr=256, nth=512, nz=64, rmax=20.0, u_inf=0.05, Re=100.0):
+    """O-grid around a unit cylinder: r = rmax^(k/(nr-1)) (log spaced), theta
+    periodic, z periodic with spacing dx; wall at r = 1, far field at r = rmax.
+    dx = radial spacing at r = 1; nu from Re = u_inf * (2 / dx) / nu."""
+    k = np.arange(-NGHOST, nr + NGHOST)
+    r = rmax ** (k / (nr - 1.0))
+    dx = float(r[NGHOST + 1] - r[NGHOST])
+    th = 2.0 * np.pi * np.arange(nth) / nth
+    z = np.arange(nz) * dx
+    X = np.empty((nz, nth, len(r), 3))
+    X[..., 0] = (r[None, None, :] * np.cos(th)[None, :, None])
+    X[..., 1] = (r[None, None, :] * np.sin(th)[None, :, None])
+    X[..., 2] = z[:, None, None]
+    nu = u_inf * (2.0 / dx) / Re
+    tau = 3.0 * nu + 0.5
+    return {
+        "name": f"D3Q19 O-grid {nr}x{nth}x{nz}",
+        "lattice": "D3Q19", "n": (nr, nth, nz), "coords": X,
+        "faces": [(WALL, FARFIELD), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)],
+        "wrap": [(0, 0, 0), (0, 0, 0), (0, 0, nz * dx)], "dx": dx,
+        "tau": tau, "body_force": (0.0, 0.0, 0.0),
+        "rho_inf": 1.0, "u_inf": (u_inf, 0.0, 0.0),
+    }
+
+
+def _stretch01(eta, s):
+    """Map [0,1] -> [0,1], clustering at both ends with centre/wall spacing ~ s."""
+    if s <= 1.0 + 1e-12:
+        return eta
+    sig = np.arccosh(np.sqrt(s))
+    return 0.5 * (1.0 + np.tanh(sig * (2.0 * eta - 1.0)) / np.tanh(sig))
+
+
+def bump_channel_2d(n1, n2, bump, stretch, tau, G=1e-6, H=1.0):
+    """Periodic-x channel with a lower wall bump y_b = bump * sin^8(pi x / L)
+    and a flat upper wall at H; wall-normal tanh clustering of ratio ~stretch.
+    dx = sqrt(3) * smallest central wall-normal spacing of the flat section;
+    L = n1 * dx."""
+    eta = (np.arange(-NGHOST, n2 + NGHOST) + 0.5) / n2
+    prof = _stretch01(eta, stretch)
+    dx = np.sqrt(3.0) * _central_min(prof * H)
+    L = n1 * dx
+    x = np.arange(n1) * dx
+    yb = bump * np.sin(np.pi * x / L) ** 8
+    X = np.empty((len(eta), n1, 2))
+    X[..., 0] = x[None, :]
+    X[..., 1] = yb[None, :] + (H - yb[None, :]) * prof[:, None]
+    # the tangent vectors need smallest spacing over the bumped section too
+    return {
+        "name": f"D2Q9 bump channel {n1}x{n2}",
+        "lattice": "D2Q9", "n": (n1, n2), "coords": X,
+        "faces": [(PERIODIC, PERIODIC), (WALL, WALL)],
+        "wrap": [(L, 0.0), (0.0, 0.0)], "dx": dx,
+        "tau": tau, "body_force": (G, 0.0),
+        "bump": bump, "stretch": stretch, "H": H,
+    }
+
+
+def batch_meshes(count=256, seed=SEED):
+    """The uneven batch: n1 ~ U{32..256}, n2 ~ U{16..128}, bump ~ U[0, 0.3] H,
+    stretch ~ U[1, 3], tau ~ U[0.55, 1.0]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n1 = int(rng.integers(32, 257))
+        n2 = int(rng.integers(16, 129))
+        bump = float(rng.uniform(0.0, 0.3))
+        s = float(rng.uniform(1.0, 3.0))
+        tau = float(rng.uniform(0.55, 1.0))
+        out.append(bump_channel_2d(n1, n2, bump, s, tau))
+    return out
+
+
+def surrogate_meshes(count, seed=SEED, n1=128, n2=64, tau=0.8):
+    """Bump channels at n1 x n2 with bump ~ U[0, 0.3] H, stretch ~ U[1, 3],
+    Re ~ U[10, 100]; G = 12 nu^2 Re / H^3 (flat-channel bulk velocity relation
+    U_b = G H^2 / (12 nu) with H the channel height in units of dx)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    nu = (tau - 0.5) / 3.0
+    for _ in range(count):
+        bump = float(rng.uniform(0.0, 0.3))
+        s = float(rng.uniform(1.0, 3.0))
+        Re = float(rng.uniform(10.0, 100.0))
+        w = bump_channel_2d(n1, n2, bump, s, tau)
+        Hl = w["H"] / w["dx"]
+        G = 12.0 * nu * nu * Re / Hl ** 3
+        w["body_force"] = (G, 0.0)
+        w["Re"] = Re
+        out.append(w)
+    return out
+
+
+def affine_mesh(lattice, n, Amat, origin=None, periodic=True):
+    """x = origin + Amat q (uniform sheared/stretched lattice); periodic in all
+    axes (or walls on axis 2 when periodic is False)."""
+    d = len(n)
+    Amat = np.asarray(Amat, dtype=np.float64)
+    origin = np.zeros(d) if origin is None else np.asarray(origin, dtype=np.float64)
+    axes = []
+    faces = []
+    wrap = []
+    for i in range(d):
+        per = periodic or i != 1
+        q = np.arange(n[i]) if per else np.arange(-NGHOST, n[i] + NGHOST)
+        axes.append(q.astype(np.float64))
+        faces.append((PERIODIC, PERIODIC) if per else (WALL, WALL))
+        wrap.append(tuple(Amat[:, i] * n[i]) if per else tuple([0.0] * d))
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    qs = [grids[d - 1 - i] for i in range(d)]
+    X = np.zeros(grids[0].shape + (d,))
+    for k in range(d):
+        X[..., k] = origin[k] + sum(Amat[k, i] * qs[i] for i in range(d))
+    return {"name": "affine", "lattice": lattice, "n": tuple(n), "coords": X,
+            "faces": faces, "wrap": wrap, "dx": 1.0, "tau": 0.8,
+            "body_force": tuple([0.0] * d)}
+
+
+def wavy_periodic(lattice, n, amp=0.15, seed=SEED, dx=1.0):
+    """Fully periodic mesh with smooth sinusoidal node displacements:
+    x^k = q^k + amp * sum of sines of the other index coordinates; a
+    curvilinear mesh with no boundary, used for the conservation checks."""
+    d = len(n)
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=(d, d))
+    axes = [np.arange(n[i], dtype=np.float64) for i in range(d)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    qs = [grids[d - 1 - i] for i in range(d)]
+    X = np.zeros(grids[0].shape + (d,))
+    for k in range(d):
+        X[..., k] = qs[k]
+        for i in range(d):
+            if i != k:
+                X[..., k] += amp * np.sin(2 * np.pi * qs[i] / n[i] + ph[k, i])
+    X *= dx
+    wrap = [tuple(dx * n[i] * (np.arange(d) == i)) for i in range(d)]
+    return {"name": f"{lattice} wavy periodic {n}", "lattice": lattice, "n": tuple(n),
+            "coords": X, "faces": [(PERIODIC, PERIODIC)] * d, "wrap": wrap, "dx": dx,
+            "tau": 0.8, "body_force": tuple([0.0] * d)}
+
+
+def wavy_channel_3d(n1=16, n2=12, n3=8, amp=0.1, strength=1.5, tau=0.7, G=1e-5, seed=SEED):
+    """Small 3-D curvilinear channel: tanh wall-normal clustering plus a smooth
+    wall-parallel waviness; periodic x, z; walls on y.  Exercises every A^i_a."""
+    eta = _cell_eta(n2)
+    yb = np.tanh(strength * eta) / np.tanh(strength)
+    dx = np.sqrt(3.0) * _central_min(yb) * 1.2
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=4)
+    i = np.arange(n1, dtype=np.float64)[None, None, :]
+    k = np.arange(n3, dtype=np.float64)[:, None, None]
+    y = yb[None, :, None]
+    X = np.empty((n3, len(eta), n1, 3))
+    X[..., 0] = i * dx + amp * dx * np.sin(2 * np.pi * k / n3 + ph[0]) * (1 - y * y)
+    X[..., 1] = y + amp * dx * np.sin(2 * np.pi * i / n1 + ph[1]) * (1 - y * y) \
+        + 0.5 * amp * dx * np.sin(2 * np.pi * k / n3 + ph[2]) * (1 - y * y)
+    X[..., 2] = k * dx + amp * dx * np.sin(2 * np.pi * i / n1 + ph[3]) * (1 - y * y)
+    rng2 = np.random.default_rng(seed + 1)
+    u = rng2.uniform(-1e-3, 1e-3, size=(3, n3, n2, n1))
+    return {"name": f"D3Q19 wavy channel {n1}x{n2}x{n3}", "lattice": "D3Q19",
+            "n": (n1, n2, n3), "coords": X,
+            "faces": [(PERIODIC, PERIODIC), (WALL, WALL), (PERIODIC, PERIODIC)],
+            "wrap": [(n1 * dx, 0, 0), (0, 0, 0), (0, 0, n3 * dx)], "dx": dx,
+            "tau": tau, "body_force": (G, 0.0, 0.0), "rho": np.ones((n3, n2, n1)), "u": u}

@@ -1,0 +1,41 @@
+"""Pins for oracle.stream (eq. (adv)): a permutation, identity after a period."""
+import numpy as np
+import pytest
+
+from oracle import stream as S
+from paper_2401_17183_amd import workloads as W
+from tests.oracle_helpers import mesh_of, sim_of
+
+
+@pytest.mark.parametrize("wl", [W.tanh_channel_2d(6, 5), W.wavy_channel_3d(5, 4, 3),
+                                W.wavy_periodic("D3Q19", (4, 5, 3), 0.1)], ids=lambda w: w["name"])
+def test_stream_is_a_permutation(wl):
+    m = mesh_of(wl)
+    ids = np.arange(m.lat.Q * m.ncells, dtype=np.float64).reshape((m.lat.Q,) + m.shape)
+    out = S.stream(m, ids)
+    assert np.array_equal(np.sort(out.ravel()), ids.ravel())
+
+
+@pytest.mark.parametrize("lat,n", [("D2Q9", (7, 7)), ("D3Q19", (5, 5, 5))])
+def test_period_of_pure_streaming_is_identity(lat, n):
+    wl = W.wavy_periodic(lat, n, 0.1)
+    s = sim_of(wl, stream_only=True)
+    rng = np.random.default_rng(0)
+    N0 = rng.random((s.lat.Q,) + s.mesh.shape)
+    s.set_state(N0)
+    s.step(n[0])
+    assert np.array_equal(s.N, N0)
+    s.step(1)
+    assert not np.array_equal(s.N, N0)
+
+
+def test_bounce_back_period_in_a_channel():
+    """Periodic x (8 cells), walls on y (4 cells): every population returns to its
+    slot after lcm(8, 2*4) = 8 pure-streaming steps, bit for bit."""
+    wl = W.tanh_channel_2d(8, 4)
+    s = sim_of(wl, stream_only=True)
+    rng = np.random.default_rng(1)
+    N0 = rng.random((9,) + s.mesh.shape)
+    s.set_state(N0)
+    s.step(8)
+    assert np.array_equal(s.N, N0)
