@@ -1,0 +1,202 @@
+/*
+ * vlbm.h -- C ABI of the MI355X (gfx950) volumetric curvilinear lattice
+ * Boltzmann library (H. Chen, "Volumetric Lattice Boltzmann Models in General
+ * Curvilinear Coordinates: Theoretical Formulation", arXiv 2401.17183).
+ *
+ * Conventions for every call:
+ *  - Every function returns an int status: VLBM_OK (0) or a negative
+ *    VLBM_ERR_* code; vlbm_last_error() then gives a message (thread-local).
+ *    No exception or C++ type crosses this boundary.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the current device (e.g. a torch tensor's data_ptr()).  Arrays
+ *    passed in are borrowed for the duration of the call and never freed by the
+ *    library.  Handles own everything they allocate and free it in *_destroy.
+ *  - A "stream" argument is a hipStream_t passed as void* (0 = the null
+ *    stream).  A simulation keeps the stream it was created with; all its work
+ *    is enqueued there.
+ *  - Index space: d axes q = (q^1, .., q^d), n_i real cells per axis; cell
+ *    index = q^1 + n_1 (q^2 + n_2 q^3)  (q^1 fastest).  Fields are SoA:
+ *    component-major, [component][cell].
+ *  - Velocity ordering (Q directions, rest first, then opposite pairs):
+ *    D2Q9 : (0,0) (1,0)(-1,0) (0,1)(0,-1) (1,1)(-1,-1) (1,-1)(-1,1)
+ *    D3Q19: (0,0,0) (+-1,0,0) (0,+-1,0) (0,0,+-1) (1,1,0)(-1,-1,0) (1,-1,0)(-1,1,0)
+ *           (1,0,1)(-1,0,-1) (1,0,-1)(-1,0,1) (0,1,1)(0,-1,-1) (0,1,-1)(0,-1,1)
+ *    with weights 4/9,1/9,1/36 (D2Q9) and 1/3,1/18,1/36 (D3Q19), T0 = 1/3
+ *    (velocity set and T0: Sec. 2.1 around eq. (iso)).
+ */
+#ifndef VLBM_H
+#define VLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { VLBM_D2Q9 = 0, VLBM_D3Q19 = 1 };
+
+/* Storage / compute precision of a simulation.  FP64 and FP32 store and compute
+ * in that type; FP16S and BF16S store scaled deviations from the per-cell rest
+ * equilibrium in 16 bits and compute in FP32. */
+enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP16S = 2, VLBM_BF16S = 3 };
+
+enum { VLBM_PERIODIC = 0, VLBM_WALL = 1, VLBM_FARFIELD = 2 };
+
+enum {
+  VLBM_OK = 0,
+  VLBM_ERR_ARG = -1,        /* invalid argument (null, sizes, tau <= 1/2, ...)      */
+  VLBM_ERR_MESH = -2,       /* degenerate mesh: beta undefined or J <= 0            */
+  VLBM_ERR_NOMEM = -3,      /* device allocation failed                              */
+  VLBM_ERR_DEVICE = -4,     /* a HIP call or kernel failed                           */
+  VLBM_ERR_NOCONVERGE = -5, /* the collision fixed point hit its iteration cap       */
+  VLBM_ERR_STATE = -6,      /* call out of order (e.g. step before init)             */
+  VLBM_ERR_NONFINITE = -7,  /* non-finite populations were detected                  */
+  VLBM_ERR_UNSUPPORTED = -8 /* combination not built (e.g. precision x lattice)      */
+};
+
+typedef struct vlbm_mesh_s* vlbm_mesh;
+typedef struct vlbm_sim_s* vlbm_sim;
+
+/* Boundary kinds per index axis and face (0 = low, 1 = high).  An axis is
+ * periodic on both faces or on neither.  wrap[i] is the Euclidean translation
+ * L_i of a periodic axis: x(q + n_i e_i) = x(q) + L_i (ignored otherwise).
+ * Walls are halfway bounce-back; far-field faces impose equilibrium
+ * populations (boundary treatment is outside the paper's scope: these are the
+ * library's readings). */
+typedef struct {
+  int32_t face[3][2];
+  double wrap[3][3];
+} vlbm_topology;
+
+/* Lattice tables.  Q, d: host int32 out; c: host int32 [Q][d] out (may be NULL);
+ * w: host double [Q] out (may be NULL). */
+int vlbm_lattice_info(int lattice, int32_t* Q, int32_t* d, int32_t* c, double* w);
+
+/* Create a mesh from node coordinates (Sec. 2.1: the node set x(q) on a unit
+ * index lattice).
+ *  n        host int64[3]: real cells per axis (n[2] = 1 for D2Q9).
+ *  coords   host double [m_d]..[m_1][d], m_i = n_i + 4 on non-periodic axes
+ *           (two ghost node layers per face), m_i = n_i on periodic axes.
+ *  topo     host, faces and wrap translations.
+ *  dx       the representative spacing of the tangent-vector formula (> 0).
+ * The coordinates are copied to the device; nothing is computed yet.
+ * Errors: VLBM_ERR_ARG for bad sizes/faces, VLBM_ERR_NOMEM. */
+int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords,
+                     const vlbm_topology* topo, double dx, vlbm_mesh* out);
+
+typedef struct {
+  double min_J, max_J;               /* cell volume range (eq. (jacobian))          */
+  double min_gup_eig, max_gup_eig;   /* eigenvalue range of g^{ij} (eq. (inverse))   */
+  double min_rest_feq_over_w;        /* min over cells, a of f^eq(rho=1,U=0)/w_a     */
+  double max_abs_A;                  /* max |A^i_a|, the contracted Theta           */
+} vlbm_geom_report;
+
+/* FP64 geometry precompute on the device, once per mesh (Sec. 2.1: the
+ * quantities "can be pre-computed before starting" a simulation):
+ * D_{+-i} (eq. (distance)), beta_i and g_i (eq. (tangent)), J (eq. (jacobian)),
+ * g^i (eq. (covectors)), g^{ij} (eq. (inverse)) on real cells and the first
+ * ghost layer, then the link coefficients
+ *   A^i_a(q) = sum_j c_a^j Theta^i_j(q + c_a, q) = [e_a(q + c_a) - e_a(q)] . g^i(q)
+ * (eqs. (lattice), (gamma)) on real cells.  Synchronises the stream and fills
+ * rep (host, may be NULL).  Errors: VLBM_ERR_MESH when some |D_i - D_-i| = 0 or
+ * J <= 0 (reorder axes for a positive handedness), VLBM_ERR_DEVICE. */
+int vlbm_geometry_precompute(vlbm_mesh m, void* stream, vlbm_geom_report* rep);
+
+/* Copy FP64 geometry to device arrays (any may be NULL):
+ *  J [cells]; gup [d*d][cells] (full symmetric matrix, row-major ij);
+ *  A [Q][d][cells] (A of the rest direction is 0); g [d][d][cells] (g_i
+ *  Euclidean components, [i][k]).  Synchronous.  VLBM_ERR_STATE before
+ *  vlbm_geometry_precompute. */
+int vlbm_geometry_fields(vlbm_mesh m, double* J, double* gup, double* A, double* g);
+
+typedef struct {
+  double tau;            /* BGK relaxation time (eq. (collide)); must exceed 1/2      */
+  double body_force[3];  /* Euclidean body acceleration G (a reading, not in the paper) */
+  double rho_inf;        /* far-field density                                          */
+  double u_inf[3];       /* far-field Euclidean velocity                               */
+  int32_t precision;     /* VLBM_FP64 / VLBM_FP32 / VLBM_FP16S / VLBM_BF16S            */
+  int32_t fp_max_iter;   /* cap of the per-cell collision fixed point (<= 0: 50)       */
+  double fp_tol;         /* stop when max_i |F_k - F_(k-1)| <= fp_tol * rho (< 0: default) */
+  int32_t audit_every;   /* enqueue an audit every k steps (0 = never)                 */
+  int32_t stream_only;   /* 1: advection only, no collision (a permutation test mode)  */
+} vlbm_params;
+
+/* Create a simulation on a precomputed mesh and set the initial state
+ * N(0) = J f^eq(rho, U, Ut) with Ut^i = u . g^i and U chosen so that the
+ * collision fixed point of N(0) reproduces Ut (the paper gives no initial
+ * state: this is the library's reading).
+ *  rho  device double [cells] or NULL (rho = 1);
+ *  u    device double [d][cells] Euclidean velocity or NULL (u = 0).
+ * Errors: VLBM_ERR_ARG (tau <= 1/2, bad precision), VLBM_ERR_STATE (geometry
+ * not precomputed), VLBM_ERR_NOCONVERGE, VLBM_ERR_NOMEM, VLBM_ERR_DEVICE. */
+int vlbm_init(vlbm_mesh m, const vlbm_params* p, const double* rho, const double* u,
+              void* stream, vlbm_sim* out);
+
+/* Advance nsteps time steps: the fused pull-advection (eq. (adv)) + BGK
+ * collision (eq. (collide)) + inertial force (eqs. (compo-constr),
+ * (delta-flux), (deltaN)) + curvilinear equilibrium (eq. (equilibrium)) update
+ * of eq. (lbe), with the implicit force solved per cell as a converged fixed
+ * point.  Asynchronous: returns after enqueueing on the sim's stream. */
+int vlbm_step(vlbm_sim s, int64_t nsteps);
+
+/* Output mapping (eq. (result)) of the current state, computed in FP64 after a
+ * dry-run of the collision fixed point:
+ *  rho  device double [cells];
+ *  u    device double [d][cells]: Euclidean velocity Ut^i g_i (the shifted
+ *       velocity Ut = U + F/(2 rho) that obeys the continuity equation);
+ *  U    device double [d][cells] or NULL: contravariant first moment U^i.
+ * Synchronises the stream.  Errors: VLBM_ERR_NOCONVERGE, VLBM_ERR_DEVICE. */
+int vlbm_moments(vlbm_sim s, double* rho, double* u, double* U);
+
+/* Current arrived populations N_a(q, t) as FP64 into device double [Q][cells]
+ * (converted from the storage precision).  Synchronises. */
+int vlbm_populations(vlbm_sim s, double* N);
+
+/* Replace the state by device double [Q][cells] arrived populations
+ * (converted to the storage precision).  Synchronises. */
+int vlbm_set_populations(vlbm_sim s, const double* N);
+
+typedef struct {
+  int64_t step;
+  double mass;             /* sum_q sum_a N_a                                        */
+  double mom_I[3];         /* mid-link Euclidean momentum 1/2 sum [e_a(q)+e_a(q-c_a)] N_a */
+  double wall_impulse[3];  /* impulse taken by bounced links in the step before       */
+  double force_impulse[3]; /* body-force impulse per step, G * mass                   */
+  double residual;         /* ||u - u_prev|| / ||u|| since the previous audit (NaN first) */
+  int32_t max_fp_iters;    /* largest fixed-point iteration count of the dry run      */
+  int32_t nonfinite;       /* populations that are NaN or Inf                          */
+  int32_t negative;        /* populations below zero                                   */
+  int32_t unconverged;     /* cells whose fixed point hit the cap                      */
+} vlbm_audit;
+
+/* Enqueue an audit of the current state into the sim's device ring buffer
+ * (FP64 wavefront + block reductions, deterministic order; no host sync). */
+int vlbm_audit_now(vlbm_sim s);
+
+/* Drain up to cap audits, oldest first, into host out; *n_out = number copied.
+ * Synchronises.  Returns VLBM_ERR_NONFINITE if any drained audit saw
+ * non-finite populations (the records are still copied). */
+int vlbm_audits(vlbm_sim s, vlbm_audit* out, int cap, int* n_out);
+
+/* Checkpoint: raw storage-precision populations, step counter and params into
+ * host memory.  With buf == NULL only *used (the size needed) is set. */
+int vlbm_save(vlbm_sim s, void* buf, size_t cap, size_t* used);
+/* Restore a checkpoint written by vlbm_save for a sim on the same mesh with the
+ * same precision.  Errors: VLBM_ERR_ARG on a size or header mismatch. */
+int vlbm_restore(vlbm_sim s, const void* buf, size_t size);
+
+/* Steps taken since init (host int64 out). */
+int vlbm_sim_step_count(vlbm_sim s, int64_t* t);
+
+int vlbm_sim_destroy(vlbm_sim s);
+int vlbm_mesh_destroy(vlbm_mesh m);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* vlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLBM_H */

@@ -1,0 +1,428 @@
+// Host side of the C ABI declared in include/vlbm.h: handle objects, argument
+// validation, error strings, the launch sequence of each call.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.hpp"
+
+namespace vlbm {
+int audit_partial_blocks(const MeshObj* m);
+int audit_words();
+}  // namespace vlbm
+
+using namespace vlbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_err[0] = 0;
+  return VLBM_OK;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                          \
+    hipError_t _e = (expr);                                                                     \
+    if (_e != hipSuccess) return fail(VLBM_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+template <class T> int dev_alloc(T** p, size_t bytes) {
+  if (hipMalloc((void**)p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(VLBM_ERR_NOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  return VLBM_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+size_t storage_bytes(int precision) { return precision == VLBM_FP64 ? 8 : 4; }
+
+constexpr uint64_t kMagic = 0x314d42564c4d4956ull;  // checkpoint tag
+
+struct CkptHeader {
+  uint64_t magic;
+  int32_t lattice, precision;
+  int64_t ncells, Q, t;
+  int64_t bytes;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* vlbm_last_error(void) { return g_err; }
+
+int vlbm_lattice_info(int lattice, int32_t* Q, int32_t* d, int32_t* c, double* w) {
+  if (!Q || !d) return fail(VLBM_ERR_ARG, "vlbm_lattice_info: null output");
+  if (lattice == VLBM_D2Q9) {
+    *Q = D2Q9::Q;
+    *d = D2Q9::D;
+    for (int a = 0; a < D2Q9::Q; ++a) {
+      for (int i = 0; i < 2; ++i)
+        if (c) c[a * 2 + i] = D2Q9::c(a, i);
+      if (w) w[a] = D2Q9::w(a);
+    }
+  } else if (lattice == VLBM_D3Q19) {
+    *Q = D3Q19::Q;
+    *d = D3Q19::D;
+    for (int a = 0; a < D3Q19::Q; ++a) {
+      for (int i = 0; i < 3; ++i)
+        if (c) c[a * 3 + i] = D3Q19::c(a, i);
+      if (w) w[a] = D3Q19::w(a);
+    }
+  } else {
+    return fail(VLBM_ERR_ARG, "unknown lattice %d", lattice);
+  }
+  return ok();
+}
+
+int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, const vlbm_topology* topo, double dx,
+                     vlbm_mesh* out) {
+  if (!n || !coords || !topo || !out) return fail(VLBM_ERR_ARG, "vlbm_mesh_create: null argument");
+  *out = nullptr;
+  if (lattice != VLBM_D2Q9 && lattice != VLBM_D3Q19) return fail(VLBM_ERR_ARG, "unknown lattice %d", lattice);
+  if (!(dx > 0.0) || !isfinite(dx)) return fail(VLBM_ERR_ARG, "dx must be positive and finite");
+  const int d = lattice == VLBM_D2Q9 ? 2 : 3;
+  if (d == 2 && n[2] != 1) return fail(VLBM_ERR_ARG, "D2Q9 needs n[2] == 1");
+  int64_t nc = 1;
+  for (int i = 0; i < d; ++i) {
+    if (n[i] < 1 || n[i] > (1 << 20)) return fail(VLBM_ERR_ARG, "n[%d] = %lld out of range", i, (long long)n[i]);
+    nc *= n[i];
+  }
+  if (nc > (int64_t)0x3fffffff) return fail(VLBM_ERR_ARG, "too many cells (%lld)", (long long)nc);
+  MeshObj* m = new (std::nothrow) MeshObj();
+  if (!m) return fail(VLBM_ERR_NOMEM, "host allocation failed");
+  m->lattice = lattice;
+  m->d = d;
+  m->Q = d == 2 ? 9 : 19;
+  m->dx = dx;
+  size_t ncoord = (size_t)d;
+  for (int i = 0; i < 3; ++i) {
+    const bool active = i < d;
+    m->box.n[i] = active ? (int)n[i] : 1;
+    for (int f = 0; f < 2; ++f) m->box.face[i][f] = active ? topo->face[i][f] : VLBM_PERIODIC;
+    if (active) {
+      const int lo = topo->face[i][0], hi = topo->face[i][1];
+      if (lo < 0 || lo > 2 || hi < 0 || hi > 2) {
+        delete m;
+        return fail(VLBM_ERR_ARG, "axis %d: unknown face kind", i);
+      }
+      if ((lo == VLBM_PERIODIC) != (hi == VLBM_PERIODIC)) {
+        delete m;
+        return fail(VLBM_ERR_ARG, "axis %d must be periodic on both faces or on neither", i);
+      }
+      if (lo == VLBM_PERIODIC && n[i] < 2) {
+        delete m;
+        return fail(VLBM_ERR_ARG, "periodic axis %d needs at least 2 cells", i);
+      }
+    }
+    m->m[i] = !active ? 1 : (m->box.face[i][0] == VLBM_PERIODIC ? (int)n[i] : (int)n[i] + 4);
+    ncoord *= m->m[i];
+    for (int k = 0; k < 3; ++k) m->wrap[i][k] = (active && k < d) ? topo->wrap[i][k] : 0.0;
+  }
+  m->box.ncells = (int)nc;
+  int rc = dev_alloc(&m->coords, ncoord * sizeof(double));
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  if (hipMemcpy(m->coords, coords, ncoord * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    dev_free(m->coords);
+    delete m;
+    return fail(VLBM_ERR_DEVICE, "copy of coordinates failed");
+  }
+  *out = reinterpret_cast<vlbm_mesh>(m);
+  return ok();
+}
+
+int vlbm_mesh_destroy(vlbm_mesh mh) {
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m) return ok();
+  dev_free(m->coords);
+  dev_free(m->J);
+  dev_free(m->gup);
+  dev_free(m->gco);
+  dev_free(m->g);
+  dev_free(m->A);
+  delete m;
+  return ok();
+}
+
+int vlbm_geometry_precompute(vlbm_mesh mh, void* stream, vlbm_geom_report* rep) {
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m) return fail(VLBM_ERR_ARG, "null mesh");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nc = m->box.ncells;
+  const int d = m->d;
+  int rc;
+  if (!m->J) {
+    if ((rc = dev_alloc(&m->J, nc * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(&m->gup, nc * d * d * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(&m->gco, nc * d * d * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(&m->g, nc * d * d * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(&m->A, nc * m->Q * d * sizeof(double)))) return rc;
+  }
+  const int nb = geometry_partial_blocks(m);
+  int* dflag = nullptr;
+  double* partial = nullptr;
+  if ((rc = dev_alloc(&dflag, sizeof(int)))) return rc;
+  if ((rc = dev_alloc(&partial, (size_t)nb * 6 * sizeof(double)))) {
+    dev_free(dflag);
+    return rc;
+  }
+  hipError_t e = hipMemsetAsync(dflag, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_geometry(m, s, dflag, partial, nb);
+  int flag = 0;
+  double* hp = new double[(size_t)nb * 6];
+  if (e == hipSuccess) e = hipMemcpy(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hp, partial, (size_t)nb * 6 * sizeof(double), hipMemcpyDeviceToHost);
+  dev_free(dflag);
+  dev_free(partial);
+  if (e != hipSuccess) {
+    delete[] hp;
+    return fail(VLBM_ERR_DEVICE, "geometry precompute: %s", hipGetErrorString(e));
+  }
+  if (flag) {
+    delete[] hp;
+    m->have_geometry = false;
+    return fail(VLBM_ERR_MESH, "degenerate mesh:%s%s", (flag & 1) ? " beta undefined (D_i == D_-i)" : "",
+                (flag & 2) ? " J <= 0 (reorder axes for a positive handedness)" : "");
+  }
+  double r[6];
+  for (int k = 0; k < 6; ++k) r[k] = INFINITY;
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < 6; ++k) r[k] = fmin(r[k], hp[b * 6 + k]);
+  delete[] hp;
+  m->report.min_J = r[0];
+  m->report.max_J = -r[1];
+  m->report.min_gup_eig = r[2];
+  m->report.max_gup_eig = -r[3];
+  m->report.min_rest_feq_over_w = r[4];
+  m->report.max_abs_A = -r[5];
+  m->have_geometry = true;
+  if (rep) *rep = m->report;
+  return ok();
+}
+
+int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double* g) {
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m) return fail(VLBM_ERR_ARG, "null mesh");
+  if (!m->have_geometry) return fail(VLBM_ERR_STATE, "geometry not precomputed");
+  const size_t nc = m->box.ncells;
+  const int d = m->d;
+  if (J) HIP_TRY(hipMemcpy(J, m->J, nc * sizeof(double), hipMemcpyDeviceToDevice));
+  if (gup) HIP_TRY(hipMemcpy(gup, m->gup, nc * d * d * sizeof(double), hipMemcpyDeviceToDevice));
+  if (A) HIP_TRY(hipMemcpy(A, m->A, nc * m->Q * d * sizeof(double), hipMemcpyDeviceToDevice));
+  if (g) HIP_TRY(hipMemcpy(g, m->g, nc * d * d * sizeof(double), hipMemcpyDeviceToDevice));
+  return ok();
+}
+
+int vlbm_sim_destroy(vlbm_sim sh) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return ok();
+  dev_free(s->pop[0]);
+  dev_free(s->pop[1]);
+  dev_free(s->geo);
+  dev_free(s->audit_ring);
+  dev_free(s->audit_partial);
+  dev_free(s->u_prev);
+  dev_free(s->flags);
+  delete s;
+  return ok();
+}
+
+int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const double* u, void* stream, vlbm_sim* out) {
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m || !p || !out) return fail(VLBM_ERR_ARG, "vlbm_init: null argument");
+  *out = nullptr;
+  if (!m->have_geometry) return fail(VLBM_ERR_STATE, "vlbm_init before vlbm_geometry_precompute");
+  if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(VLBM_ERR_ARG, "tau must exceed 1/2 (got %g)", p->tau);
+  if (p->precision != VLBM_FP64 && p->precision != VLBM_FP32)
+    return fail(VLBM_ERR_UNSUPPORTED, "precision %d is not built", p->precision);
+  if (p->audit_every < 0) return fail(VLBM_ERR_ARG, "audit_every must be >= 0");
+  SimObj* s = new (std::nothrow) SimObj();
+  if (!s) return fail(VLBM_ERR_NOMEM, "host allocation failed");
+  s->mesh = m;
+  s->p = *p;
+  if (s->p.fp_max_iter <= 0) s->p.fp_max_iter = 50;
+  if (s->p.fp_tol < 0) s->p.fp_tol = s->p.precision == VLBM_FP64 ? 1e-14 : 1e-7;
+  s->stream = static_cast<hipStream_t>(stream);
+  const int d = m->d;
+  for (int k = 0; k < d; ++k)
+    if (p->body_force[k] != 0.0) s->has_force = 1;
+  for (int i = 0; i < d; ++i)
+    for (int f = 0; f < 2; ++f)
+      if (m->box.face[i][f] == VLBM_FARFIELD) s->has_farfield = 1;
+  const size_t nc = m->box.ncells;
+  const size_t sb = storage_bytes(s->p.precision);
+  s->pop_bytes = nc * m->Q * sb;
+  int rc;
+  auto bail = [&](int code) {
+    vlbm_sim_destroy(reinterpret_cast<vlbm_sim>(s));
+    return code;
+  };
+  if ((rc = dev_alloc(&s->pop[0], s->pop_bytes))) return bail(rc);
+  if ((rc = dev_alloc(&s->pop[1], s->pop_bytes))) return bail(rc);
+  const int words = m->lattice == VLBM_D2Q9 ? Pack<D2Q9>::WORDS : Pack<D3Q19>::WORDS;
+  if ((rc = dev_alloc(&s->geo, nc * words * sb))) return bail(rc);
+  s->audit_cap = 4096;
+  if ((rc = dev_alloc(&s->audit_ring, sizeof(vlbm_audit) * s->audit_cap))) return bail(rc);
+  s->audit_blocks = audit_partial_blocks(m);
+  if ((rc = dev_alloc(&s->audit_partial, sizeof(double) * s->audit_blocks * audit_words()))) return bail(rc);
+  if ((rc = dev_alloc(&s->u_prev, sizeof(double) * nc * d))) return bail(rc);
+  if ((rc = dev_alloc(&s->flags, sizeof(int) * 4))) return bail(rc);
+  hipError_t e = hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream);
+  if (e == hipSuccess) e = launch_pack(s);
+  if (e == hipSuccess) e = launch_init(s, rho, u, s->flags);
+  int hflag = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    fail(VLBM_ERR_DEVICE, "vlbm_init: %s", hipGetErrorString(e));
+    return bail(VLBM_ERR_DEVICE);
+  }
+  if (hflag) {
+    fail(VLBM_ERR_NOCONVERGE, "initial-state fixed point did not converge in %d cells", hflag);
+    return bail(VLBM_ERR_NOCONVERGE);
+  }
+  (void)hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream);
+  s->buf = 0;
+  s->t = 0;
+  *out = reinterpret_cast<vlbm_sim>(s);
+  return ok();
+}
+
+int vlbm_audit_now(vlbm_sim sh) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  const int slot = (int)(s->audit_head % s->audit_cap);
+  HIP_TRY(launch_audit(s, slot));
+  s->audit_head++;
+  if (s->audit_head - s->audit_tail > s->audit_cap) s->audit_tail = s->audit_head - s->audit_cap;
+  return ok();
+}
+
+int vlbm_step(vlbm_sim sh, int64_t nsteps) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  if (nsteps < 0) return fail(VLBM_ERR_ARG, "nsteps < 0");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIP_TRY(launch_step(s));
+    s->buf ^= 1;
+    s->t++;
+    if (s->p.audit_every > 0 && s->t % s->p.audit_every == 0) {
+      int rc = vlbm_audit_now(sh);
+      if (rc) return rc;
+    }
+  }
+  return ok();
+}
+
+int vlbm_moments(vlbm_sim sh, double* rho, double* u, double* U) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !rho || !u) return fail(VLBM_ERR_ARG, "vlbm_moments: null argument");
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
+  HIP_TRY(launch_moments(s, rho, u, U, s->flags));
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (hflag) return fail(VLBM_ERR_NOCONVERGE, "fixed point did not converge in %d cells", hflag);
+  return ok();
+}
+
+int vlbm_populations(vlbm_sim sh, double* N) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !N) return fail(VLBM_ERR_ARG, "vlbm_populations: null argument");
+  HIP_TRY(launch_get_pop(s, N));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return ok();
+}
+
+int vlbm_set_populations(vlbm_sim sh, const double* N) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !N) return fail(VLBM_ERR_ARG, "vlbm_set_populations: null argument");
+  HIP_TRY(launch_set_pop(s, N));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return ok();
+}
+
+int vlbm_audits(vlbm_sim sh, vlbm_audit* out, int cap, int* n_out) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !n_out || (cap > 0 && !out)) return fail(VLBM_ERR_ARG, "vlbm_audits: null argument");
+  *n_out = 0;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int n = 0;
+  bool bad = false;
+  vlbm_audit* ring = static_cast<vlbm_audit*>(s->audit_ring);
+  while (n < cap && s->audit_tail < s->audit_head) {
+    const int slot = (int)(s->audit_tail % s->audit_cap);
+    HIP_TRY(hipMemcpy(out + n, ring + slot, sizeof(vlbm_audit), hipMemcpyDeviceToHost));
+    if (out[n].nonfinite) bad = true;
+    ++n;
+    s->audit_tail++;
+  }
+  *n_out = n;
+  if (bad) return fail(VLBM_ERR_NONFINITE, "non-finite populations detected");
+  return ok();
+}
+
+int vlbm_save(vlbm_sim sh, void* buf, size_t cap, size_t* used) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !used) return fail(VLBM_ERR_ARG, "vlbm_save: null argument");
+  const size_t need = sizeof(CkptHeader) + s->pop_bytes;
+  *used = need;
+  if (!buf) return ok();
+  if (cap < need) return fail(VLBM_ERR_ARG, "buffer too small: need %zu bytes", need);
+  CkptHeader h{kMagic, s->mesh->lattice, s->p.precision, s->mesh->box.ncells, s->mesh->Q, s->t,
+               (int64_t)s->pop_bytes};
+  memcpy(buf, &h, sizeof(h));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy(static_cast<char*>(buf) + sizeof(h), s->pop[s->buf], s->pop_bytes, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+int vlbm_restore(vlbm_sim sh, const void* buf, size_t size) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !buf) return fail(VLBM_ERR_ARG, "vlbm_restore: null argument");
+  if (size < sizeof(CkptHeader)) return fail(VLBM_ERR_ARG, "checkpoint too small");
+  CkptHeader h;
+  memcpy(&h, buf, sizeof(h));
+  if (h.magic != kMagic || h.lattice != s->mesh->lattice || h.precision != s->p.precision ||
+      h.ncells != s->mesh->box.ncells || h.Q != s->mesh->Q || h.bytes != (int64_t)s->pop_bytes ||
+      size != sizeof(h) + s->pop_bytes)
+    return fail(VLBM_ERR_ARG, "checkpoint does not match this simulation");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy(s->pop[s->buf], static_cast<const char*>(buf) + sizeof(h), s->pop_bytes,
+                    hipMemcpyHostToDevice));
+  s->t = h.t;
+  s->have_u_prev = 0;
+  return ok();
+}
+
+int vlbm_sim_step_count(vlbm_sim sh, int64_t* t) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !t) return fail(VLBM_ERR_ARG, "null argument");
+  *t = s->t;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations shared by the HIP translation units of libvlbm.
+// Not part of the public ABI (include/vlbm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vlbm.h"
+
+namespace vlbm {
+
+// ---------------------------------------------------------------------------
+// Lattices (Sec. 2.1, eq. (iso) and the D3Q19 set printed there; D2Q9 is its
+// planar analogue).  Rest first, then opposite pairs (2k-1, 2k).  All lookups
+// are constexpr so fully unrolled loops fold them into immediates.
+// ---------------------------------------------------------------------------
+struct D2Q9 {
+  static constexpr int Q = 9;
+  static constexpr int D = 2;
+  static constexpr int ID = VLBM_D2Q9;
+  __host__ __device__ static constexpr int c(int a, int i) {
+    constexpr int t[9][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                             {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+    return t[a][i];
+  }
+  __host__ __device__ static constexpr double w(int a) {
+    return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr int D = 3;
+  static constexpr int ID = VLBM_D3Q19;
+  __host__ __device__ static constexpr int c(int a, int i) {
+    constexpr int t[19][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},
+                              {0, 0, 1},   {0, 0, -1},  {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},
+                              {-1, 1, 0},  {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
+                              {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1}};
+    return t[a][i];
+  }
+  __host__ __device__ static constexpr double w(int a) {
+    return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+__host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+
+constexpr double T0 = 1.0 / 3.0;
+
+// Number of stored g^{ij} words (upper triangle) and its index map.
+template <int D> __host__ __device__ constexpr int nup() { return D * (D + 1) / 2; }
+template <int D> __host__ __device__ constexpr int up(int i, int j) {
+  // row-major upper triangle: D=2: 00,01,11; D=3: 00,01,02,11,12,22
+  return (i <= j) ? (i * D - i * (i - 1) / 2 + (j - i)) : (j * D - j * (j - 1) / 2 + (i - j));
+}
+
+// ---------------------------------------------------------------------------
+// Topology of the index box, passed by value to kernels.
+// ---------------------------------------------------------------------------
+struct Box {
+  int n[3];        // real cells per axis (n[2] = 1 in 2-D)
+  int face[3][2];  // VLBM_PERIODIC / VLBM_WALL / VLBM_FARFIELD
+  int ncells;
+};
+
+// Kind of the source of a pulled link.
+enum LinkKind { LINK_INTERIOR = 0, LINK_WALL = 1, LINK_FARFIELD = 2 };
+
+// Source of direction a arriving at cell (x, y, z): N_a(q) = N'_a(q - c_a)
+// (eq. (adv)).  Periodic axes wrap; a link that leaves through a far-field
+// face is FARFIELD, otherwise through a wall face is WALL.
+template <class L>
+__device__ __forceinline__ int link_source(const Box& b, int a, int x, int y, int z, int& src) {
+  int q[3] = {x, y, z};
+  int kind = LINK_INTERIOR;
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    const int ci = L::c(a, i);
+    if (ci == 0) continue;
+    int s = q[i] - ci;
+    if (s < 0) {
+      const int f = b.face[i][0];
+      if (f == VLBM_PERIODIC) s += b.n[i];
+      else kind = (f == VLBM_FARFIELD || kind == LINK_FARFIELD) ? LINK_FARFIELD : LINK_WALL;
+    } else if (s >= b.n[i]) {
+      const int f = b.face[i][1];
+      if (f == VLBM_PERIODIC) s -= b.n[i];
+      else kind = (f == VLBM_FARFIELD || kind == LINK_FARFIELD) ? LINK_FARFIELD : LINK_WALL;
+    }
+    q[i] = s;
+  }
+  src = q[0] + b.n[0] * (q[1] + b.n[1] * q[2]);
+  return kind;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side objects.
+// ---------------------------------------------------------------------------
+struct MeshObj {
+  int lattice;
+  int d, Q;
+  Box box;
+  int m[3];          // coordinate array extents (with ghosts on non-periodic axes)
+  double wrap[3][3];
+  double dx;
+  double* coords = nullptr;   // device [m3][m2][m1][d]
+  // FP64 geometry (device), valid after precompute
+  bool have_geometry = false;
+  double* J = nullptr;        // [cells]
+  double* gup = nullptr;      // [d*d][cells]
+  double* gco = nullptr;      // [d][d][cells]  g^i components
+  double* g = nullptr;        // [d][d][cells]  g_i components
+  double* A = nullptr;        // [Q][d][cells]
+  vlbm_geom_report report{};
+};
+
+// Geometry pack words for the step kernels (SoA, stride = ncells).
+template <class L> struct Pack {
+  static constexpr int J = 0;
+  static constexpr int GUP = 1;
+  static constexpr int A = GUP + nup<L::D>();                 // A^i_a for a >= 1
+  static constexpr int AEXT = A + (L::Q - 1) * L::D;          // present if force
+  static constexpr int UINF = AEXT + L::D;                    // present if far field
+  static constexpr int WORDS = UINF + L::D;
+};
+
+struct SimObj {
+  MeshObj* mesh;
+  vlbm_params p;
+  hipStream_t stream;
+  int64_t t = 0;
+  int buf = 0;            // index of the buffer that holds N'(t-1)
+  void* pop[2] = {nullptr, nullptr};
+  size_t pop_bytes = 0;
+  void* geo = nullptr;    // precision pack
+  int has_force = 0, has_farfield = 0;
+  // audits
+  void* audit_ring = nullptr;   // device vlbm_audit[cap]
+  int audit_cap = 0;
+  int64_t audit_head = 0, audit_tail = 0;
+  double* audit_partial = nullptr;  // device scratch for block partials
+  int audit_blocks = 0;
+  double* u_prev = nullptr;     // device [d][cells]
+  int have_u_prev = 0;
+  int* flags = nullptr;         // device int[4]: 0 = unconverged count, 1 = max iters
+};
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial);
+hipError_t launch_pack(SimObj* s);
+hipError_t launch_init(SimObj* s, const double* rho, const double* u, int* dflag);
+hipError_t launch_step(SimObj* s);
+hipError_t launch_moments(SimObj* s, double* rho, double* u, double* U, int* dflag);
+hipError_t launch_get_pop(SimObj* s, double* N);
+hipError_t launch_set_pop(SimObj* s, const double* N);
+hipError_t launch_audit(SimObj* s, int slot);
+
+int geometry_partial_blocks(const MeshObj* m);
+
+}  // namespace vlbm

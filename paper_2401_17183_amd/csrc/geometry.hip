@@ -1,0 +1,293 @@
+// FP64 geometry precompute on the device (Sec. 2.1): tangent vectors, volume,
+// co-tangent vectors, inverse metric, and the link coefficients A (Theta of
+// eq. (gamma) contracted with the link velocity), plus a diagnostics report.
+#include <math.h>
+
+#include "common.hpp"
+
+namespace vlbm {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct GeoArgs {
+  Box box;
+  int d;
+  int m[3];           // coordinate extents
+  int nb[3];          // box extents (n_i + 2 on axes < d, 1 otherwise)
+  int nbox;
+  double wrap[3][3];
+  double inv2dx;
+  const double* coords;
+  double* gbox;       // [d][d][nbox]
+  double* J;
+  double* gup;        // [d*d][cells]
+  double* gco;        // [d][d][cells]
+  double* g;          // [d][d][cells]
+  double* A;          // [Q][d][cells]
+  int* flag;
+  double* partial;    // [blocks][6]
+};
+
+// x(q) for q with one or two layers outside the real box: periodic axes wrap
+// the index and add the translation, non-periodic axes read ghost nodes.
+__device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
+  int idx[3] = {0, 0, 0};
+  double shift[3] = {0, 0, 0};
+  for (int i = 0; i < a.d; ++i) {
+    int qi = q[i];
+    if (a.box.face[i][0] == VLBM_PERIODIC) {
+      const int n = a.box.n[i];
+      int s = 0;
+      while (qi < 0) { qi += n; --s; }
+      while (qi >= n) { qi -= n; ++s; }
+      idx[i] = qi;
+      shift[i] = (double)s;
+    } else {
+      idx[i] = qi + 2;
+    }
+  }
+  const long off = ((long)idx[2] * a.m[1] + idx[1]) * a.m[0] + idx[0];
+  for (int k = 0; k < a.d; ++k) {
+    double v = a.coords[off * a.d + k];
+    for (int i = 0; i < a.d; ++i) v += shift[i] * a.wrap[i][k];
+    x[k] = v;
+  }
+}
+
+// Pass 1: one thread per box cell (real cells and the first ghost layer):
+// D_{+-i} (eq. (distance)), beta_i and g_i (eq. (tangent)), J (eq. (jacobian)),
+// g^i (eq. (covectors)), g^{ij} (eq. (inverse)).
+__global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= a.nbox) return;
+  const int d = a.d;
+  int bq[3] = {b % a.nb[0], (b / a.nb[0]) % a.nb[1], b / (a.nb[0] * a.nb[1])};
+  int q[3] = {0, 0, 0};
+  for (int i = 0; i < d; ++i) q[i] = bq[i] - 1;
+  double x0[3];
+  coord_at(a, q, x0);
+  double gv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int bad = 0;
+  for (int i = 0; i < d; ++i) {
+    int qp[3] = {q[0], q[1], q[2]};
+    int qm[3] = {q[0], q[1], q[2]};
+    qp[i] += 1;
+    qm[i] -= 1;
+    double xp[3], xm[3];
+    coord_at(a, qp, xp);
+    coord_at(a, qm, xm);
+    double Dp[3], Dm[3], df[3];
+    double np2 = 0, nm2 = 0, nd2 = 0;
+    for (int k = 0; k < d; ++k) {
+      Dp[k] = xp[k] - x0[k];
+      Dm[k] = xm[k] - x0[k];
+      df[k] = Dp[k] - Dm[k];
+      np2 += Dp[k] * Dp[k];
+      nm2 += Dm[k] * Dm[k];
+      nd2 += df[k] * df[k];
+    }
+    if (!(nd2 > 0.0)) {
+      bad |= 1;
+      nd2 = 1.0;
+    }
+    const double beta = (sqrt(np2) + sqrt(nm2)) / sqrt(nd2);
+    for (int k = 0; k < d; ++k) gv[i][k] = beta * df[k] * a.inv2dx;
+  }
+  double J;
+  double gc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (d == 2) {
+    J = gv[0][0] * gv[1][1] - gv[0][1] * gv[1][0];
+    gc[0][0] = gv[1][1] / J;
+    gc[0][1] = -gv[1][0] / J;
+    gc[1][0] = -gv[0][1] / J;
+    gc[1][1] = gv[0][0] / J;
+  } else {
+    double c12[3] = {gv[0][1] * gv[1][2] - gv[0][2] * gv[1][1], gv[0][2] * gv[1][0] - gv[0][0] * gv[1][2],
+                     gv[0][0] * gv[1][1] - gv[0][1] * gv[1][0]};
+    J = c12[0] * gv[2][0] + c12[1] * gv[2][1] + c12[2] * gv[2][2];
+    const double c23[3] = {gv[1][1] * gv[2][2] - gv[1][2] * gv[2][1], gv[1][2] * gv[2][0] - gv[1][0] * gv[2][2],
+                           gv[1][0] * gv[2][1] - gv[1][1] * gv[2][0]};
+    const double c31[3] = {gv[2][1] * gv[0][2] - gv[2][2] * gv[0][1], gv[2][2] * gv[0][0] - gv[2][0] * gv[0][2],
+                           gv[2][0] * gv[0][1] - gv[2][1] * gv[0][0]};
+    for (int k = 0; k < 3; ++k) {
+      gc[0][k] = c23[k] / J;
+      gc[1][k] = c31[k] / J;
+      gc[2][k] = c12[k] / J;
+    }
+  }
+  if (!(J > 0.0)) bad |= 2;
+  if (bad) atomicOr(a.flag, bad);
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) a.gbox[(long)(i * d + k) * a.nbox + b] = gv[i][k];
+  // real cell?
+  bool real = true;
+  for (int i = 0; i < d; ++i) real = real && q[i] >= 0 && q[i] < a.box.n[i];
+  if (!real) return;
+  const int cell = q[0] + a.box.n[0] * (q[1] + a.box.n[1] * q[2]);
+  const long nc = a.box.ncells;
+  a.J[cell] = J;
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) {
+      a.gco[(i * d + k) * nc + cell] = gc[i][k];
+      a.g[(i * d + k) * nc + cell] = gv[i][k];
+    }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double s = 0;
+      for (int k = 0; k < d; ++k) s += gc[i][k] * gc[j][k];
+      a.gup[(i * d + j) * nc + cell] = s;
+    }
+}
+
+__device__ inline void sym_eig_range(int d, const double* G /* d*d */, double& lo, double& hi) {
+  if (d == 2) {
+    const double m = 0.5 * (G[0] + G[3]);
+    const double h = 0.5 * (G[0] - G[3]);
+    const double r = sqrt(h * h + G[1] * G[1]);
+    lo = m - r;
+    hi = m + r;
+    return;
+  }
+  const double a00 = G[0], a11 = G[4], a22 = G[8], a01 = G[1], a02 = G[2], a12 = G[5];
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  const double p2 = (a00 - q) * (a00 - q) + (a11 - q) * (a11 - q) + (a22 - q) * (a22 - q) + 2.0 * p1;
+  if (p2 <= 0.0) {
+    lo = hi = q;
+    return;
+  }
+  const double p = sqrt(p2 / 6.0);
+  const double b00 = (a00 - q) / p, b11 = (a11 - q) / p, b22 = (a22 - q) / p;
+  const double b01 = a01 / p, b02 = a02 / p, b12 = a12 / p;
+  double r = 0.5 * (b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02));
+  r = fmin(1.0, fmax(-1.0, r));
+  const double phi = acos(r) / 3.0;
+  hi = q + 2.0 * p * cos(phi);
+  lo = q + 2.0 * p * cos(phi + 2.0943951023931957);
+}
+
+// Pass 2: one thread per real cell: A^i_a = [e_a(q + c_a) - e_a(q)] . g^i(q)
+// (eqs. (lattice), (gamma)) and the per-block diagnostics.
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_links(GeoArgs a) {
+  constexpr int D = L::D;
+  __shared__ double red[6][kBlock];
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  double vmin_J = INFINITY, vmax_J = -INFINITY, vmin_e = INFINITY, vmax_e = -INFINITY, vrest = INFINITY, vA = 0;
+  if (cell < a.box.ncells) {
+    const long nc = a.box.ncells;
+    const int x = cell % a.box.n[0];
+    const int y = (cell / a.box.n[0]) % a.box.n[1];
+    const int z = cell / (a.box.n[0] * a.box.n[1]);
+    int bq[3] = {x + 1, y + (D > 1 ? 1 : 0), z + (D > 2 ? 1 : 0)};
+    const int b0 = bq[0] + a.nb[0] * (bq[1] + a.nb[1] * bq[2]);
+    double gco[D][D], g0[D][D];
+    for (int i = 0; i < D; ++i)
+      for (int k = 0; k < D; ++k) {
+        gco[i][k] = a.gco[(i * D + k) * nc + cell];
+        g0[i][k] = a.gbox[(long)(i * D + k) * a.nbox + b0];
+      }
+    for (int i = 0; i < D; ++i) a.A[(0 * D + i) * nc + cell] = 0.0;
+#pragma unroll
+    for (int al = 1; al < L::Q; ++al) {
+      int bs[3] = {bq[0], bq[1], bq[2]};
+      for (int i = 0; i < D; ++i) bs[i] += L::c(al, i);
+      const int b1 = bs[0] + a.nb[0] * (bs[1] + a.nb[1] * bs[2]);
+      double de[D];
+      for (int k = 0; k < D; ++k) {
+        double s = 0;
+        for (int j = 0; j < D; ++j) {
+          const int cj = L::c(al, j);
+          if (cj == 0) continue;
+          s += cj * (a.gbox[(long)(j * D + k) * a.nbox + b1] - g0[j][k]);
+        }
+        de[k] = s;
+      }
+      for (int i = 0; i < D; ++i) {
+        double s = 0;
+        for (int k = 0; k < D; ++k) s += de[k] * gco[i][k];
+        a.A[(al * D + i) * nc + cell] = s;
+        vA = fmax(vA, fabs(s));
+      }
+    }
+    const double J = a.J[cell];
+    vmin_J = vmax_J = J;
+    double G[9];
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) G[i * D + j] = a.gup[(i * D + j) * nc + cell];
+    sym_eig_range(D, G, vmin_e, vmax_e);
+    double trg = 0;
+    for (int i = 0; i < D; ++i) trg += G[i * D + i];
+#pragma unroll
+    for (int al = 0; al < L::Q; ++al) {
+      double cgc = 0;
+      int cc = 0;
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) cgc += L::c(al, i) * L::c(al, j) * G[i * D + j];
+      for (int i = 0; i < D; ++i) cc += L::c(al, i) * L::c(al, i);
+      const double ratio = 1.0 + 0.5 * (3.0 * (cgc - cc) - (trg - D));
+      vrest = fmin(vrest, ratio);
+    }
+  }
+  red[0][threadIdx.x] = vmin_J;
+  red[1][threadIdx.x] = -vmax_J;
+  red[2][threadIdx.x] = vmin_e;
+  red[3][threadIdx.x] = -vmax_e;
+  red[4][threadIdx.x] = vrest;
+  red[5][threadIdx.x] = -vA;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) a.partial[blockIdx.x * 6 + k] = red[k][0];
+}
+
+}  // namespace
+
+int geometry_partial_blocks(const MeshObj* m) { return (m->box.ncells + kBlock - 1) / kBlock; }
+
+hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial) {
+  GeoArgs a;
+  a.box = m->box;
+  a.d = m->d;
+  a.nbox = 1;
+  for (int i = 0; i < 3; ++i) {
+    a.m[i] = m->m[i];
+    a.nb[i] = i < m->d ? m->box.n[i] + 2 : 1;
+    a.nbox *= a.nb[i];
+    for (int k = 0; k < 3; ++k) a.wrap[i][k] = m->wrap[i][k];
+  }
+  a.inv2dx = 1.0 / (2.0 * m->dx);
+  a.coords = m->coords;
+  a.J = m->J;
+  a.gup = m->gup;
+  a.gco = m->gco;
+  a.g = m->g;
+  a.A = m->A;
+  a.flag = dflag;
+  a.partial = partial;
+  hipError_t e = hipMalloc((void**)&a.gbox, sizeof(double) * m->d * m->d * (size_t)a.nbox);
+  if (e != hipSuccess) return e;
+  k_basis<<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    (void)hipFree(a.gbox);
+    return e;
+  }
+  if (m->lattice == VLBM_D2Q9)
+    k_links<D2Q9><<<nblocks_partial, kBlock, 0, s>>>(a);
+  else
+    k_links<D3Q19><<<nblocks_partial, kBlock, 0, s>>>(a);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    (void)hipFree(a.gbox);
+    return e;
+  }
+  e = hipStreamSynchronize(s);
+  (void)hipFree(a.gbox);
+  return e;
+}
+
+}  // namespace vlbm

@@ -1,0 +1,308 @@
+"""Thin ctypes binding of libvlbm.so (include/vlbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory and the current HIP stream.  The library is
+loaded from this package directory; if it is missing the import fails loudly
+(there is no CPU fallback).
+
+The module exposes the C functions under their C names (vlbm_mesh_create, ...),
+raising VlbmError on a non-zero status, and two small handle classes, Mesh and
+Sim, that own the C handles and the torch tensors passed across the boundary.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libvlbm.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is not built: run __graft_entry__.build() "
+                      "or python -m paper_2401_17183_amd.build")
+_lib = C.CDLL(LIBPATH)
+
+D2Q9, D3Q19 = 0, 1
+FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
+PERIODIC, WALL, FARFIELD = 0, 1, 2
+OK, ERR_ARG, ERR_MESH, ERR_NOMEM, ERR_DEVICE, ERR_NOCONVERGE, ERR_STATE, ERR_NONFINITE, ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S, "bf16s": BF16S}
+
+
+class VlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class vlbm_topology(C.Structure):
+    _fields_ = [("face", (C.c_int32 * 2) * 3), ("wrap", (C.c_double * 3) * 3)]
+
+
+class vlbm_geom_report(C.Structure):
+    _fields_ = [("min_J", C.c_double), ("max_J", C.c_double), ("min_gup_eig", C.c_double),
+                ("max_gup_eig", C.c_double), ("min_rest_feq_over_w", C.c_double), ("max_abs_A", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vlbm_params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("body_force", C.c_double * 3), ("rho_inf", C.c_double),
+                ("u_inf", C.c_double * 3), ("precision", C.c_int32), ("fp_max_iter", C.c_int32),
+                ("fp_tol", C.c_double), ("audit_every", C.c_int32), ("stream_only", C.c_int32)]
+
+
+class vlbm_audit(C.Structure):
+    _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("mom_I", C.c_double * 3),
+                ("wall_impulse", C.c_double * 3), ("force_impulse", C.c_double * 3), ("residual", C.c_double),
+                ("max_fp_iters", C.c_int32), ("nonfinite", C.c_int32), ("negative", C.c_int32),
+                ("unconverged", C.c_int32)]
+
+    def as_dict(self):
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = np.array(list(v)) if isinstance(v, C.Array) else v
+        return out
+
+
+_P = C.c_void_p
+_SIGS = {
+    "vlbm_last_error": (C.c_char_p, []),
+    "vlbm_lattice_info": (C.c_int, [C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double)]),
+    "vlbm_mesh_create": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                   C.POINTER(vlbm_topology), C.c_double, C.POINTER(_P)]),
+    "vlbm_mesh_destroy": (C.c_int, [_P]),
+    "vlbm_geometry_precompute": (C.c_int, [_P, _P, C.POINTER(vlbm_geom_report)]),
+    "vlbm_geometry_fields": (C.c_int, [_P, _P, _P, _P, _P]),
+    "vlbm_init": (C.c_int, [_P, C.POINTER(vlbm_params), _P, _P, _P, C.POINTER(_P)]),
+    "vlbm_step": (C.c_int, [_P, C.c_int64]),
+    "vlbm_moments": (C.c_int, [_P, _P, _P, _P]),
+    "vlbm_populations": (C.c_int, [_P, _P]),
+    "vlbm_set_populations": (C.c_int, [_P, _P]),
+    "vlbm_audit_now": (C.c_int, [_P]),
+    "vlbm_audits": (C.c_int, [_P, C.POINTER(vlbm_audit), C.c_int, C.POINTER(C.c_int)]),
+    "vlbm_save": (C.c_int, [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "vlbm_restore": (C.c_int, [_P, _P, C.c_size_t]),
+    "vlbm_sim_step_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "vlbm_sim_destroy": (C.c_int, [_P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def vlbm_last_error():
+    return _lib.vlbm_last_error().decode()
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise VlbmError(rc, vlbm_last_error())
+    return rc
+
+
+def _wrap(name):
+    f = getattr(_lib, name)
+
+    def call(*args, allow=()):
+        return _check(f(*args), allow)
+    call.__name__ = name
+    call.__doc__ = f"ctypes call of {name} (include/vlbm.h); raises VlbmError on failure"
+    return call
+
+
+for _name in _SIGS:
+    if _name != "vlbm_last_error":
+        globals()[_name] = _wrap(_name)
+
+
+def lattice_info(lattice):
+    Q, d = C.c_int32(), C.c_int32()
+    vlbm_lattice_info(lattice, C.byref(Q), C.byref(d), None, None)
+    c = (C.c_int32 * (Q.value * d.value))()
+    w = (C.c_double * Q.value)()
+    vlbm_lattice_info(lattice, C.byref(Q), C.byref(d), c, w)
+    return np.array(c[:]).reshape(Q.value, d.value), np.array(w[:])
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the library has no CPU path")
+    return torch
+
+
+def _stream_ptr(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(torch, a, shape=None):
+    """Contiguous float64 device tensor from a numpy array / tensor."""
+    t = torch.as_tensor(a, dtype=torch.float64)
+    if shape is not None:
+        t = t.reshape(shape)
+    return t.to("cuda").contiguous()
+
+
+class Mesh:
+    """A mesh handle: coordinates in, FP64 geometry precomputed on the device."""
+
+    def __init__(self, lattice, n, coords, faces, wrap, dx, precompute=True):
+        self.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+        self.d = 2 if self.lattice == D2Q9 else 3
+        self.Q = 9 if self.lattice == D2Q9 else 19
+        n = tuple(int(v) for v in n)
+        self.n = n
+        self.ncells = int(np.prod(n))
+        nn = (C.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+        topo = vlbm_topology()
+        for i in range(self.d):
+            for f in range(2):
+                topo.face[i][f] = int(faces[i][f])
+            for k in range(self.d):
+                topo.wrap[i][k] = float(wrap[i][k])
+        X = np.ascontiguousarray(coords, dtype=np.float64)
+        h = _P()
+        vlbm_mesh_create(self.lattice, nn, X.ctypes.data_as(C.POINTER(C.c_double)), C.byref(topo), float(dx),
+                         C.byref(h))
+        self.h = h
+        self.report = None
+        if precompute:
+            self.precompute()
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w["lattice"], w["n"], w["coords"], w["faces"], w["wrap"], w["dx"], **kw)
+
+    def precompute(self):
+        torch = _torch()
+        rep = vlbm_geom_report()
+        vlbm_geometry_precompute(self.h, _stream_ptr(torch), C.byref(rep))
+        self.report = rep.as_dict()
+        return self.report
+
+    def fields(self):
+        """FP64 geometry as torch tensors: J, gup (d,d), A (Q,d), g (d,d) per cell."""
+        torch = _torch()
+        nc, d, Q = self.ncells, self.d, self.Q
+        J = torch.empty(nc, dtype=torch.float64, device="cuda")
+        gup = torch.empty(d * d * nc, dtype=torch.float64, device="cuda")
+        A = torch.empty(Q * d * nc, dtype=torch.float64, device="cuda")
+        g = torch.empty(d * d * nc, dtype=torch.float64, device="cuda")
+        vlbm_geometry_fields(self.h, _P(J.data_ptr()), _P(gup.data_ptr()), _P(A.data_ptr()), _P(g.data_ptr()))
+        return {"J": J, "gup": gup.reshape(d, d, nc), "A": A.reshape(Q, d, nc), "g": g.reshape(d, d, nc)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            vlbm_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(tau, body_force=(0, 0, 0), rho_inf=1.0, u_inf=(0, 0, 0), precision=FP64, fp_max_iter=0,
+                fp_tol=-1.0, audit_every=0, stream_only=False):
+    p = vlbm_params()
+    p.tau = float(tau)
+    bf = list(body_force) + [0.0] * (3 - len(body_force))
+    ui = list(u_inf) + [0.0] * (3 - len(u_inf))
+    for k in range(3):
+        p.body_force[k] = float(bf[k])
+        p.u_inf[k] = float(ui[k])
+    p.rho_inf = float(rho_inf)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.fp_max_iter = int(fp_max_iter)
+    p.fp_tol = float(fp_tol)
+    p.audit_every = int(audit_every)
+    p.stream_only = int(bool(stream_only))
+    return p
+
+
+class Sim:
+    """A simulation handle on a Mesh (populations, packed geometry, audits)."""
+
+    def __init__(self, mesh, params, rho=None, u=None):
+        torch = _torch()
+        self.mesh = mesh
+        self.params = params
+        nc, d = mesh.ncells, mesh.d
+        r = _dev(torch, rho, (nc,)) if rho is not None else None
+        v = _dev(torch, u, (d, nc)) if u is not None else None
+        h = _P()
+        vlbm_init(mesh.h, C.byref(params), _P(r.data_ptr()) if r is not None else None,
+                  _P(v.data_ptr()) if v is not None else None, _stream_ptr(torch), C.byref(h))
+        self.h = h
+
+    def step(self, n=1):
+        vlbm_step(self.h, int(n))
+
+    @property
+    def t(self):
+        v = C.c_int64()
+        vlbm_sim_step_count(self.h, C.byref(v))
+        return v.value
+
+    def moments(self, with_U=False):
+        torch = _torch()
+        nc, d = self.mesh.ncells, self.mesh.d
+        rho = torch.empty(nc, dtype=torch.float64, device="cuda")
+        u = torch.empty(d * nc, dtype=torch.float64, device="cuda")
+        U = torch.empty(d * nc, dtype=torch.float64, device="cuda") if with_U else None
+        vlbm_moments(self.h, _P(rho.data_ptr()), _P(u.data_ptr()), _P(U.data_ptr()) if U is not None else None)
+        out = {"rho": rho, "u": u.reshape(d, nc)}
+        if U is not None:
+            out["U"] = U.reshape(d, nc)
+        return out
+
+    def populations(self):
+        torch = _torch()
+        Q, nc = self.mesh.Q, self.mesh.ncells
+        N = torch.empty(Q * nc, dtype=torch.float64, device="cuda")
+        vlbm_populations(self.h, _P(N.data_ptr()))
+        return N.reshape(Q, nc)
+
+    def set_populations(self, N):
+        torch = _torch()
+        t = _dev(torch, N, (self.mesh.Q * self.mesh.ncells,))
+        vlbm_set_populations(self.h, _P(t.data_ptr()))
+
+    def audit_now(self):
+        vlbm_audit_now(self.h)
+
+    def audits(self, cap=4096, allow_nonfinite=True):
+        buf = (vlbm_audit * cap)()
+        n = C.c_int()
+        vlbm_audits(self.h, buf, cap, C.byref(n), allow=(ERR_NONFINITE,) if allow_nonfinite else ())
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def save(self):
+        used = C.c_size_t()
+        vlbm_save(self.h, None, 0, C.byref(used))
+        buf = C.create_string_buffer(used.value)
+        vlbm_save(self.h, buf, used.value, C.byref(used))
+        return bytes(buf.raw[: used.value])
+
+    def restore(self, blob):
+        b = C.create_string_buffer(blob, len(blob))
+        vlbm_restore(self.h, b, len(blob))
+
+    def close(self):
+        if getattr(self, "h", None):
+            vlbm_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

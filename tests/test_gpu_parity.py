@@ -1,0 +1,233 @@
+"""GPU (HIP, through the C-ABI) versus the FP64 oracle, element by element.
+
+Every case prints its name before the GPU call so a failing run names it."""
+import numpy as np
+import pytest
+
+from paper_2401_17183_amd import workloads as W
+from tests.oracle_helpers import mesh_of, sim_of
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _vlbm():
+    from paper_2401_17183_amd import vlbm
+    return vlbm
+
+
+def announce(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def gpu_mesh(w):
+    return _vlbm().Mesh.from_workload(w)
+
+
+def gpu_sim(w, mesh=None, precision="fp64", rho=None, u=None, **kw):
+    v = _vlbm()
+    mesh = mesh or gpu_mesh(w)
+    p = v.make_params(w["tau"], body_force=w.get("body_force", (0, 0, 0)), rho_inf=w.get("rho_inf", 1.0),
+                      u_inf=w.get("u_inf", (0, 0, 0)), precision=precision, **kw)
+    return v.Sim(mesh, p, rho=rho, u=u), mesh
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+SMALL = [W.tanh_channel_2d(12, 10), W.wavy_channel_3d(9, 7, 5), W.ogrid_3d(8, 12, 4),
+         W.tanh_channel_3d(10, 8, 6), W.wavy_periodic("D2Q9", (11, 9), 0.2),
+         W.affine_mesh("D3Q19", (5, 6, 4), np.eye(3) + 0.2 * np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]]),
+                       periodic=False)]
+
+
+@pytest.mark.parametrize("w", SMALL, ids=lambda w: w["name"])
+def test_geometry_fp64_parity(w):
+    announce(f"geometry {w['name']}")
+    from oracle import geometry
+    m = gpu_mesh(w)
+    f = m.fields()
+    og = geometry.Geometry(mesh_of(w))
+    d, Q = og.mesh.d, og.lat.Q
+    def flat(a, lead):
+        return a.reshape(a.shape[:lead] + (-1,))
+    assert np.allclose(cpu(f["J"]), og.J.ravel(), rtol=1e-14, atol=0)
+    assert np.allclose(cpu(f["gup"]), flat(og.gup, 2), rtol=1e-13, atol=1e-14)
+    assert np.allclose(cpu(f["g"]), flat(og.g, 2), rtol=1e-14, atol=1e-15)
+    scale = max(np.abs(og.A).max(), 1e-300)
+    assert np.max(np.abs(cpu(f["A"]) - flat(og.A, 2))) <= 1e-13 * max(scale, 1.0)
+    rep = og.report()
+    for k, v in rep.items():
+        assert abs(m.report[k] - v) <= 1e-12 * max(1.0, abs(v)), (k, m.report[k], v)
+
+
+def test_degenerate_meshes_are_rejected():
+    v = _vlbm()
+    w = W.tanh_channel_2d(8, 6)
+    X = w["coords"].copy()
+    X[..., 0] *= -1.0   # mirrored: J < 0
+    announce("degenerate: mirrored mesh")
+    with pytest.raises(v.VlbmError) as e:
+        v.Mesh(w["lattice"], w["n"], X, w["faces"], w["wrap"], w["dx"])
+    assert e.value.code == v.ERR_MESH and "J <= 0" in str(e.value)
+    X = w["coords"].copy()
+    X[5, :, :] = X[4, :, :]   # two coincident node rows: D_+ = D_- = 0 somewhere
+    X[3, :, :] = X[4, :, :]
+    announce("degenerate: coincident nodes")
+    with pytest.raises(v.VlbmError) as e:
+        v.Mesh(w["lattice"], w["n"], X, w["faces"], w["wrap"], w["dx"])
+    assert e.value.code == v.ERR_MESH
+
+
+@pytest.mark.parametrize("w", SMALL[:4], ids=lambda w: w["name"])
+def test_initial_state_parity(w):
+    announce(f"init {w['name']}")
+    rng = np.random.default_rng(11)
+    os_ = sim_of(w)
+    shape = os_.mesh.shape
+    d = os_.mesh.d
+    rho = 1 + 0.01 * rng.standard_normal(shape)
+    u = 0.01 * rng.standard_normal((d,) + shape)
+    os_.init(rho, u)
+    s, m = gpu_sim(w, rho=rho.ravel(), u=u.reshape(d, -1))
+    N = cpu(s.populations())
+    J = os_.geom.J.ravel()
+    err = np.max(np.abs(N / J - os_.N.reshape(os_.lat.Q, -1) / J))
+    assert err < 1e-13, err
+
+
+@pytest.mark.parametrize("w", [W.wavy_periodic("D3Q19", (5, 4, 6), 0.1), W.tanh_channel_2d(8, 4),
+                               W.ogrid_3d(6, 8, 3)], ids=lambda w: w["name"])
+def test_stream_only_is_bit_exact(w):
+    """Advection alone: bit-identical to the oracle's permutation after several
+    steps; on the periodic mesh n steps return the state exactly."""
+    announce(f"stream-only {w['name']}")
+    os_ = sim_of(w, stream_only=True)
+    rng = np.random.default_rng(3)
+    N0 = rng.random((os_.lat.Q,) + os_.mesh.shape)
+    os_.set_state(N0)
+    s, m = gpu_sim(w, stream_only=True)
+    s.set_populations(N0.reshape(os_.lat.Q, -1))
+    assert np.array_equal(cpu(s.populations()), N0.reshape(os_.lat.Q, -1)) or w["faces"][0][1] == 2
+    k = 5
+    s.step(k)
+    os_.step(k)
+    assert np.array_equal(cpu(s.populations()), os_.N.reshape(os_.lat.Q, -1))
+
+
+@pytest.mark.parametrize("w,steps", [(W.tanh_channel_2d(64, 32), 100), (W.wavy_channel_3d(16, 12, 8), 100),
+                                     (W.ogrid_3d(12, 16, 4), 20)], ids=lambda x: str(x) if isinstance(x, int) else x["name"])
+def test_fp64_step_parity(w, steps):
+    """FP64 path: max |f_gpu - f_oracle| <= 1e-12 after `steps` steps (f = N/J)."""
+    announce(f"fp64 step parity {w['name']} x{steps}")
+    os_ = sim_of(w)
+    rho = w.get("rho")
+    u = w.get("u")
+    if w["lattice"] == "D2Q9" and "half_height" in w:
+        rho, u = W.poiseuille_fields(w)
+    os_.init(rho, u)
+    d = os_.mesh.d
+    s, m = gpu_sim(w, rho=None if rho is None else rho.ravel(), u=None if u is None else u.reshape(d, -1))
+    s.step(steps)
+    os_.step(steps)
+    J = os_.geom.J.ravel()
+    f_gpu = cpu(s.populations()) / J
+    f_orc = os_.N.reshape(os_.lat.Q, -1) / J
+    err = np.max(np.abs(f_gpu - f_orc))
+    assert err <= 1e-12, err
+    mo = s.moments()
+    om = os_.moments()
+    assert np.allclose(cpu(mo["rho"]), om["rho"].ravel(), rtol=0, atol=1e-12)
+    assert np.allclose(cpu(mo["u"]), om["u"].reshape(d, -1), rtol=0, atol=1e-12)
+
+
+def test_fp32_velocity_parity_short():
+    """FP32 storage and compute: velocity relative L2 error vs the FP64 oracle
+    <= 1e-5 on a small replica of the stretched channel (200 steps)."""
+    w = W.tanh_channel_3d(24, 16, 12)
+    announce("fp32 parity tanh channel 24x16x12 x200")
+    os_ = sim_of(w)
+    os_.init(w["rho"], w["u"])
+    s, m = gpu_sim(w, precision="fp32", rho=w["rho"].ravel(), u=w["u"].reshape(3, -1))
+    s.step(200)
+    os_.step(200)
+    u_g = cpu(s.moments()["u"])
+    u_o = os_.moments()["u"].reshape(3, -1)
+    rel = np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o)
+    print("fp32 rel L2", rel)
+    assert rel <= 1e-5, rel
+
+
+def test_audits_match_oracle_and_balance():
+    """Device audits: mass, mid-link momentum I and wall impulse equal the
+    oracle's; I(t+1) = I(t) + G*mass + W(t) every step."""
+    w = W.wavy_channel_3d(10, 8, 6)
+    announce("audits wavy channel")
+    os_ = sim_of(w)
+    os_.init(w["rho"], w["u"])
+    s, m = gpu_sim(w, rho=w["rho"].ravel(), u=w["u"].reshape(3, -1), audit_every=1)
+    s.audit_now()
+    s.step(4)
+    aud = s.audits()
+    assert len(aud) == 5
+    prev = None
+    for k, a in enumerate(aud):
+        if k > 0:
+            os_.step()
+        o = os_.audit()
+        assert a["step"] == k
+        assert abs(a["mass"] - o["mass"]) <= 1e-13 * o["mass"]
+        assert np.allclose(a["mom_I"][:3], o["mom_I"], rtol=0, atol=1e-12 * o["mass"])
+        assert np.allclose(a["wall_impulse"][:3], o["wall_impulse"], rtol=0, atol=1e-12 * o["mass"])
+        if prev is not None:
+            bal = a["mom_I"] - prev["mom_I"] - prev["force_impulse"] - a["wall_impulse"]
+            assert np.max(np.abs(bal)) <= 1e-12 * a["mass"], bal
+            assert abs(a["mass"] / prev["mass"] - 1) <= 1e-14
+            assert a["residual"] >= 0
+        else:
+            assert np.isnan(a["residual"])
+        assert a["nonfinite"] == 0 and a["unconverged"] == 0
+        prev = a
+
+
+def test_checkpoint_restore_is_bit_exact():
+    w = W.wavy_channel_3d(9, 7, 5)
+    announce("checkpoint/restore")
+    s, m = gpu_sim(w, precision="fp32", rho=w["rho"].ravel(), u=w["u"].reshape(3, -1))
+    s.step(7)
+    blob = s.save()
+    s.step(6)
+    ref = cpu(s.populations())
+    s2, _ = gpu_sim(w, mesh=m, precision="fp32")
+    s2.restore(blob)
+    assert s2.t == 7
+    s2.step(6)
+    assert np.array_equal(cpu(s2.populations()), ref)
+
+
+def test_error_paths():
+    v = _vlbm()
+    w = W.tanh_channel_2d(8, 6)
+    m = gpu_mesh(w)
+    announce("error paths")
+    with pytest.raises(v.VlbmError) as e:
+        v.Sim(m, v.make_params(0.5))
+    assert e.value.code == v.ERR_ARG
+    with pytest.raises(v.VlbmError) as e:
+        v.Sim(m, v.make_params(0.8, precision=99))
+    assert e.value.code == v.ERR_UNSUPPORTED
+    # forced non-convergence: one iteration with zero tolerance
+    with pytest.raises(v.VlbmError) as e:
+        v.Sim(m, v.make_params(0.8, fp_max_iter=1, fp_tol=0.0))
+    assert e.value.code == v.ERR_NOCONVERGE
+    # a NaN written from the host is flagged by the audit
+    s = v.Sim(m, v.make_params(0.8))
+    N = s.populations()
+    N[3, 5] = float("nan")
+    s.set_populations(N)
+    s.audit_now()
+    with pytest.raises(v.VlbmError) as e:
+        v.vlbm_audits(s.h, (v.vlbm_audit * 4)(), 4, v.C.byref(v.C.c_int()))
+    assert e.value.code == v.ERR_NONFINITE
