@@ -36,10 +36,14 @@ extern "C" {
 
 enum { VLBM_D2Q9 = 0, VLBM_D3Q19 = 1 };
 
-/* Storage / compute precision of a simulation.  FP64 and FP32 store and compute
- * in that type; FP16S and BF16S store scaled deviations from the per-cell rest
- * equilibrium in 16 bits and compute in FP32. */
-enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP16S = 2, VLBM_BF16S = 3 };
+/* Storage / arithmetic precision of a simulation:
+ *  FP64   populations and geometry stored in FP64, FP64 arithmetic;
+ *  FP32   populations and geometry stored in FP32, FP64 arithmetic in registers
+ *         (FP32 arithmetic loses the small velocity signal to cancellation);
+ *  FP32C  FP32 storage and FP32 arithmetic (faster, less accurate);
+ *  FP16S / BF16S  scaled deviations from the per-cell rest equilibrium stored
+ *         in 16 bits. */
+enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP16S = 2, VLBM_BF16S = 3, VLBM_FP32C = 4 };
 
 enum { VLBM_PERIODIC = 0, VLBM_WALL = 1, VLBM_FARFIELD = 2 };
 
@@ -117,7 +121,8 @@ typedef struct {
   double u_inf[3];       /* far-field Euclidean velocity                               */
   int32_t precision;     /* VLBM_FP64 / VLBM_FP32 / VLBM_FP16S / VLBM_BF16S            */
   int32_t fp_max_iter;   /* cap of the per-cell collision fixed point (<= 0: 50)       */
-  double fp_tol;         /* stop when max_i |F_k - F_(k-1)| <= fp_tol * rho (< 0: default) */
+  double fp_tol;         /* stop when max_i |F_k - F_(k-1)| <= fp_tol * rho (< 0: default:
+                            1e-14 FP64, 1e-10 FP32, 1e-7 FP32C)                         */
   int32_t audit_every;   /* enqueue an audit every k steps (0 = never)                 */
   int32_t stream_only;   /* 1: advection only, no collision (a permutation test mode)  */
 } vlbm_params;

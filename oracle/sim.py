@@ -79,7 +79,9 @@ class Sim:
         return self.N
 
     def set_state(self, N):
-        self.N = np.array(N, dtype=np.float64, copy=True)
+        """Replace the arrived populations; far-field links keep their imposed
+        value (they carry no information from inside the mesh)."""
+        self.N = self._impose_farfield(np.array(N, dtype=np.float64, copy=True))
 
     def step(self, n=1):
         info = None

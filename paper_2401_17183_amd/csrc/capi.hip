@@ -234,9 +234,7 @@ int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double
   return ok();
 }
 
-int vlbm_sim_destroy(vlbm_sim sh) {
-  SimObj* s = reinterpret_cast<SimObj*>(sh);
-  if (!s) return ok();
+static void free_sim(SimObj* s) {
   dev_free(s->pop[0]);
   dev_free(s->pop[1]);
   dev_free(s->geo);
@@ -245,6 +243,11 @@ int vlbm_sim_destroy(vlbm_sim sh) {
   dev_free(s->u_prev);
   dev_free(s->flags);
   delete s;
+}
+
+int vlbm_sim_destroy(vlbm_sim sh) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (s) free_sim(s);
   return ok();
 }
 
@@ -254,7 +257,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   *out = nullptr;
   if (!m->have_geometry) return fail(VLBM_ERR_STATE, "vlbm_init before vlbm_geometry_precompute");
   if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(VLBM_ERR_ARG, "tau must exceed 1/2 (got %g)", p->tau);
-  if (p->precision != VLBM_FP64 && p->precision != VLBM_FP32)
+  if (p->precision != VLBM_FP64 && p->precision != VLBM_FP32 && p->precision != VLBM_FP32C)
     return fail(VLBM_ERR_UNSUPPORTED, "precision %d is not built", p->precision);
   if (p->audit_every < 0) return fail(VLBM_ERR_ARG, "audit_every must be >= 0");
   SimObj* s = new (std::nothrow) SimObj();
@@ -262,7 +265,8 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   s->mesh = m;
   s->p = *p;
   if (s->p.fp_max_iter <= 0) s->p.fp_max_iter = 50;
-  if (s->p.fp_tol < 0) s->p.fp_tol = s->p.precision == VLBM_FP64 ? 1e-14 : 1e-7;
+  if (s->p.fp_tol < 0)
+    s->p.fp_tol = s->p.precision == VLBM_FP64 ? 1e-14 : (s->p.precision == VLBM_FP32 ? 1e-10 : 1e-7);
   s->stream = static_cast<hipStream_t>(stream);
   const int d = m->d;
   for (int k = 0; k < d; ++k)
@@ -275,7 +279,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   s->pop_bytes = nc * m->Q * sb;
   int rc;
   auto bail = [&](int code) {
-    vlbm_sim_destroy(reinterpret_cast<vlbm_sim>(s));
+    free_sim(s);
     return code;
   };
   if ((rc = dev_alloc(&s->pop[0], s->pop_bytes))) return bail(rc);

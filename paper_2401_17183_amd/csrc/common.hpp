@@ -146,6 +146,8 @@ struct SimObj {
   int* flags = nullptr;         // device int[4]: 0 = unconverged count, 1 = max iters
 };
 
+inline bool storage_is_fp64(int precision) { return precision == VLBM_FP64; }
+
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial);
 hipError_t launch_pack(SimObj* s);

@@ -330,7 +330,7 @@ StateArgs<S> make_args(SimObj* s) {
   a.rho_inf = s->p.rho_inf;
   a.tau = s->p.tau;
   // the FP64 dry run converges to FP64 roundoff whatever the storage precision
-  a.tol = s->p.precision == VLBM_FP64 ? s->p.fp_tol : 1e-13;
+  a.tol = fmin(s->p.fp_tol, 1e-13);
   a.max_iter = s->p.fp_max_iter;
   a.in = static_cast<const S*>(s->pop[s->buf]);
   a.out = static_cast<S*>(s->pop[s->buf]);
@@ -348,7 +348,6 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
     case 0:
       a.rho_in = r_in;
       a.u_in = u_in;
-      a.tol = s->p.precision == VLBM_FP64 ? s->p.fp_tol : 1e-13;
       k_init<L, S><<<nb, kBlock, 0, st>>>(a);
       break;
     case 1:
@@ -385,7 +384,7 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
 hipError_t dispatch_any(SimObj* s, int what, const double* r_in, const double* u_in, double* r_out, double* u_out,
                         double* U_out, double* N_out, const double* N_in, int slot) {
   const bool d2 = s->mesh->lattice == VLBM_D2Q9;
-  if (s->p.precision == VLBM_FP64)
+  if (storage_is_fp64(s->p.precision))
     return d2 ? dispatch<D2Q9, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
               : dispatch<D3Q19, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
   return d2 ? dispatch<D2Q9, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)

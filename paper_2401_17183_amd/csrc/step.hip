@@ -8,11 +8,12 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <class T> struct StepArgs {
+// S: storage type of populations and packed geometry; T: arithmetic type.
+template <class S, class T> struct StepArgs {
   Box box;
-  const T* __restrict__ in;
-  T* __restrict__ out;
-  const T* __restrict__ geo;
+  const S* __restrict__ in;
+  S* __restrict__ out;
+  const S* __restrict__ geo;
   T tau, tol, rho_inf;
   int max_iter;
   int stream_only;
@@ -20,25 +21,25 @@ template <class T> struct StepArgs {
   int* flags;
 };
 
-template <class L, class T>
-__device__ __forceinline__ CellGeo<L, T> load_pack(const T* __restrict__ geo, int nc, int cell, int has_force) {
+template <class L, class S, class T>
+__device__ __forceinline__ CellGeo<L, T> load_pack(const S* __restrict__ geo, int nc, int cell, int has_force) {
   CellGeo<L, T> g;
-  g.J = geo[(long)Pack<L>::J * nc + cell];
+  g.J = T(geo[(long)Pack<L>::J * nc + cell]);
 #pragma unroll
-  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = geo[(long)(Pack<L>::GUP + k) * nc + cell];
+  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = T(geo[(long)(Pack<L>::GUP + k) * nc + cell]);
 #pragma unroll
   for (int i = 0; i < L::D; ++i) g.A[0][i] = T(0);
 #pragma unroll
   for (int a = 1; a < L::Q; ++a)
 #pragma unroll
-    for (int i = 0; i < L::D; ++i) g.A[a][i] = geo[(long)(Pack<L>::A + (a - 1) * L::D + i) * nc + cell];
+    for (int i = 0; i < L::D; ++i) g.A[a][i] = T(geo[(long)(Pack<L>::A + (a - 1) * L::D + i) * nc + cell]);
 #pragma unroll
-  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? geo[(long)(Pack<L>::AEXT + i) * nc + cell] : T(0);
+  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? T(geo[(long)(Pack<L>::AEXT + i) * nc + cell]) : T(0);
   return g;
 }
 
-template <class L, class T>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
+template <class L, class S, class T>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs<S, T> a) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   const int cell = blockIdx.x * kBlock + threadIdx.x;
@@ -55,18 +56,18 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
   for (int al = 0; al < Q; ++al) {
     int src;
     const int kind = link_source<L>(a.box, al, x, y, z, src);
-    if (kind == LINK_INTERIOR) N[al] = a.in[(long)al * nc + src];
-    else if (kind == LINK_WALL) N[al] = a.in[(long)opp(al) * nc + cell];
+    if (kind == LINK_INTERIOR) N[al] = T(a.in[(long)al * nc + src]);
+    else if (kind == LINK_WALL) N[al] = T(a.in[(long)opp(al) * nc + cell]);
     else {
       N[al] = T(0);
       ff |= 1u << al;
     }
   }
-  const CellGeo<L, T> g = load_pack<L, T>(a.geo, nc, cell, a.has_force);
+  const CellGeo<L, T> g = load_pack<L, S, T>(a.geo, nc, cell, a.has_force);
   if (ff) {
     T Uinf[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) Uinf[i] = a.geo[(long)(Pack<L>::UINF + i) * nc + cell];
+    for (int i = 0; i < D; ++i) Uinf[i] = T(a.geo[(long)(Pack<L>::UINF + i) * nc + cell]);
     T fe[Q];
     feq_farfield<L, T>(g, a.rho_inf, Uinf, fe);
 #pragma unroll
@@ -75,14 +76,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<T> a) {
   }
   if (a.stream_only) {
 #pragma unroll
-    for (int al = 0; al < Q; ++al) a.out[(long)al * nc + cell] = N[al];
+    for (int al = 0; al < Q; ++al) a.out[(long)al * nc + cell] = S(N[al]);
     return;
   }
   T Np[Q], F[D], Ut[D], U[D], rho;
   const CollideOut o = collide<L, T>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
   if (o.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
 #pragma unroll
-  for (int al = 0; al < Q; ++al) a.out[(long)al * nc + cell] = Np[al];
+  for (int al = 0; al < Q; ++al) a.out[(long)al * nc + cell] = S(Np[al]);
 }
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
@@ -113,13 +114,13 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
   }
 }
 
-template <class L, class T>
+template <class L, class S, class T>
 hipError_t step_typed(SimObj* s) {
-  StepArgs<T> a;
+  StepArgs<S, T> a;
   a.box = s->mesh->box;
-  a.in = static_cast<const T*>(s->pop[s->buf]);
-  a.out = static_cast<T*>(s->pop[s->buf ^ 1]);
-  a.geo = static_cast<const T*>(s->geo);
+  a.in = static_cast<const S*>(s->pop[s->buf]);
+  a.out = static_cast<S*>(s->pop[s->buf ^ 1]);
+  a.geo = static_cast<const S*>(s->geo);
   a.tau = T(s->p.tau);
   a.tol = T(s->p.fp_tol);
   a.rho_inf = T(s->p.rho_inf);
@@ -129,7 +130,7 @@ hipError_t step_typed(SimObj* s) {
   a.has_ff = s->has_farfield;
   a.flags = s->flags;
   const int nb = (a.box.ncells + kBlock - 1) / kBlock;
-  k_step<L, T><<<nb, kBlock, 0, s->stream>>>(a);
+  k_step<L, S, T><<<nb, kBlock, 0, s->stream>>>(a);
   return hipGetLastError();
 }
 
@@ -148,13 +149,19 @@ hipError_t pack_typed(SimObj* s) {
 
 hipError_t launch_step(SimObj* s) {
   const bool d2 = s->mesh->lattice == VLBM_D2Q9;
-  if (s->p.precision == VLBM_FP64) return d2 ? step_typed<D2Q9, double>(s) : step_typed<D3Q19, double>(s);
-  return d2 ? step_typed<D2Q9, float>(s) : step_typed<D3Q19, float>(s);
+  switch (s->p.precision) {
+    case VLBM_FP64:
+      return d2 ? step_typed<D2Q9, double, double>(s) : step_typed<D3Q19, double, double>(s);
+    case VLBM_FP32:
+      return d2 ? step_typed<D2Q9, float, double>(s) : step_typed<D3Q19, float, double>(s);
+    default:
+      return d2 ? step_typed<D2Q9, float, float>(s) : step_typed<D3Q19, float, float>(s);
+  }
 }
 
 hipError_t launch_pack(SimObj* s) {
   const bool d2 = s->mesh->lattice == VLBM_D2Q9;
-  if (s->p.precision == VLBM_FP64) return d2 ? pack_typed<D2Q9, double>(s) : pack_typed<D3Q19, double>(s);
+  if (storage_is_fp64(s->p.precision)) return d2 ? pack_typed<D2Q9, double>(s) : pack_typed<D3Q19, double>(s);
   return d2 ? pack_typed<D2Q9, float>(s) : pack_typed<D3Q19, float>(s);
 }
 

@@ -23,12 +23,12 @@ if not os.path.exists(LIBPATH):
 _lib = C.CDLL(LIBPATH)
 
 D2Q9, D3Q19 = 0, 1
-FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
+FP64, FP32, FP16S, BF16S, FP32C = 0, 1, 2, 3, 4
 PERIODIC, WALL, FARFIELD = 0, 1, 2
 OK, ERR_ARG, ERR_MESH, ERR_NOMEM, ERR_DEVICE, ERR_NOCONVERGE, ERR_STATE, ERR_NONFINITE, ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S, "bf16s": BF16S}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S, "bf16s": BF16S, "fp32c": FP32C}
 
 
 class VlbmError(RuntimeError):

@@ -91,13 +91,13 @@ def tanh_channel_3d(n1=256, n2=128, n3=128, strength=2.5, tau=0.52, G=1e-6,
     }
 
 
-def ogrid_3d(nr=256, nth=512, nz=64, rmax=20.0, u_inf=0.05, Re=100.0):
+def ogrid_3d(nr=256, nth=512, nz=64, rmax=20.0, u_inf=0.05, Re=100.0, dx_factor=1.0):
     """O-grid around a unit cylinder: r = rmax^(k/(nr-1)) (log spaced), theta
     periodic, z periodic with spacing dx; wall at r = 1, far field at r = rmax.
-    dx = radial spacing at r = 1; nu from Re = u_inf * (2 / dx) / nu."""
+    dx = dx_factor * (radial spacing at r = 1); nu from Re = u_inf * (2 / dx) / nu."""
     k = np.arange(-NGHOST, nr + NGHOST)
     r = rmax ** (k / (nr - 1.0))
-    dx = float(r[NGHOST + 1] - r[NGHOST])
+    dx = dx_factor * float(r[NGHOST + 1] - r[NGHOST])
     th = 2.0 * np.pi * np.arange(nth) / nth
     z = np.arange(nz) * dx
     X = np.empty((nz, nth, len(r), 3))
@@ -232,12 +232,14 @@ def wavy_periodic(lattice, n, amp=0.15, seed=SEED, dx=1.0):
             "tau": 0.8, "body_force": tuple([0.0] * d)}
 
 
-def wavy_channel_3d(n1=16, n2=12, n3=8, amp=0.1, strength=1.5, tau=0.7, G=1e-5, seed=SEED):
+def wavy_channel_3d(n1=16, n2=12, n3=8, amp=0.1, strength=1.0, tau=0.7, G=1e-5, seed=SEED):
     """Small 3-D curvilinear channel: tanh wall-normal clustering plus a smooth
-    wall-parallel waviness; periodic x, z; walls on y.  Exercises every A^i_a."""
+    wall-parallel waviness of every node coordinate; periodic x, z; walls on y.
+    dx = 1.1 * smallest central wall-normal spacing keeps the rest equilibrium
+    positive.  Exercises every A^i_a."""
     eta = _cell_eta(n2)
     yb = np.tanh(strength * eta) / np.tanh(strength)
-    dx = np.sqrt(3.0) * _central_min(yb) * 1.2
+    dx = 1.1 * _central_min(yb)
     rng = np.random.default_rng(seed)
     ph = rng.uniform(0, 2 * np.pi, size=4)
     i = np.arange(n1, dtype=np.float64)[None, None, :]
