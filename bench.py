@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--workload", default="channel")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="after timing, run one plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: --gpus must be 1 (the multi-GPU slab "
@@ -109,7 +111,7 @@ def main():
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
     mlups = cells * args.steps / (ms / 1e3) / 1e6
-    sb = {"fp64": 8, "fp32": 4, "fp16s": 2, "bf16s": 2}[args.precision]
+    sb = {"fp64": 8, "fp32": 4, "fp32c": 4, "fp16s": 2, "bf16s": 2}[args.precision]
     has_force = any(v != 0 for v in w.get("body_force", (0, 0, 0)))
     bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, sb, has_force)
     achieved = bpc * cells / (ms_per_step / 1e3) / 1e9
@@ -119,14 +121,25 @@ def main():
         "metric": "MLUPS + % HBM roofline (D3Q19 FP32); warm vs cold time-to-1e-6 residual",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "fp16s": "f16", "bf16s": "bf16"}[args.precision],
+        # the arithmetic type: the fp32 storage mode computes in FP64 registers
+        "vs_baseline": None, "dtype": {"fp32": "f64", "fp32c": "f32", "fp64": "f64", "fp16s": "f32",
+                                       "bf16s": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w["name"] + f" {args.precision.upper()}", "cells": cells, "lattice": w["lattice"],
-                   "tau": w["tau"], "wall_s": round(wall, 3), "finite": finite},
+                   "tau": w["tau"], "storage": {"fp32": "f32", "fp32c": "f32", "fp64": "f64", "fp16s": "f16",
+                                                "bf16s": "bf16"}[args.precision],
+                   "wall_s": round(wall, 3), "finite": finite},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_cell": bpc, "kernel": "k_step"},
     }
+    if args.copy_ref:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["config"]["copy_ref_bytes"] = 2 * src.numel() * 4
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -238,6 +238,7 @@ static void free_sim(SimObj* s) {
   dev_free(s->pop[0]);
   dev_free(s->pop[1]);
   dev_free(s->geo);
+  dev_free(s->fcache);
   dev_free(s->audit_ring);
   dev_free(s->audit_partial);
   dev_free(s->u_prev);
@@ -286,6 +287,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   if ((rc = dev_alloc(&s->pop[1], s->pop_bytes))) return bail(rc);
   const int words = m->lattice == VLBM_D2Q9 ? Pack<D2Q9>::WORDS : Pack<D3Q19>::WORDS;
   if ((rc = dev_alloc(&s->geo, nc * words * sb))) return bail(rc);
+  if ((rc = dev_alloc(&s->fcache, nc * d * fcache_elem(s->p.precision)))) return bail(rc);
   s->audit_cap = 4096;
   if ((rc = dev_alloc(&s->audit_ring, sizeof(vlbm_audit) * s->audit_cap))) return bail(rc);
   s->audit_blocks = audit_partial_blocks(m);
@@ -295,6 +297,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   hipError_t e = hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->fcache, 0, nc * d * fcache_elem(s->p.precision), s->stream);
   if (e == hipSuccess) e = launch_pack(s);
   if (e == hipSuccess) e = launch_init(s, rho, u, s->flags);
   int hflag = 0;
@@ -365,6 +368,8 @@ int vlbm_set_populations(vlbm_sim sh, const double* N) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s || !N) return fail(VLBM_ERR_ARG, "vlbm_set_populations: null argument");
   HIP_TRY(launch_set_pop(s, N));
+  HIP_TRY(hipMemsetAsync(s->fcache, 0, (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision),
+                         s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return ok();
 }
@@ -392,7 +397,8 @@ int vlbm_audits(vlbm_sim sh, vlbm_audit* out, int cap, int* n_out) {
 int vlbm_save(vlbm_sim sh, void* buf, size_t cap, size_t* used) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s || !used) return fail(VLBM_ERR_ARG, "vlbm_save: null argument");
-  const size_t need = sizeof(CkptHeader) + s->pop_bytes;
+  const size_t fbytes = (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision);
+  const size_t need = sizeof(CkptHeader) + s->pop_bytes + fbytes;
   *used = need;
   if (!buf) return ok();
   if (cap < need) return fail(VLBM_ERR_ARG, "buffer too small: need %zu bytes", need);
@@ -401,6 +407,7 @@ int vlbm_save(vlbm_sim sh, void* buf, size_t cap, size_t* used) {
   memcpy(buf, &h, sizeof(h));
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemcpy(static_cast<char*>(buf) + sizeof(h), s->pop[s->buf], s->pop_bytes, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(static_cast<char*>(buf) + sizeof(h) + s->pop_bytes, s->fcache, fbytes, hipMemcpyDeviceToHost));
   return ok();
 }
 
@@ -408,14 +415,17 @@ int vlbm_restore(vlbm_sim sh, const void* buf, size_t size) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s || !buf) return fail(VLBM_ERR_ARG, "vlbm_restore: null argument");
   if (size < sizeof(CkptHeader)) return fail(VLBM_ERR_ARG, "checkpoint too small");
+  const size_t fbytes = (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision);
   CkptHeader h;
   memcpy(&h, buf, sizeof(h));
   if (h.magic != kMagic || h.lattice != s->mesh->lattice || h.precision != s->p.precision ||
       h.ncells != s->mesh->box.ncells || h.Q != s->mesh->Q || h.bytes != (int64_t)s->pop_bytes ||
-      size != sizeof(h) + s->pop_bytes)
+      size != sizeof(h) + s->pop_bytes + fbytes)
     return fail(VLBM_ERR_ARG, "checkpoint does not match this simulation");
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemcpy(s->pop[s->buf], static_cast<const char*>(buf) + sizeof(h), s->pop_bytes,
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->fcache, static_cast<const char*>(buf) + sizeof(h) + s->pop_bytes, fbytes,
                     hipMemcpyHostToDevice));
   s->t = h.t;
   s->have_u_prev = 0;

@@ -69,29 +69,30 @@ enum LinkKind { LINK_INTERIOR = 0, LINK_WALL = 1, LINK_FARFIELD = 2 };
 
 // Source of direction a arriving at cell (x, y, z): N_a(q) = N'_a(q - c_a)
 // (eq. (adv)).  Periodic axes wrap; a link that leaves through a far-field
-// face is FARFIELD, otherwise through a wall face is WALL.
+// face is FARFIELD, otherwise through a wall face is WALL.  Written with
+// selects only, so that a wavefront never diverges on it.
 template <class L>
 __device__ __forceinline__ int link_source(const Box& b, int a, int x, int y, int z, int& src) {
   int q[3] = {x, y, z};
-  int kind = LINK_INTERIOR;
+  int wall = 0, far = 0;
 #pragma unroll
   for (int i = 0; i < L::D; ++i) {
     const int ci = L::c(a, i);
-    if (ci == 0) continue;
-    int s = q[i] - ci;
-    if (s < 0) {
-      const int f = b.face[i][0];
-      if (f == VLBM_PERIODIC) s += b.n[i];
-      else kind = (f == VLBM_FARFIELD || kind == LINK_FARFIELD) ? LINK_FARFIELD : LINK_WALL;
-    } else if (s >= b.n[i]) {
-      const int f = b.face[i][1];
-      if (f == VLBM_PERIODIC) s -= b.n[i];
-      else kind = (f == VLBM_FARFIELD || kind == LINK_FARFIELD) ? LINK_FARFIELD : LINK_WALL;
-    }
-    q[i] = s;
+    if (ci == 0) continue;                    // compile-time
+    const int s = q[i] - ci;
+    const int n = b.n[i];
+    const int side = ci > 0 ? 0 : 1;          // compile-time: leaving through the low (0) or high (1) face
+    const int out = ci > 0 ? (s < 0) : (s >= n);
+    const int f = b.face[i][side];
+    const int per = f == VLBM_PERIODIC;
+    q[i] = out ? (per ? (ci > 0 ? s + n : s - n) : q[i]) : s;
+    wall |= out & (f == VLBM_WALL);
+    far |= out & (f == VLBM_FARFIELD);
   }
   src = q[0] + b.n[0] * (q[1] + b.n[1] * q[2]);
-  return kind;
+  // non-periodic exits keep the own cell as source (the bounce-back slot)
+  src = (wall | far) ? x + b.n[0] * (y + b.n[1] * z) : src;
+  return far ? LINK_FARFIELD : (wall ? LINK_WALL : LINK_INTERIOR);
 }
 
 // ---------------------------------------------------------------------------
@@ -134,6 +135,8 @@ struct SimObj {
   void* pop[2] = {nullptr, nullptr};
   size_t pop_bytes = 0;
   void* geo = nullptr;    // precision pack
+  void* fcache = nullptr;   // [d][cells]: converged inertial force of the last step (fixed-point start),
+                            // in the arithmetic type (FP64 except for FP32C)
   int has_force = 0, has_farfield = 0;
   // audits
   void* audit_ring = nullptr;   // device vlbm_audit[cap]
@@ -147,6 +150,7 @@ struct SimObj {
 };
 
 inline bool storage_is_fp64(int precision) { return precision == VLBM_FP64; }
+inline size_t fcache_elem(int precision) { return precision == VLBM_FP32C ? 4 : 8; }
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial);

@@ -1,23 +1,63 @@
 // Per-cell dynamics of the volumetric curvilinear LBM (Sec. 2.2), templated on
-// the lattice L and the arithmetic type T.  Everything here runs in registers
-// of one thread; the kernels around it do the data movement.
+// the lattice L, the arithmetic type T and the register type AT of the link
+// coefficients A (FP32 registers halve their footprint when T is FP64; every
+// use converts to T).  Everything here runs in registers of one thread; the
+// kernels around it do the data movement.
 #pragma once
 
 #include "common.hpp"
 
 namespace vlbm {
 
-// Per-cell geometry as the collision needs it.
-template <class L, class T> struct CellGeo {
-  T J;
-  T gup[nup<L::D>()];     // g^{ij}, upper triangle
-  T A[L::Q][L::D];        // A^i_a (A[0] = 0)
-  T aext[L::D];           // a_ext^i = G . g^i
+// Per-cell geometry as the collision needs it, held in registers of type AT
+// (the storage type) and converted to the arithmetic type T at each use.  The
+// link coefficients A live either in registers (STRIDE = 0) or in LDS, word
+// (a - 1) * D + i at lds[word * STRIDE] (STRIDE = threads per block).
+template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
+  AT J;
+  AT gup[nup<L::D>()];     // g^{ij}, upper triangle
+  AT aext[L::D];           // a_ext^i = G . g^i
+  AT Areg[STRIDE ? 1 : L::Q][L::D];
+  const AT* lds;
+  __device__ __forceinline__ T j() const { return T(J); }
+  __device__ __forceinline__ T ae(int i) const { return T(aext[i]); }
+  __device__ __forceinline__ AT a(int al, int i) const {
+    if constexpr (STRIDE == 0) return Areg[al][i];
+    else return al == 0 ? AT(0) : lds[((al - 1) * L::D + i) * STRIDE];
+  }
 };
 
-template <class L, class T>
-__device__ __forceinline__ T gval(const CellGeo<L, T>& g, int i, int j) {
-  return g.gup[up<L::D>(i, j)];
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ T gval(const CellGeo<L, T, AT, ST>& g, int i, int j) {
+  return T(g.gup[up<L::D>(i, j)]);
+}
+
+template <class V>
+__device__ __forceinline__ void pin(V& v) {
+  if constexpr (sizeof(V) == 8) {
+    asm volatile("" : "+v"(v));
+  } else {
+    asm volatile("" : "+v"(v));
+  }
+}
+
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void pin_scalars(CellGeo<L, T, AT, ST>& g, T& rho) {
+  pin(g.J);
+#pragma unroll
+  for (int k = 0; k < nup<L::D>(); ++k) pin(g.gup[k]);
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) pin(g.aext[i]);
+  pin(rho);
+}
+
+// A^i_a in the arithmetic type.  When A is held narrower than T, the empty
+// register constraint keeps the widening inside the fixed-point loop instead
+// of letting it be hoisted (which would keep a wide copy of every A live).
+template <class T, class AT>
+__device__ __forceinline__ T widen(AT v) {
+  if constexpr (sizeof(AT) < sizeof(T)) asm volatile("" : "+v"(v));
+  return T(v);
 }
 
 // Per-cell scalars of the equilibrium that do not depend on the direction.
@@ -25,12 +65,12 @@ template <class L, class T> struct EqCoef {
   T rho, trG, U[L::D], Ut[L::D], r[L::D];
 };
 
-// Build the direction-independent parts of eq. (equilibrium):
-//  G^{ij} = (g^{ij} - d^{ij}) T0 + Ut^i Ut^j        -> trace
+// Direction-independent parts of eq. (equilibrium):
+//  G^{ij} = (g^{ij} - d^{ij}) T0 + Ut^i Ut^j        -> its trace
 //  R^{ijk} (fully symmetric)                          -> r^i = sum_j R^{ijj}
 //         = T0 [2 (g Ut)^i + tr(g) Ut^i - (D + 2) U^i] + |Ut|^2 Ut^i
-template <class L, class T>
-__device__ __forceinline__ EqCoef<L, T> eq_coef(const CellGeo<L, T>& g, T rho, const T* U, const T* Ut) {
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ EqCoef<L, T> eq_coef(const CellGeo<L, T, AT, ST>& g, T rho, const T* U, const T* Ut) {
   constexpr int D = L::D;
   const T t0 = T(T0);
   EqCoef<L, T> e;
@@ -59,16 +99,14 @@ __device__ __forceinline__ EqCoef<L, T> eq_coef(const CellGeo<L, T>& g, T rho, c
 // with H2:G = c.G.c/T0 - tr G and H3:R = R(c,c,c) - 3 T0 c.r,
 //   c.G.c = T0 (c.g.c - c.c) + (c.Ut)^2,
 //   R(c,c,c) = 3 T0 [(c.g.c)(c.Ut) - (c.c)(c.U)] + (c.Ut)^3.
-template <class L, class T, int a>
-__device__ __forceinline__ T feq_dir(const CellGeo<L, T>& g, const EqCoef<L, T>& e) {
+template <class L, class T, class AT, int ST, int a>
+__device__ __forceinline__ T feq_dir(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e) {
   constexpr int D = L::D;
   const T t0 = T(T0);
   T cU = 0, cUt = 0, cr = 0, cgc = 0;
   int cc = 0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    constexpr int dummy = 0;
-    (void)dummy;
     const int ci = L::c(a, i);
     if (ci == 0) continue;
     cc += ci * ci;
@@ -83,52 +121,18 @@ __device__ __forceinline__ T feq_dir(const CellGeo<L, T>& g, const EqCoef<L, T>&
     }
   }
   const T cGc = t0 * (cgc - T(cc)) + cUt * cUt;
-  const T H2G = cGc * T(3) - e.trG;                       // / T0 = * 3
+  const T H2G = cGc * T(3) - e.trG;
   const T H3R = T(3) * t0 * (cgc * cUt - T(cc) * cU) + cUt * cUt * cUt - T(3) * t0 * cr;
-  // 1/(2 T0) = 3/2, 1/(6 T0^3) = 27/6 = 9/2, 1/T0 = 3
+  // 1/T0 = 3, 1/(2 T0) = 3/2, 1/(6 T0^3) = 9/2
   return e.rho * T(L::w(a)) * (T(1) + T(3) * cU + T(1.5) * H2G + T(4.5) * H3R);
 }
 
-template <class L, class T, int a = 0>
-__device__ __forceinline__ void feq_all(const CellGeo<L, T>& g, const EqCoef<L, T>& e, T* fe) {
+template <class L, class T, class AT, int ST, int a = 0>
+__device__ __forceinline__ void feq_all(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, T* fe) {
   if constexpr (a < L::Q) {
-    fe[a] = feq_dir<L, T, a>(g, e);
-    feq_all<L, T, a + 1>(g, e, fe);
+    fe[a] = feq_dir<L, T, AT, ST, a>(g, e);
+    feq_all<L, T, AT, ST, a + 1>(g, e, fe);
   }
-}
-
-// Symmetrised dPi of eq. (delta-flux) (A contracted with c, S_a = A_a + A_opp(a)),
-// using the pair symmetry S_a = S_opp(a), c_opp(a) = -c_a:
-//   sum_a c^i S^j f_a = sum_pairs c^i_p S^j_p (f_p - f_opp(p)),
-// plus the body-force reading 1/2 k (Ut^i rho a^j + rho a^i Ut^j), k = 1 - 1/(2 tau).
-template <class L, class T>
-__device__ __forceinline__ void delta_pi(const CellGeo<L, T>& g, const T* fe, const T* Ut, T rho, T k,
-                                         T* dpi /* nup */) {
-  constexpr int D = L::D;
-  T M[D][D];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) M[i][j] = 0;
-#pragma unroll
-  for (int p = 1; p < L::Q; p += 2) {
-    const T df = fe[p] - fe[p + 1];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const int ci = L::c(p, i);
-      if (ci == 0) continue;
-#pragma unroll
-      for (int j = 0; j < D; ++j) M[i][j] += T(ci) * (g.A[p][j] + g.A[p + 1][j]) * df;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j) {
-      const T fi = T(-0.25) * k * (M[i][j] + M[j][i]);
-      const T fb = T(0.5) * k * rho * (Ut[i] * g.aext[j] + g.aext[i] * Ut[j]);
-      dpi[up<D>(i, j)] = fi + fb;
-    }
 }
 
 // dN_a = w_a J [c.F/T0 + H2_a:dPi/T0],  H2:dPi = c.dPi.c/T0 - tr dPi  (eq. (deltaN))
@@ -151,157 +155,244 @@ __device__ __forceinline__ T delta_n_dir(T J, const T* Ft, const T* dpi, T trdpi
   return T(L::w(a)) * J * (T(3) * cF + T(3) * (T(3) * cpc - trdpi));
 }
 
-// N'_a = N_a - (N_a - J f^eq_a)/tau + dN_a (eqs. (lbe), (collide)) and the
-// accumulation of -1/2 sum_a A^i_a N'_a for the next force (eq. (compo-constr)).
-template <class L, class T, int a = 0>
-__device__ __forceinline__ void post_collision(const CellGeo<L, T>& g, const T* N, const T* fe, const T* Ft,
-                                               const T* dpi, T trdpi, T inv_tau, T* Np, T* acc) {
-  if constexpr (a < L::Q) {
-    const T v = N[a] - (N[a] - g.J * fe[a]) * inv_tau + delta_n_dir<L, T, a>(g.J, Ft, dpi, trdpi);
-    Np[a] = v;
-    if constexpr (a > 0) {
+// Pass 1 of one fixed-point iteration, with the equilibrium at the current Ut:
+//   X^i  = sum_a A^i_a f^eq_a,   Xo^i = sum_a A^i_opp(a) f^eq_a (if wanted),
+//   M^{ij} = sum_a c^i_a S^j_a f^eq_a,  S_a = A_a + A_opp(a),
+// accumulated over opposite pairs (S_a = S_opp(a), c_opp(a) = -c_a) without
+// storing f^eq.
+template <class L, class T, class AT, int ST, bool WITH_XO, int p = 1>
+__device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, T* X, T* Xo,
+                                         T (*M)[L::D]) {
+  if constexpr (p < L::Q) {
+    const T fp = feq_dir<L, T, AT, ST, p>(g, e);
+    const T fm = feq_dir<L, T, AT, ST, p + 1>(g, e);
+    const T df = fp - fm;
 #pragma unroll
-      for (int i = 0; i < L::D; ++i) acc[i] -= T(0.5) * g.A[a][i] * v;
+    for (int i = 0; i < L::D; ++i) {
+      const T ap = widen<T>(g.a(p, i)), am = widen<T>(g.a(p + 1, i));
+      X[i] += ap * fp + am * fm;
+      if constexpr (WITH_XO) Xo[i] += am * fp + ap * fm;
     }
-    post_collision<L, T, a + 1>(g, N, fe, Ft, dpi, trdpi, inv_tau, Np, acc);
+#pragma unroll
+    for (int i = 0; i < L::D; ++i) {
+      const int ci = L::c(p, i);
+      if (ci == 0) continue;
+#pragma unroll
+      for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * (widen<T>(g.a(p, j)) + widen<T>(g.a(p + 1, j))) * df;
+    }
+    pass_feq<L, T, AT, ST, WITH_XO, p + 2>(g, e, X, Xo, M);
   }
+}
+
+// Pass 2: Y^i = sum_a A^i_a dN_a.
+template <class L, class T, class AT, int ST, int a = 1>
+__device__ __forceinline__ void pass_dn(const CellGeo<L, T, AT, ST>& g, const T* Ft, const T* dpi, T trdpi, T* Y) {
+  if constexpr (a < L::Q) {
+    const T dn = delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
+#pragma unroll
+    for (int i = 0; i < L::D; ++i) Y[i] += widen<T>(g.a(a, i)) * dn;
+    pass_dn<L, T, AT, ST, a + 1>(g, Ft, dpi, trdpi, Y);
+  }
+}
+
+// Output pass: N'_a = N_a - (N_a - J f^eq_a)/tau + dN_a  (eqs. (lbe), (collide)).
+template <class L, class T, class AT, int ST, class NS, int a = 0>
+__device__ __forceinline__ void pass_out(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, const NS* N, const T* Ft,
+                                         const T* dpi, T trdpi, T inv_tau, T* Np) {
+  if constexpr (a < L::Q) {
+    const T n = T(N[a]);
+    Np[a] = n - (n - g.j() * feq_dir<L, T, AT, ST, a>(g, e)) * inv_tau + delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
+    pass_out<L, T, AT, ST, NS, a + 1>(g, e, N, Ft, dpi, trdpi, inv_tau, Np);
+  }
+}
+
+// Symmetrised dPi of eq. (delta-flux) from M of pass 1, plus the body-force
+// reading 1/2 k (Ut^i rho a^j + rho a^i Ut^j), k = 1 - 1/(2 tau).  Returns tr dPi.
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ T finish_dpi(const CellGeo<L, T, AT, ST>& g, T (*M)[L::D], const T* Ut, T rho, T k, T* dpi) {
+  constexpr int D = L::D;
+  T tr = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      const T v = T(-0.25) * k * (M[i][j] + M[j][i]) + T(0.5) * k * rho * (Ut[i] * g.ae(j) + g.ae(i) * Ut[j]);
+      dpi[up<D>(i, j)] = v;
+      if (i == j) tr += v;
+    }
+  return tr;
+}
+
+// State of one cell's collision between its phases.
+template <class L, class T> struct CollState {
+  T rho, invJ, half_inv_rho, cJ;
+  T U[L::D], BC[L::D];          // BC = B - (1 - 1/tau) C / 2 (constant part of J F)
+  T Ut[L::D], Ft[L::D];
+  T dpi[nup<L::D>()], trdpi;
+  EqCoef<L, T> e;
+  int iters;                    // iterations used; max_iter + 1 when the cap was hit
+};
+
+// Phase 1: moments (eqs. (dist), (moments), (vcurvi)) and the parts of
+// eq. (compo-constr) that do not change during the fixed point:
+//   B^i = -1/2 sum_a A^i_opp(a) N_a  and  C^i = sum_a A^i_a N_a.
+template <class L, class T, class AT, int ST, class NS>
+__device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, const NS* N, T tau, CollState<L, T>& st) {
+  constexpr int D = L::D;
+  constexpr int Q = L::Q;
+  T rhoJ = 0;
+  T mom[D], C[D], B[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) mom[i] = C[i] = B[i] = 0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const T n = T(N[a]);
+    rhoJ += n;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * n;
+      if (a > 0) {
+        C[i] += T(g.a(a, i)) * n;
+        B[i] -= T(0.5) * T(g.a(opp(a), i)) * n;
+      }
+    }
+  }
+  const T inv_tau = T(1) / tau;
+  st.rho = rhoJ / g.j();
+  st.invJ = T(1) / g.j();
+  st.half_inv_rho = T(0.5) / st.rho;
+  st.cJ = g.j() * inv_tau;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    st.U[i] = mom[i] / rhoJ;
+    st.BC[i] = B[i] - T(0.5) * (T(1) - inv_tau) * C[i];
+  }
+}
+
+// Phase 2: the implicit inertial force (eq. (compo-constr) and the remark
+// after eq. (deltaN)) as a fixed point on F, iterated until
+// max_i |F_k - F_(k-1)| <= tol * rho.  F holds the starting guess on entry
+// (0, or the previous step's converged F: the converged fixed point does not
+// depend on it) and the converged F on exit; st keeps the equilibrium, dPi and
+// F_tot of the last iteration for the output phase.  Each iteration uses
+//   sum_a A_a N'_a = (1 - 1/tau) C + (J/tau) sum_a A_a f^eq_a + sum_a A_a dN_a
+// so that no per-direction array is live inside the loop.
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, T tau, T tol, int max_iter, T* F,
+                                                CollState<L, T>& st, int min_iter = 1) {
+  constexpr int D = L::D;
+  const T k = T(1) - T(0.5) / tau;
+  int it = 1;
+  int done = 0;
+  CellGeo<L, T, AT, ST> gl = g;
+  T rho_l = st.rho;
+  for (; it <= max_iter; ++it) {
+    // Re-define the per-cell scalars each iteration (empty register
+    // constraints): quantities derived from them (c.g.c per direction, rho w,
+    // widened g^{ij}) are then recomputed instead of being kept live across
+    // iterations, which keeps the register footprint and occupancy reasonable.
+    pin_scalars<L, T, AT, ST>(gl, rho_l);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      st.Ft[i] = F[i] + rho_l * gl.ae(i);
+      st.Ut[i] = st.U[i] + st.Ft[i] * st.half_inv_rho;
+    }
+    st.e = eq_coef<L, T, AT, ST>(gl, rho_l, st.U, st.Ut);
+    T X[D], M[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      X[i] = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) M[i][j] = 0;
+    }
+    pass_feq<L, T, AT, ST, false>(gl, st.e, X, nullptr, M);
+    st.trdpi = finish_dpi<L, T, AT, ST>(gl, M, st.Ut, rho_l, k, st.dpi);
+    T Y[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) Y[i] = 0;
+    pass_dn<L, T, AT, ST>(gl, st.Ft, st.dpi, st.trdpi, Y);
+    T change = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const T Fn = (st.BC[i] - T(0.5) * (st.cJ * X[i] + Y[i])) * st.invJ;
+      const T dd = Fn - F[i];
+      change = fmax(change, dd < T(0) ? -dd : dd);
+      F[i] = Fn;
+    }
+    if (change <= tol * rho_l && it >= min_iter) {
+      done = 1;
+      break;
+    }
+  }
+  st.iters = done ? it : max_iter + 1;
+}
+
+// Phase 3: N' of the last iteration (eqs. (lbe), (collide), (deltaN)).
+template <class L, class T, class AT, int ST, class NS>
+__device__ __forceinline__ void collide_output(const CellGeo<L, T, AT, ST>& g, const NS* N, T tau, const CollState<L, T>& st,
+                                               T* Np) {
+  pass_out<L, T, AT, ST, NS>(g, st.e, N, st.Ft, st.dpi, st.trdpi, T(1) / tau, Np);
 }
 
 struct CollideOut {
   int iters;   // iterations used; max_iter + 1 when the cap was hit
 };
 
-// The collision of one cell: moments (eqs. (dist), (moments), (vcurvi)), then
-// the implicit inertial force (eq. (compo-constr), remark after eq. (deltaN))
-// solved as a fixed point on F from F = 0, iterated until
-// max_i |F_k - F_(k-1)| <= tol * rho; Np receives the N' of the last iteration.
-template <class L, class T>
-__device__ __forceinline__ CollideOut collide(const CellGeo<L, T>& g, const T* N, T tau, T tol, int max_iter, T* Np,
-                                              T* F_out, T* Ut_out, T* U_out, T& rho_out) {
-  constexpr int D = L::D;
-  constexpr int Q = L::Q;
-  T rhoJ = 0;
-  T mom[D];
+// The whole collision of one cell with N held in registers throughout.
+template <class L, class T, class AT, int ST, class NS>
+__device__ __forceinline__ CollideOut collide(const CellGeo<L, T, AT, ST>& g, const NS* N, T tau, T tol, int max_iter,
+                                              T* Np, T* F, T* Ut_out, T* U_out, T& rho_out) {
+  CollState<L, T> st;
+  collide_prepare<L, T, AT, ST, NS>(g, N, tau, st);
+  collide_iterate<L, T, AT, ST>(g, tau, tol, max_iter, F, st);
+  collide_output<L, T, AT, ST, NS>(g, N, tau, st, Np);
 #pragma unroll
-  for (int i = 0; i < D; ++i) mom[i] = 0;
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    rhoJ += N[a];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-      if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * N[a];
+  for (int i = 0; i < L::D; ++i) {
+    Ut_out[i] = st.Ut[i];
+    U_out[i] = st.U[i];
   }
-  const T rho = rhoJ / g.J;
-  T U[D], B[D], F[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    U[i] = mom[i] / rhoJ;
-    B[i] = 0;
-    F[i] = 0;
-  }
-  // B^i = -1/2 sum_a A^i_opp(a) N_a (the incoming part of eq. (compo-constr))
-#pragma unroll
-  for (int a = 1; a < Q; ++a)
-#pragma unroll
-    for (int i = 0; i < D; ++i) B[i] -= T(0.5) * g.A[opp(a)][i] * N[a];
-  const T k = T(1) - T(0.5) / tau;
-  const T inv_tau = T(1) / tau;
-  const T invJ = T(1) / g.J;
-  const T half_inv_rho = T(0.5) / rho;
-  T Ut[D];
-  int it = 1;
-  int done = 0;
-  for (; it <= max_iter; ++it) {
-    T Ft[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      Ft[i] = F[i] + rho * g.aext[i];
-      Ut[i] = U[i] + Ft[i] * half_inv_rho;
-    }
-    const EqCoef<L, T> e = eq_coef<L, T>(g, rho, U, Ut);
-    T fe[Q];
-    feq_all<L, T>(g, e, fe);
-    T dpi[nup<D>()];
-    delta_pi<L, T>(g, fe, Ut, rho, k, dpi);
-    T trdpi = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) trdpi += dpi[up<D>(i, i)];
-    T acc[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) acc[i] = B[i];
-    post_collision<L, T>(g, N, fe, Ft, dpi, trdpi, inv_tau, Np, acc);
-    T change = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const T Fn = acc[i] * invJ;
-      const T dd = Fn - F[i];
-      change = fmax(change, dd < T(0) ? -dd : dd);
-      F[i] = Fn;
-    }
-    if (change <= tol * rho) {
-      done = 1;
-      break;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    F_out[i] = F[i];
-    Ut_out[i] = Ut[i];
-    U_out[i] = U[i];
-  }
-  rho_out = rho;
+  rho_out = st.rho;
   CollideOut o;
-  o.iters = done ? it : max_iter + 1;
+  o.iters = st.iters;
   return o;
 }
 
-// Consistent equilibrium (the library's reading for initial and imposed
-// states): find F such that with U = Ut - F_tot/(2 rho) the populations
-// N = J f^eq(rho, U, Ut) have that F as their collision fixed point.
-template <class L, class T>
-__device__ __forceinline__ int consistent_equilibrium(const CellGeo<L, T>& g, T rho, const T* Ut, T tau, T tol,
-                                                      int max_iter, T* N) {
+// Consistent equilibrium (the library's reading for the initial state): find F
+// such that with U = Ut - F_tot/(2 rho) the populations N = J f^eq(rho, U, Ut)
+// have that F as their collision fixed point.  Omega = 0 there (f = f^eq at
+// that Ut), so N' = N + dN and
+//   J F = -1/2 sum_a [A_a (N_a + dN_a) + A_opp(a) N_a] = -1/2 [J X + Y + J Xo].
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ int consistent_equilibrium(const CellGeo<L, T, AT, ST>& g, T rho, const T* Ut, T tau, T tol,
+                                                      int max_iter, T* N, T* F_out) {
   constexpr int D = L::D;
-  constexpr int Q = L::Q;
   const T k = T(1) - T(0.5) / tau;
-  const T invJ = T(1) / g.J;
   const T half_inv_rho = T(0.5) / rho;
-  T F[D];
+  T F[D], U[D], Ft[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) F[i] = 0;
   int ok = 0;
   for (int it = 0; it < max_iter; ++it) {
-    T Ft[D], U[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      Ft[i] = F[i] + rho * g.aext[i];
+      Ft[i] = F[i] + rho * g.ae(i);
       U[i] = Ut[i] - Ft[i] * half_inv_rho;
     }
-    const EqCoef<L, T> e = eq_coef<L, T>(g, rho, U, Ut);
-    T fe[Q];
-    feq_all<L, T>(g, e, fe);
-    T dpi[nup<D>()];
-    delta_pi<L, T>(g, fe, Ut, rho, k, dpi);
-    T trdpi = 0;
+    const EqCoef<L, T> e = eq_coef<L, T, AT, ST>(g, rho, U, Ut);
+    T X[D], Xo[D], M[D][D], Y[D], dpi[nup<D>()];
 #pragma unroll
-    for (int i = 0; i < D; ++i) trdpi += dpi[up<D>(i, i)];
-    T Nc[Q];
+    for (int i = 0; i < D; ++i) {
+      X[i] = Xo[i] = Y[i] = 0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) Nc[a] = g.J * fe[a];
-    // N' = N + dN (Omega = 0 since f = f^eq at this Ut); B uses the arrived N = N
-    T acc[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) acc[i] = 0;
-#pragma unroll
-    for (int a = 1; a < Q; ++a)
-#pragma unroll
-      for (int i = 0; i < D; ++i) acc[i] -= T(0.5) * g.A[opp(a)][i] * Nc[a];
-    T Np[Q];
-    post_collision<L, T>(g, Nc, fe, Ft, dpi, trdpi, T(0), Np, acc);
+      for (int j = 0; j < D; ++j) M[i][j] = 0;
+    }
+    pass_feq<L, T, AT, ST, true>(g, e, X, Xo, M);
+    const T trdpi = finish_dpi<L, T, AT, ST>(g, M, Ut, rho, k, dpi);
+    pass_dn<L, T, AT, ST>(g, Ft, dpi, trdpi, Y);
     T change = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const T Fn = acc[i] * invJ;
+      const T Fn = T(-0.5) * (X[i] + Xo[i] + Y[i] / g.j());
       const T dd = Fn - F[i];
       change = fmax(change, dd < T(0) ? -dd : dd);
       F[i] = Fn;
@@ -311,25 +402,25 @@ __device__ __forceinline__ int consistent_equilibrium(const CellGeo<L, T>& g, T 
       break;
     }
   }
-  T Ft[D], U[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    Ft[i] = F[i] + rho * g.aext[i];
+    Ft[i] = F[i] + rho * g.ae(i);
     U[i] = Ut[i] - Ft[i] * half_inv_rho;
+    F_out[i] = F[i];
   }
-  const EqCoef<L, T> e = eq_coef<L, T>(g, rho, U, Ut);
-  T fe[Q];
-  feq_all<L, T>(g, e, fe);
+  const EqCoef<L, T> e = eq_coef<L, T, AT, ST>(g, rho, U, Ut);
+  T fe[L::Q];
+  feq_all<L, T, AT, ST>(g, e, fe);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) N[a] = g.J * fe[a];
+  for (int a = 0; a < L::Q; ++a) N[a] = g.j() * fe[a];
   return ok;
 }
 
-// Far-field population J f^eq(rho_inf, U_inf, U_inf) for direction a (runtime a).
-template <class L, class T>
-__device__ __forceinline__ void feq_farfield(const CellGeo<L, T>& g, T rho_inf, const T* Uinf, T* fe) {
-  const EqCoef<L, T> e = eq_coef<L, T>(g, rho_inf, Uinf, Uinf);
-  feq_all<L, T>(g, e, fe);
+// Far-field populations f^eq(rho_inf, U_inf, U_inf) (multiply by J for N).
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void feq_farfield(const CellGeo<L, T, AT, ST>& g, T rho_inf, const T* Uinf, T* fe) {
+  const EqCoef<L, T> e = eq_coef<L, T, AT, ST>(g, rho_inf, Uinf, Uinf);
+  feq_all<L, T, AT, ST>(g, e, fe);
 }
 
 }  // namespace vlbm

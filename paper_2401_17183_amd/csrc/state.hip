@@ -31,6 +31,8 @@ template <class S> struct StateArgs {
   double* N_out;
   int* flag;
   double* u_prev;
+  void* fcache;        // [d][cells], FP64 or FP32 (fc64)
+  int fc64;
   int have_prev;
   double* partial;     // [blocks][kAuditWords]
 };
@@ -46,7 +48,7 @@ __device__ inline CellGeo<L, double> load_fp64(const StateArgs<S>& a, int cell, 
 #pragma unroll
   for (int al = 0; al < L::Q; ++al)
 #pragma unroll
-    for (int i = 0; i < D; ++i) g.A[al][i] = a.A[(al * D + i) * nc + cell];
+    for (int i = 0; i < D; ++i) g.Areg[al][i] = a.A[(al * D + i) * nc + cell];
   for (int i = 0; i < D; ++i) {
     double ae = 0, uc = 0;
     for (int k = 0; k < D; ++k) {
@@ -93,7 +95,7 @@ __device__ inline void gather64(const StateArgs<S>& a, const CellGeo<L, double>&
     feq_farfield<L, double>(g, a.rho_inf, Uinf, fe);
 #pragma unroll
     for (int al = 0; al < L::Q; ++al)
-      if (ff & (1u << al)) N[al] = g.J * fe[al];
+      if (ff & (1u << al)) N[al] = g.j() * fe[al];
   }
 }
 
@@ -128,9 +130,13 @@ __global__ __launch_bounds__(kBlock) void k_init(StateArgs<S> a) {
       for (int k = 0; k < D; ++k) s += a.u_in[k * nc + cell] * a.gco[(i * D + k) * nc + cell];
     Ut[i] = s;
   }
-  double N[L::Q];
-  if (!consistent_equilibrium<L, double>(g, rho, Ut, a.tau, a.tol, a.max_iter, N)) atomicAdd(a.flag, 1);
+  double N[L::Q], F[D];
+  if (!consistent_equilibrium<L, double>(g, rho, Ut, a.tau, a.tol, a.max_iter, N, F)) atomicAdd(a.flag, 1);
   unstream_store<L, S>(a, cell, x, y, z, N);
+  for (int i = 0; i < D; ++i) {
+    if (a.fc64) static_cast<double*>(a.fcache)[i * nc + cell] = F[i];
+    else static_cast<float*>(a.fcache)[i * nc + cell] = (float)F[i];
+  }
 }
 
 template <class L, class S>
@@ -178,7 +184,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(StateArgs<S> a) {
   unsigned wm;
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
   double Np[L::Q], F[D], Ut[D], U[D], rho;
-  const CollideOut o = collide<L, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
+  for (int i = 0; i < D; ++i) F[i] = 0;
+  const CollideOut o = collide<L, double, double, 0, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
   if (o.iters > a.max_iter) atomicAdd(a.flag, 1);
   a.rho_out[cell] = rho;
   for (int k = 0; k < D; ++k) {
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
 #pragma unroll
       for (int i = 0; i < D; ++i) {
         const double ci = L::c(al, i);
-        const double Ao = g.A[opp(al)][i];
+        const double Ao = g.a(opp(al), i);
         inner[i] += (ci - 0.5 * Ao) * n;
         if (wm & (1u << al)) wall[i] += (2.0 * ci - Ao) * n;
       }
@@ -243,7 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
     v[10] = negative;
     if (!nonfinite) {
       double Np[Q], F[D], Ut[D], U[D], rho;
-      const CollideOut o = collide<L, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
+      for (int i = 0; i < D; ++i) F[i] = 0;
+      const CollideOut o = collide<L, double, double, 0, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
       v[11] = o.iters > a.max_iter ? 1.0 : 0.0;
       v[12] = o.iters;
       double du2 = 0, uu = 0;
@@ -335,6 +343,8 @@ StateArgs<S> make_args(SimObj* s) {
   a.in = static_cast<const S*>(s->pop[s->buf]);
   a.out = static_cast<S*>(s->pop[s->buf]);
   a.flag = s->flags;
+  a.fcache = s->fcache;
+  a.fc64 = fcache_elem(s->p.precision) == 8;
   return a;
 }
 

@@ -8,6 +8,13 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Two resident waves per SIMD: the LDS staging of A (55 KB per 256-thread
+// block for D3Q19 FP32) allows two blocks per CU, and the register budget is
+// held to that occupancy.
+#ifndef VLBM_STEP_ATTR
+#define VLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 8)))
+#endif
+
 // S: storage type of populations and packed geometry; T: arithmetic type.
 template <class S, class T> struct StepArgs {
   Box box;
@@ -18,28 +25,80 @@ template <class S, class T> struct StepArgs {
   int max_iter;
   int stream_only;
   int has_force, has_ff;
+  T* __restrict__ fcache;       // [D][cells] starting guess in, converged F out
+  int min_iter;
   int* flags;
 };
 
-template <class L, class S, class T>
-__device__ __forceinline__ CellGeo<L, T> load_pack(const S* __restrict__ geo, int nc, int cell, int has_force) {
-  CellGeo<L, T> g;
-  g.J = T(geo[(long)Pack<L>::J * nc + cell]);
+// A stays in registers in its storage type S and converts to T at each use.
+// Word w of a SoA array: the wave-uniform base (w * nc) is formed in scalar
+// registers, lanes carry only their 32-bit cell offset.
+template <class S>
+__device__ __forceinline__ const S* word(const S* __restrict__ base, int w, int nc) {
+  return base + (size_t)w * (size_t)nc;
+}
+template <class S>
+__device__ __forceinline__ S* word(S* __restrict__ base, int w, int nc) {
+  return base + (size_t)w * (size_t)nc;
+}
+
+// With ST > 0 the link coefficients are staged in LDS (this thread's column
+// of lds, stride ST) instead of registers; only this thread reads its column.
+template <class L, class S, class T, int ST>
+__device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ geo, int nc, int cell, int has_force,
+                                                          S* lds) {
+  CellGeo<L, T, S, ST> g;
+  g.J = word(geo, Pack<L>::J, nc)[cell];
 #pragma unroll
-  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = T(geo[(long)(Pack<L>::GUP + k) * nc + cell]);
-#pragma unroll
-  for (int i = 0; i < L::D; ++i) g.A[0][i] = T(0);
+  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = word(geo, Pack<L>::GUP + k, nc)[cell];
 #pragma unroll
   for (int a = 1; a < L::Q; ++a)
 #pragma unroll
-    for (int i = 0; i < L::D; ++i) g.A[a][i] = T(geo[(long)(Pack<L>::A + (a - 1) * L::D + i) * nc + cell]);
+    for (int i = 0; i < L::D; ++i) {
+      const S v = word(geo, Pack<L>::A + (a - 1) * L::D + i, nc)[cell];
+      if constexpr (ST == 0) g.Areg[a][i] = v;
+      else lds[((a - 1) * L::D + i) * ST] = v;
+    }
+  if constexpr (ST == 0)
 #pragma unroll
-  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? T(geo[(long)(Pack<L>::AEXT + i) * nc + cell]) : T(0);
+    for (int i = 0; i < L::D; ++i) g.Areg[0][i] = S(0);
+  g.lds = lds;
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? word(geo, Pack<L>::AEXT + i, nc)[cell] : S(0);
   return g;
 }
 
+// Pull N_a(q) = N'_a(q - c_a) (eq. (adv)).  Every load is unconditional and in
+// bounds (a bounced or far-field link reads the cell's own opposite slot), so
+// no lane diverges; far-field links then take J f^eq(rho_inf, U_inf, U_inf).
+template <class L, class S, class T, int ST>
+__device__ __forceinline__ void gather(const StepArgs<S, T>& a, const CellGeo<L, T, S, ST>& g, int x, int y, int z,
+                                       int cell, S* N) {
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  const int nc = a.box.ncells;
+  unsigned ff = 0;
+#pragma unroll
+  for (int al = 0; al < Q; ++al) {
+    int src;
+    const int kind = link_source<L>(a.box, al, x, y, z, src);
+    const int dir = kind == LINK_INTERIOR ? al : opp(al);
+    N[al] = word(a.in, 0, nc)[(size_t)dir * nc + src];
+    ff |= (kind == LINK_FARFIELD ? 1u : 0u) << al;
+  }
+  if (a.has_ff) {   // wave-uniform
+    T Uinf[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) Uinf[i] = T(word(a.geo, Pack<L>::UINF + i, nc)[cell]);
+    T fe[Q];
+    feq_farfield<L, T>(g, a.rho_inf, Uinf, fe);
+#pragma unroll
+    for (int al = 0; al < Q; ++al) N[al] = (ff >> al) & 1u ? S(g.j() * fe[al]) : N[al];
+  }
+}
+
 template <class L, class S, class T>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs<S, T> a) {
+__device__ __forceinline__ void step_cell(const StepArgs<S, T>& a) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   const int cell = blockIdx.x * kBlock + threadIdx.x;
@@ -49,41 +108,47 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<S, T> a) {
   const int r = cell / a.box.n[0];
   const int y = r % a.box.n[1];
   const int z = r / a.box.n[1];
-  // pull advection: N_a(q) = N'_a(q - c_a); walls bounce back, far field imposes
-  T N[Q];
-  unsigned ff = 0;
-#pragma unroll
-  for (int al = 0; al < Q; ++al) {
-    int src;
-    const int kind = link_source<L>(a.box, al, x, y, z, src);
-    if (kind == LINK_INTERIOR) N[al] = T(a.in[(long)al * nc + src]);
-    else if (kind == LINK_WALL) N[al] = T(a.in[(long)opp(al) * nc + cell]);
-    else {
-      N[al] = T(0);
-      ff |= 1u << al;
-    }
-  }
-  const CellGeo<L, T> g = load_pack<L, S, T>(a.geo, nc, cell, a.has_force);
-  if (ff) {
-    T Uinf[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) Uinf[i] = T(a.geo[(long)(Pack<L>::UINF + i) * nc + cell]);
-    T fe[Q];
-    feq_farfield<L, T>(g, a.rho_inf, Uinf, fe);
-#pragma unroll
-    for (int al = 0; al < Q; ++al)
-      if (ff & (1u << al)) N[al] = g.J * fe[al];
-  }
+  // FP32 storage stages A in LDS (55 KB per 256-thread block for D3Q19)
+  constexpr int ST = sizeof(S) == 4 ? kBlock : 0;
+  __shared__ S sA[ST ? (Q - 1) * D * kBlock : 1];
+  // pull advection: N_a(q) = N'_a(q - c_a); walls bounce back, far field imposes.
+  S N[Q];
+  const CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
+  gather<L, S, T, ST>(a, g, x, y, z, cell, N);
   if (a.stream_only) {
 #pragma unroll
-    for (int al = 0; al < Q; ++al) a.out[(long)al * nc + cell] = S(N[al]);
+    for (int al = 0; al < Q; ++al) word(a.out, al, nc)[cell] = N[al];
     return;
   }
-  T Np[Q], F[D], Ut[D], U[D], rho;
-  const CollideOut o = collide<L, T>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
-  if (o.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
+  T F[D];
 #pragma unroll
-  for (int al = 0; al < Q; ++al) a.out[(long)al * nc + cell] = S(Np[al]);
+  for (int i = 0; i < D; ++i) F[i] = T(word(a.fcache, i, nc)[cell]);
+  CollState<L, T> st;
+  collide_prepare<L, T, S, ST, S>(g, N, a.tau, st);
+  collide_iterate<L, T, S, ST>(g, a.tau, a.tol, a.max_iter, F, st, a.min_iter);
+  if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
+#pragma unroll
+  for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
+  // gather again (cache hits) rather than keeping N live across the fixed point
+  int xr = x;
+  pin(xr);
+  gather<L, S, T, ST>(a, g, xr, y, z, cell, N);
+  T Np[Q];
+  collide_output<L, T, S, ST, S>(g, N, a.tau, st, Np);
+#pragma unroll
+  for (int al = 0; al < Q; ++al) word(a.out, al, nc)[cell] = S(Np[al]);
+}
+
+// FP32 storage: two waves per SIMD (see VLBM_STEP_ATTR).
+template <class L, class S, class T>
+__global__ __launch_bounds__(kBlock) VLBM_STEP_ATTR void k_step(StepArgs<S, T> a) {
+  step_cell<L, S, T>(a);
+}
+
+// FP64 storage keeps A in registers and runs at the occupancy the compiler picks.
+template <class L, class S, class T>
+__global__ __launch_bounds__(kBlock) void k_step64(StepArgs<S, T> a) {
+  step_cell<L, S, T>(a);
 }
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
@@ -129,8 +194,15 @@ hipError_t step_typed(SimObj* s) {
   a.has_force = s->has_force;
   a.has_ff = s->has_farfield;
   a.flags = s->flags;
+  a.fcache = static_cast<T*>(s->fcache);
+  // FP32 arithmetic cannot resolve a warm-started first update below its own
+  // roundoff: take at least two iterations there.
+  a.min_iter = sizeof(T) == 4 ? 2 : 1;
   const int nb = (a.box.ncells + kBlock - 1) / kBlock;
-  k_step<L, S, T><<<nb, kBlock, 0, s->stream>>>(a);
+  if constexpr (sizeof(S) == 8)
+    k_step64<L, S, T><<<nb, kBlock, 0, s->stream>>>(a);
+  else
+    k_step<L, S, T><<<nb, kBlock, 0, s->stream>>>(a);
   return hipGetLastError();
 }
 
