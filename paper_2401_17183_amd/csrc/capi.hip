@@ -52,7 +52,8 @@ void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
-size_t storage_bytes(int precision) { return precision == VLBM_FP64 ? 8 : 4; }
+size_t storage_bytes(int precision) { return pop_elem(precision); }
+size_t geometry_bytes(int precision) { return precision == VLBM_FP64 ? 8 : 4; }
 
 constexpr uint64_t kMagic = 0x314d42564c4d4956ull;  // checkpoint tag
 
@@ -239,6 +240,8 @@ static void free_sim(SimObj* s) {
   dev_free(s->pop[1]);
   dev_free(s->geo);
   dev_free(s->fcache);
+  dev_free(s->rown);
+  dev_free(s->rsrc);
   dev_free(s->audit_ring);
   dev_free(s->audit_partial);
   dev_free(s->u_prev);
@@ -258,7 +261,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   *out = nullptr;
   if (!m->have_geometry) return fail(VLBM_ERR_STATE, "vlbm_init before vlbm_geometry_precompute");
   if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(VLBM_ERR_ARG, "tau must exceed 1/2 (got %g)", p->tau);
-  if (p->precision != VLBM_FP64 && p->precision != VLBM_FP32 && p->precision != VLBM_FP32C)
+  if (p->precision < VLBM_FP64 || p->precision > VLBM_FP32C)
     return fail(VLBM_ERR_UNSUPPORTED, "precision %d is not built", p->precision);
   if (p->audit_every < 0) return fail(VLBM_ERR_ARG, "audit_every must be >= 0");
   SimObj* s = new (std::nothrow) SimObj();
@@ -268,6 +271,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   if (s->p.fp_max_iter <= 0) s->p.fp_max_iter = 50;
   if (s->p.fp_tol < 0)
     s->p.fp_tol = s->p.precision == VLBM_FP64 ? 1e-14 : (s->p.precision == VLBM_FP32 ? 1e-10 : 1e-7);
+  // (FP16S / BF16S use FP32 arithmetic, like FP32C)
   s->stream = static_cast<hipStream_t>(stream);
   const int d = m->d;
   for (int k = 0; k < d; ++k)
@@ -286,7 +290,11 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   if ((rc = dev_alloc(&s->pop[0], s->pop_bytes))) return bail(rc);
   if ((rc = dev_alloc(&s->pop[1], s->pop_bytes))) return bail(rc);
   const int words = m->lattice == VLBM_D2Q9 ? Pack<D2Q9>::WORDS : Pack<D3Q19>::WORDS;
-  if ((rc = dev_alloc(&s->geo, nc * words * sb))) return bail(rc);
+  if ((rc = dev_alloc(&s->geo, nc * words * geometry_bytes(s->p.precision)))) return bail(rc);
+  if (storage_is_16(s->p.precision)) {
+    if ((rc = dev_alloc(&s->rown, nc * m->Q * sb))) return bail(rc);
+    if ((rc = dev_alloc(&s->rsrc, nc * m->Q * sb))) return bail(rc);
+  }
   if ((rc = dev_alloc(&s->fcache, nc * d * fcache_elem(s->p.precision)))) return bail(rc);
   s->audit_cap = 4096;
   if ((rc = dev_alloc(&s->audit_ring, sizeof(vlbm_audit) * s->audit_cap))) return bail(rc);
@@ -299,6 +307,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->fcache, 0, nc * d * fcache_elem(s->p.precision), s->stream);
   if (e == hipSuccess) e = launch_pack(s);
+  if (e == hipSuccess && storage_is_16(s->p.precision)) e = launch_refs(s);
   if (e == hipSuccess) e = launch_init(s, rho, u, s->flags);
   int hflag = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream);

@@ -2,6 +2,8 @@
 // Not part of the public ABI (include/vlbm.h is).
 #pragma once
 
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -47,6 +49,36 @@ struct D3Q19 {
 __host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
 
 constexpr double T0 = 1.0 / 3.0;
+
+// ---------------------------------------------------------------------------
+// Population storage codecs.  FP64/FP32 store N itself.  The 16-bit modes
+// store h = round16(s (N - R)), a scaled deviation from a per-link reference R:
+// the post-collision rest state of the cell that wrote the slot.  R is itself
+// held in the 16-bit type, so writer and reader add back the same value.
+// ---------------------------------------------------------------------------
+template <class P> struct PopCodec {
+  static constexpr bool shifted = false;
+  template <class T> __device__ __forceinline__ static T decode(P h, P, float) { return T(h); }
+  template <class T> __device__ __forceinline__ static P encode(T n, P, float) { return P(n); }
+};
+template <> struct PopCodec<__half> {
+  static constexpr bool shifted = true;
+  template <class T> __device__ __forceinline__ static T decode(__half h, __half r, float inv_s) {
+    return T(__half2float(r)) + T(__half2float(h)) * T(inv_s);
+  }
+  template <class T> __device__ __forceinline__ static __half encode(T n, __half r, float s) {
+    return __float2half_rn(float((n - T(__half2float(r))) * T(s)));
+  }
+};
+template <> struct PopCodec<__hip_bfloat16> {
+  static constexpr bool shifted = true;
+  template <class T> __device__ __forceinline__ static T decode(__hip_bfloat16 h, __hip_bfloat16 r, float inv_s) {
+    return T(__bfloat162float(r)) + T(__bfloat162float(h)) * T(inv_s);
+  }
+  template <class T> __device__ __forceinline__ static __hip_bfloat16 encode(T n, __hip_bfloat16 r, float s) {
+    return __float2bfloat16(float((n - T(__bfloat162float(r))) * T(s)));
+  }
+};
 
 // Number of stored g^{ij} words (upper triangle) and its index map.
 template <int D> __host__ __device__ constexpr int nup() { return D * (D + 1) / 2; }
@@ -135,6 +167,8 @@ struct SimObj {
   void* pop[2] = {nullptr, nullptr};
   size_t pop_bytes = 0;
   void* geo = nullptr;    // precision pack
+  void* rown = nullptr;     // 16-bit modes: [Q][cells] reference of the slot this cell writes
+  void* rsrc = nullptr;     // 16-bit modes: [Q][cells] reference of the slot this cell reads
   void* fcache = nullptr;   // [d][cells]: converged inertial force of the last step (fixed-point start),
                             // in the arithmetic type (FP64 except for FP32C)
   int has_force = 0, has_farfield = 0;
@@ -150,7 +184,16 @@ struct SimObj {
 };
 
 inline bool storage_is_fp64(int precision) { return precision == VLBM_FP64; }
-inline size_t fcache_elem(int precision) { return precision == VLBM_FP32C ? 4 : 8; }
+inline bool storage_is_16(int precision) { return precision == VLBM_FP16S || precision == VLBM_BF16S; }
+inline size_t pop_elem(int precision) {
+  return precision == VLBM_FP64 ? 8 : (storage_is_16(precision) ? 2 : 4);
+}
+// scale s of the 16-bit deviations: FP16 needs it to keep small deviations
+// out of its subnormal range, BF16 shares FP32's exponent range
+inline float pop_scale(int precision) { return precision == VLBM_FP16S ? 4096.0f : 1.0f; }
+inline size_t fcache_elem(int precision) {
+  return (precision == VLBM_FP32C || storage_is_16(precision)) ? 4 : 8;
+}
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial);
@@ -161,6 +204,7 @@ hipError_t launch_moments(SimObj* s, double* rho, double* u, double* U, int* dfl
 hipError_t launch_get_pop(SimObj* s, double* N);
 hipError_t launch_set_pop(SimObj* s, const double* N);
 hipError_t launch_audit(SimObj* s, int slot);
+hipError_t launch_refs(SimObj* s);
 
 int geometry_partial_blocks(const MeshObj* m);
 

@@ -22,6 +22,9 @@ template <class S> struct StateArgs {
   int max_iter;
   const S* in;         // populations to gather from (N'(t-1))
   S* out;              // populations to scatter into
+  const S* rsrc;       // 16-bit modes: reference of each arriving link
+  S* rown;             // 16-bit modes: reference of each written slot
+  float scale, inv_scale;
   const double* rho_in;
   const double* u_in;
   const double* N_in;
@@ -81,14 +84,11 @@ __device__ inline void gather64(const StateArgs<S>& a, const CellGeo<L, double>&
   for (int al = 0; al < L::Q; ++al) {
     int src;
     const int kind = link_source<L>(a.box, al, x, y, z, src);
-    if (kind == LINK_INTERIOR) N[al] = (double)a.in[al * nc + src];
-    else if (kind == LINK_WALL) {
-      N[al] = (double)a.in[opp(al) * nc + cell];
-      wallmask |= 1u << al;
-    } else {
-      N[al] = 0;
-      ff |= 1u << al;
-    }
+    const int dir = kind == LINK_INTERIOR ? al : opp(al);
+    N[al] = PopCodec<S>::template decode<double>(a.in[dir * nc + src], a.rsrc ? a.rsrc[al * nc + cell] : S(0),
+                                                 a.inv_scale);
+    if (kind == LINK_WALL) wallmask |= 1u << al;
+    if (kind == LINK_FARFIELD) ff |= 1u << al;
   }
   if (ff) {
     double fe[L::Q];
@@ -107,8 +107,11 @@ __device__ inline void unstream_store(const StateArgs<S>& a, int cell, int x, in
   for (int al = 0; al < L::Q; ++al) {
     int src;
     const int kind = link_source<L>(a.box, al, x, y, z, src);
-    if (kind == LINK_INTERIOR) a.out[al * nc + src] = (S)N[al];
-    else if (kind == LINK_WALL) a.out[opp(al) * nc + cell] = (S)N[al];
+    if (kind == LINK_FARFIELD) continue;
+    const int dir = kind == LINK_INTERIOR ? al : opp(al);
+    // the reader's reference is the writer's: rsrc of the arriving link
+    a.out[dir * nc + src] =
+        PopCodec<S>::template encode<double>(N[al], a.rsrc ? a.rsrc[al * nc + cell] : S(0), a.scale);
   }
 }
 
@@ -166,6 +169,44 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(StateArgs<S> a) {
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
 #pragma unroll
   for (int al = 0; al < L::Q; ++al) a.N_out[al * nc + cell] = N[al];
+}
+
+// 16-bit storage references: the post-collision rest state of every cell
+// (rest consistent equilibrium, rho = 1, u = 0, then one collision), rounded to
+// the storage type, is the reference of the slots the cell writes (rown).
+template <class L, class S>
+__global__ __launch_bounds__(kBlock) void k_refs_own(StateArgs<S> a) {
+  constexpr int D = L::D;
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= a.box.ncells) return;
+  const long nc = a.box.ncells;
+  double Uinf[D];
+  const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
+  double Ut[D], N[L::Q], F[D];
+  for (int i = 0; i < D; ++i) Ut[i] = 0;
+  if (!consistent_equilibrium<L, double>(g, 1.0, Ut, a.tau, a.tol, a.max_iter, N, F)) atomicAdd(a.flag, 1);
+  double Np[L::Q], U[D], rho;
+  for (int i = 0; i < D; ++i) F[i] = 0;
+  const CollideOut o = collide<L, double, double, 0, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
+  if (o.iters > a.max_iter) atomicAdd(a.flag, 1);
+  for (int al = 0; al < L::Q; ++al) a.rown[al * nc + cell] = S(Np[al]);
+}
+
+// ... and, gathered along the links, the reference of each arriving link (rsrc).
+template <class L, class S>
+__global__ __launch_bounds__(kBlock) void k_refs_src(StateArgs<S> a) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= a.box.ncells) return;
+  const long nc = a.box.ncells;
+  int x, y, z;
+  cell_xyz(a.box, cell, x, y, z);
+  S* rsrc = const_cast<S*>(a.rsrc);
+  for (int al = 0; al < L::Q; ++al) {
+    int src;
+    const int kind = link_source<L>(a.box, al, x, y, z, src);
+    const int dir = kind == LINK_INTERIOR ? al : opp(al);
+    rsrc[al * nc + cell] = a.rown[dir * nc + src];
+  }
 }
 
 // Output mapping: rho, u = Ut^i g_i (Euclidean), U^i (eq. (result) and the
@@ -342,6 +383,10 @@ StateArgs<S> make_args(SimObj* s) {
   a.max_iter = s->p.fp_max_iter;
   a.in = static_cast<const S*>(s->pop[s->buf]);
   a.out = static_cast<S*>(s->pop[s->buf]);
+  a.rsrc = static_cast<const S*>(s->rsrc);
+  a.rown = static_cast<S*>(s->rown);
+  a.scale = pop_scale(s->p.precision);
+  a.inv_scale = 1.0f / a.scale;
   a.flag = s->flags;
   a.fcache = s->fcache;
   a.fc64 = fcache_elem(s->p.precision) == 8;
@@ -374,6 +419,11 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
       a.N_in = N_in;
       k_set_pop<L, S><<<nb, kBlock, 0, st>>>(a);
       break;
+    case 5:
+      k_refs_own<L, S><<<nb, kBlock, 0, st>>>(a);
+      if (hipGetLastError() != hipSuccess) break;
+      k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
+      break;
     case 4: {
       a.u_prev = s->u_prev;
       a.have_prev = s->have_u_prev;
@@ -394,11 +444,20 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
 hipError_t dispatch_any(SimObj* s, int what, const double* r_in, const double* u_in, double* r_out, double* u_out,
                         double* U_out, double* N_out, const double* N_in, int slot) {
   const bool d2 = s->mesh->lattice == VLBM_D2Q9;
-  if (storage_is_fp64(s->p.precision))
-    return d2 ? dispatch<D2Q9, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
-              : dispatch<D3Q19, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
-  return d2 ? dispatch<D2Q9, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
-            : dispatch<D3Q19, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+  switch (s->p.precision) {
+    case VLBM_FP64:
+      return d2 ? dispatch<D2Q9, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
+                : dispatch<D3Q19, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    case VLBM_FP16S:
+      return d2 ? dispatch<D2Q9, __half>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
+                : dispatch<D3Q19, __half>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    case VLBM_BF16S:
+      return d2 ? dispatch<D2Q9, __hip_bfloat16>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
+                : dispatch<D3Q19, __hip_bfloat16>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    default:
+      return d2 ? dispatch<D2Q9, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
+                : dispatch<D3Q19, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+  }
 }
 
 }  // namespace
@@ -417,6 +476,9 @@ hipError_t launch_get_pop(SimObj* s, double* N) {
 }
 hipError_t launch_set_pop(SimObj* s, const double* N) {
   return dispatch_any(s, 3, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, N, 0);
+}
+hipError_t launch_refs(SimObj* s) {
+  return dispatch_any(s, 5, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 hipError_t launch_audit(SimObj* s, int slot) {
   return dispatch_any(s, 4, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, slot);
