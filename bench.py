@@ -1,11 +1,17 @@
 """Benchmark: D3Q19 FP32 fused stream-collide-force update on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload channel|ogrid] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload channel|ogrid|batch]
+                    [--precision fp32|fp32c|fp64|fp16s|bf16s] [--no-cpu]
 
 Prints ONE JSON line: MLUPS of the whole job (inputs resident in HBM), the
 roofline of the fused step kernel (algorithmic bytes per launch / average
 launch duration from HIP events on the stream the kernel runs on), and the FP64
 CPU oracle timed on a bounded sample of the same workload.
+
+--workload batch times the 256-mesh uneven D2Q9 batch instead: one persistent
+launch per step replayed from captured graphs, with the launch shape chosen by
+the library's autotuner, beside the same batch stepped by one launch per mesh
+(plain and graph-captured).
 """
 import argparse
 import json
@@ -19,11 +25,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_per_cell(Q, d, storage_bytes, has_force):
-    """Populations read + written once (2 Q s) plus the packed per-cell geometry
-    the kernel must read: J, g^{ij} (upper), A^i_a (a >= 1), a_ext."""
-    words = 1 + d * (d + 1) // 2 + (Q - 1) * d + (d if has_force else 0)
-    return 2 * Q * storage_bytes + words * storage_bytes
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp32c": 4, "fp16s": 2, "bf16s": 2}
+
+
+def algorithmic_bytes_per_cell(Q, d, precision, has_force, has_farfield=False):
+    """Bytes one step must move per cell: the Q populations read once and
+    written once, the packed per-cell geometry words (J, g^{ij} upper, A^i_a for
+    a >= 1, a_ext when a body force acts, U_inf when there is a far field; FP64
+    words for FP64 storage, FP32 otherwise), and for the 16-bit storage modes
+    the two 16-bit reference states (the cell's own and its link sources')."""
+    sb = STORAGE_BYTES[precision]
+    gb = 8 if precision == "fp64" else 4
+    words = 1 + d * (d + 1) // 2 + (Q - 1) * d + (d if has_force else 0) + (d if has_farfield else 0)
+    refs = 2 * Q * 2 if sb == 2 else 0
+    return 2 * Q * sb + words * gb + refs
 
 
 def make_workload(name):
@@ -35,55 +50,74 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(seconds_target=12.0):
-    """The FP64 NumPy oracle, single BLAS thread, on a 32x32x16 replica of the
-    stretched channel (same strength and tau); steps until ~seconds_target."""
+def cpu_baseline(workload="channel", seconds_target=12.0):
+    """The FP64 NumPy oracle, one BLAS thread, on a bounded replica of the
+    workload (same lattice, stretching, tau and boundaries, fewer cells), stepped
+    until ~seconds_target; MLUPS = cell updates / wall time."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import geometry, lattice, sim
     from paper_2401_17183_amd import workloads as W
 
-    w = W.tanh_channel_3d(32, 32, 16)
-    lat = lattice.by_name(w["lattice"])
+    if workload == "batch":
+        ws = W.batch_meshes(256)[:4]
+        label = "first 4 meshes of the 256-mesh D2Q9 bump batch"
+    elif workload == "ogrid":
+        ws = [W.ogrid_3d(32, 64, 8)]
+        label = "D3Q19 O-grid 32x64x8"
+    else:
+        ws = [W.tanh_channel_3d(32, 32, 16)]
+        label = "D3Q19 tanh(2.5) channel 32x32x16"
     with threadpool_limits(limits=1):
-        m = geometry.Mesh(lat, w["n"], w["coords"], w["faces"], w["wrap"], w["dx"])
-        s = sim.Sim(m, sim.Params(w["tau"], body_force=w["body_force"]))
-        s.init(w["rho"], w["u"])
-        s.step(1)
+        sims = []
+        for w in ws:
+            lat = lattice.by_name(w["lattice"])
+            m = geometry.Mesh(lat, w["n"], w["coords"], w["faces"], w["wrap"], w["dx"])
+            s = sim.Sim(m, sim.Params(w["tau"], body_force=w.get("body_force", (0, 0, 0)),
+                                      rho_inf=w.get("rho_inf", 1.0), u_inf=w.get("u_inf", (0, 0, 0))))
+            s.init(w.get("rho"), w.get("u"))
+            s.step(1)
+            sims.append(s)
+        cells = sum(int(np.prod(w["n"])) for w in ws)
         t0 = time.perf_counter()
         steps = 0
         while time.perf_counter() - t0 < seconds_target:
-            s.step(1)
+            for s in sims:
+                s.step(1)
             steps += 1
         dt = time.perf_counter() - t0
-    cells = int(np.prod(w["n"]))
-    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"D3Q19 tanh(2.5) channel 32x32x16 FP64, {steps} steps, {dt:.1f} s, 1 thread"}
+    return {"value": round(cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{label}, FP64, {steps} steps, {dt:.1f} s, 1 thread"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="channel")
-    ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-ref", action="store_true",
-                    help="after timing, run one plain 1 GiB device copy (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("this build runs on one GPU only: --gpus must be 1 (the multi-GPU slab "
-              "decomposition is a design, not code)", file=sys.stderr)
-        sys.exit(2)
+def _event_pair(torch, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    return e0, e1
 
-    import numpy as np
-    import torch
 
-    from paper_2401_17183_amd import vlbm
+def _timed(torch, stream, fn, steps):
+    """Milliseconds of `fn(steps)` between HIP events recorded on `stream`."""
+    e0, e1 = _event_pair(torch, stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
 
-    torch.cuda.set_device(0)
+
+def _copy_ref(torch, out):
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["config"]["copy_ref_bytes"] = 2 * src.numel() * 4
+
+
+def run_single(args, torch, vlbm):
     w = make_workload(args.workload)
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
     mesh = vlbm.Mesh.from_workload(w)
@@ -97,52 +131,114 @@ def main():
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()   # the Sim launches on torch's current stream
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms = _timed(torch, stream, sim.step, args.steps)
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
     mlups = cells * args.steps / (ms / 1e3) / 1e6
-    sb = {"fp64": 8, "fp32": 4, "fp32c": 4, "fp16s": 2, "bf16s": 2}[args.precision]
     has_force = any(v != 0 for v in w.get("body_force", (0, 0, 0)))
-    bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, sb, has_force)
+    has_ff = any(f == vlbm.FARFIELD for face in w["faces"] for f in face)
+    bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, args.precision, has_force, has_ff)
     achieved = bpc * cells / (ms_per_step / 1e3) / 1e9
     mo = sim.moments()
     finite = bool(torch.isfinite(mo["u"]).all().item())
-    out = {
-        "metric": "MLUPS + % HBM roofline (D3Q19 FP32); warm vs cold time-to-1e-6 residual",
+    return {
+        "metric": METRIC,
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
-        # the arithmetic type: the fp32 storage mode computes in FP64 registers
-        "vs_baseline": None, "dtype": {"fp32": "f64", "fp32c": "f32", "fp64": "f64", "fp16s": "f32",
-                                       "bf16s": "f32"}[args.precision],
+        "vs_baseline": None, "dtype": ARITH[args.precision],
         "data": "synthetic",
         "config": {"workload": w["name"] + f" {args.precision.upper()}", "cells": cells, "lattice": w["lattice"],
-                   "tau": w["tau"], "storage": {"fp32": "f32", "fp32c": "f32", "fp64": "f64", "fp16s": "f16",
-                                                "bf16s": "bf16"}[args.precision],
+                   "tau": w["tau"], "storage": STORAGE[args.precision],
                    "wall_s": round(wall, 3), "finite": finite},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_cell": bpc, "kernel": "k_step"},
     }
+
+
+def run_batch(args, torch, vlbm):
+    from paper_2401_17183_amd import workloads as W
+    ws = W.batch_meshes(256)
+    print("[bench] building 256 bump-channel meshes", file=sys.stderr, flush=True)
+    meshes = [vlbm.Mesh.from_workload(w) for w in ws]
+    params = [vlbm.make_params(w["tau"], body_force=w["body_force"], precision=args.precision) for w in ws]
+    b = vlbm.Batch(meshes, params)
+    cells = b.info()["cells"]
+    stream = torch.cuda.ExternalStream(b.info()["stream"])
+    print("[bench] autotune", file=sys.stderr, flush=True)
+    block, gpc = b.autotune(trial_steps=10, cache_path=args.tune_cache)
+    modes = {}
+    for name, mode, steps in (("persistent_graph", vlbm.BATCH_PERSISTENT_GRAPH, args.steps),
+                              ("persistent", vlbm.BATCH_PERSISTENT, max(32, args.steps // 4)),
+                              ("eager_per_mesh", vlbm.BATCH_EAGER, max(32, args.steps // 10)),
+                              ("graph_per_mesh", vlbm.BATCH_EAGER_GRAPH, max(32, args.steps // 10))):
+        b.set_mode(mode)
+        print(f"[bench] {name}: warmup {args.warmup + 32}, timing {steps} steps", file=sys.stderr, flush=True)
+        b.step(args.warmup + 32)   # includes the graph capture
+        b.sync()
+        ms = _timed(torch, stream, b.step, steps)
+        b.sync()
+        modes[name] = {"steps": steps, "ms_per_step": round(ms / steps, 5),
+                       "MLUPS": round(cells * steps / (ms / 1e3) / 1e6, 1)}
+    b.set_mode(vlbm.BATCH_PERSISTENT_GRAPH)
+    main = modes["persistent_graph"]
+    bpc = algorithmic_bytes_per_cell(9, 2, args.precision, True)
+    achieved = bpc * cells / (main["ms_per_step"] / 1e3) / 1e9
+    finite = all(bool(torch.isfinite(m.moments()["u"]).all().item()) for m in b.members[:8])
+    out = {
+        "metric": METRIC,
+        "value": main["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": main["steps"], "warmup": args.warmup,
+        "ms_per_step": main["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": ARITH[args.precision], "data": "synthetic",
+        "config": {"workload": f"256 uneven D2Q9 bump channels {args.precision.upper()}, one persistent launch "
+                               "per step, graph-replayed", "cells": cells, "meshes": 256,
+                   "storage": STORAGE[args.precision], "block": block, "grid_per_cu": gpc, "modes": modes,
+                   "finite": finite},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell": bpc, "kernel": "k_batch"},
+    }
+    b.close()
+    return out
+
+
+METRIC = "MLUPS + % HBM roofline (D3Q19 FP32); warm vs cold time-to-1e-6 residual"
+# the arithmetic type of each storage mode: fp32 storage computes in FP64 registers
+ARITH = {"fp32": "f64", "fp32c": "f32", "fp64": "f64", "fp16s": "f32", "bf16s": "f32"}
+STORAGE = {"fp32": "f32", "fp32c": "f32", "fp64": "f64", "fp16s": "f16", "bf16s": "bf16"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch"])
+    ap.add_argument("--precision", default="fp32", choices=sorted(STORAGE_BYTES))
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file for --workload batch")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="after timing, run one plain 1 GiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only: --gpus must be 1 (the multi-GPU slab "
+              "decomposition is a design, not code)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2401_17183_amd import vlbm
+
+    torch.cuda.set_device(0)
+    out = run_batch(args, torch, vlbm) if args.workload == "batch" else run_single(args, torch, vlbm)
     if args.copy_ref:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["config"]["copy_ref_bytes"] = 2 * src.numel() * 4
+        _copy_ref(torch, out)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 

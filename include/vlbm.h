@@ -191,11 +191,58 @@ int vlbm_save(vlbm_sim s, void* buf, size_t cap, size_t* used);
  * same precision.  Errors: VLBM_ERR_ARG on a size or header mismatch. */
 int vlbm_restore(vlbm_sim s, const void* buf, size_t size);
 
+/* Re-initialise an existing simulation in place (same mesh, params, stream)
+ * with the initial state of vlbm_init from rho / u (device, nullable); resets
+ * the step counter.  Synchronises.  Used to warm-start a solve from predicted
+ * fields. */
+int vlbm_reinit(vlbm_sim s, const double* rho, const double* u);
+
 /* Steps taken since init (host int64 out). */
 int vlbm_sim_step_count(vlbm_sim s, int64_t* t);
 
 int vlbm_sim_destroy(vlbm_sim s);
 int vlbm_mesh_destroy(vlbm_mesh m);
+
+/* ----------------------------------------------------------------------------
+ * Batches: many independent meshes advanced together (growth form of the
+ * method's data-parallel step over cells to a data-parallel step over meshes).
+ * Every member is an ordinary simulation (vlbm_batch_member returns a
+ * borrowed handle; vlbm_moments, vlbm_populations, vlbm_audit_now,
+ * vlbm_reinit work on it); all members share the lattice, the precision
+ * (FP64, FP32 or FP32C) and the batch's stream.
+ * Modes of vlbm_batch_step:
+ *   PERSISTENT_GRAPH  one launch per step of a persistent kernel whose blocks
+ *                     stride over a table of (mesh, tile) work items of all
+ *                     members, captured in a hipGraph per 32 steps (default);
+ *   PERSISTENT        the same launches without the graph;
+ *   EAGER             one launch per member per step;
+ *   EAGER_GRAPH       a hipGraph of the per-member launches.
+ * -------------------------------------------------------------------------- */
+typedef struct vlbm_batch_s* vlbm_batch;
+enum { VLBM_BATCH_PERSISTENT_GRAPH = 0, VLBM_BATCH_PERSISTENT = 1, VLBM_BATCH_EAGER = 2, VLBM_BATCH_EAGER_GRAPH = 3 };
+
+/* meshes: host array of count precomputed meshes; params: host array of count
+ * parameter sets (tau may differ per member); stream: a hipStream_t that is
+ * not the null stream, or NULL for a stream the batch creates and owns.
+ * Members start from rho = 1, u = 0 (use vlbm_reinit on a member to change). */
+int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int count, void* stream,
+                      vlbm_batch* out);
+int vlbm_batch_member(vlbm_batch b, int i, vlbm_sim* out);
+/* Host outs (each nullable): member count, total cells, the batch stream, and
+ * the launch shape (threads per block, blocks per CU; 0 = one block per tile). */
+int vlbm_batch_info(vlbm_batch b, int* count, int64_t* cells, void** stream, int* block, int* grid_per_cu);
+int vlbm_batch_set_mode(vlbm_batch b, int mode);
+/* block in {64, 128, 256}; grid_per_cu >= 0. */
+int vlbm_batch_config(vlbm_batch b, int block, int grid_per_cu);
+/* Asynchronous on the batch stream. */
+int vlbm_batch_step(vlbm_batch b, int64_t nsteps);
+/* Synchronise; VLBM_ERR_NOCONVERGE if any member's fixed point hit its cap. */
+int vlbm_batch_sync(vlbm_batch b);
+/* Time each launch shape for trial_steps steps (the state is restored
+ * afterwards), keep the fastest, and append it to the text cache at
+ * cache_path (nullable; a cached entry for the same key is reused). */
+int vlbm_batch_autotune(vlbm_batch b, int trial_steps, const char* cache_path, int* block, int* grid_per_cu);
+int vlbm_batch_destroy(vlbm_batch b);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* vlbm_last_error(void);

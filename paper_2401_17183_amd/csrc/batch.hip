@@ -1,0 +1,160 @@
+// Batched time stepping of many independent meshes: one launch advances every
+// member mesh by one step.  The work list is a table of (mesh, first cell)
+// tiles of BLOCK cells over all members, largest meshes first; a persistent
+// grid of blocks strides over it.  The kernel boundary is the only barrier
+// between steps (no cross-workgroup waiting), and n steps replay a captured
+// hipGraph of such launches.  The launch shape (BLOCK, blocks per CU) is
+// chosen by a small measured search, cached in a text file.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "batch.hpp"
+#include "stepcore.hpp"
+
+namespace vlbm {
+
+namespace {
+
+template <class L, class P, class S, class T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_batch(const StepArgs<P, S, T>* __restrict__ args,
+                                                                const Tile* __restrict__ tiles, int ntiles,
+                                                                int parity) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    const StepArgs<P, S, T> a = args[2 * tl.mesh + parity];
+    step_cell<L, P, S, T, BLOCK>(a, tl.first + threadIdx.x);
+  }
+}
+
+}  // namespace
+
+namespace {
+
+template <class P, class S, class T>
+hipError_t upload_args(BatchObj* b) {
+  std::vector<StepArgs<P, S, T>> h(2 * b->members.size());
+  for (size_t m = 0; m < b->members.size(); ++m) {
+    SimObj* s = b->members[m];
+    const int buf = s->buf;
+    for (int par = 0; par < 2; ++par) {
+      s->buf = par;
+      h[2 * m + par] = make_step_args<P, S, T>(s);
+    }
+    s->buf = buf;
+  }
+  if (!b->d_args) {
+    hipError_t e = hipMalloc(&b->d_args, sizeof(StepArgs<P, S, T>) * h.size());
+    if (e != hipSuccess) return e;
+  }
+  return hipMemcpy(b->d_args, h.data(), sizeof(StepArgs<P, S, T>) * h.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t build_tiles(BatchObj* b) {
+  std::vector<int> order(b->members.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->members[x]->mesh->box.ncells > b->members[y]->mesh->box.ncells;
+  });
+  std::vector<Tile> tiles;
+  for (int m : order) {
+    const int nc = b->members[m]->mesh->box.ncells;
+    for (int c = 0; c < nc; c += b->block) tiles.push_back(Tile{m, c});
+  }
+  b->ntiles = (int)tiles.size();
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  hipError_t e = hipMalloc((void**)&b->d_tiles, sizeof(Tile) * tiles.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(b->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
+}
+
+template <class L, class P, class S, class T, int BLOCK>
+hipError_t launch_batch_typed(BatchObj* b, int parity) {
+  const int grid = b->grid_per_cu > 0 ? std::min(b->ntiles, b->grid_per_cu * b->cus) : b->ntiles;
+  k_batch<L, P, S, T, BLOCK><<<grid, BLOCK, 0, b->stream>>>(static_cast<const StepArgs<P, S, T>*>(b->d_args),
+                                                            b->d_tiles, b->ntiles, parity);
+  return hipGetLastError();
+}
+
+template <class L, class P, class S, class T>
+hipError_t launch_batch_block(BatchObj* b, int parity) {
+  switch (b->block) {
+    case 64: return launch_batch_typed<L, P, S, T, 64>(b, parity);
+    case 128: return launch_batch_typed<L, P, S, T, 128>(b, parity);
+    default: return launch_batch_typed<L, P, S, T, 256>(b, parity);
+  }
+}
+
+template <class L>
+hipError_t launch_batch_lattice(BatchObj* b, int parity) {
+  switch (b->precision) {
+    case VLBM_FP64: return launch_batch_block<L, double, double, double>(b, parity);
+    case VLBM_FP32: return launch_batch_block<L, float, float, double>(b, parity);
+    default: return launch_batch_block<L, float, float, float>(b, parity);
+  }
+}
+
+template <class L>
+hipError_t upload_lattice(BatchObj* b) {
+  switch (b->precision) {
+    case VLBM_FP64: return upload_args<double, double, double>(b);
+    case VLBM_FP32: return upload_args<float, float, double>(b);
+    default: return upload_args<float, float, float>(b);
+  }
+}
+
+}  // namespace
+
+hipError_t batch_launch(BatchObj* b, int parity) {
+  return b->lattice == VLBM_D2Q9 ? launch_batch_lattice<D2Q9>(b, parity) : launch_batch_lattice<D3Q19>(b, parity);
+}
+
+hipError_t batch_upload(BatchObj* b) {
+  hipError_t e = b->lattice == VLBM_D2Q9 ? upload_lattice<D2Q9>(b) : upload_lattice<D3Q19>(b);
+  if (e != hipSuccess) return e;
+  return build_tiles(b);
+}
+
+void batch_drop_graphs(BatchObj* b) {
+  for (int p = 0; p < 2; ++p)
+    if (b->exec[p]) {
+      (void)hipGraphExecDestroy(b->exec[p]);
+      b->exec[p] = nullptr;
+    }
+}
+
+// Capture graph_steps consecutive steps (parities alternate) starting at parity p.
+hipError_t batch_capture(BatchObj* b, int p, bool per_member) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k) {
+    const int par = (p + k) & 1;
+    if (!per_member) {
+      le = batch_launch(b, par);
+    } else {
+      for (SimObj* s : b->members) {
+        const int keep = s->buf;
+        s->buf = par;
+        le = launch_step(s);
+        s->buf = keep;
+        if (le != hipSuccess) break;
+      }
+    }
+  }
+  e = hipStreamEndCapture(b->stream, &g);
+  if (le != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return le;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(&b->exec[p], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+}  // namespace vlbm

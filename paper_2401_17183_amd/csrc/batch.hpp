@@ -1,0 +1,36 @@
+// Host-side batch object shared by batch.hip and the C API.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace vlbm {
+
+struct Tile {
+  int mesh;
+  int first;
+};
+
+struct BatchObj {
+  std::vector<SimObj*> members;
+  int lattice = 0, precision = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* d_args = nullptr;      // StepArgs [count][2 parities]
+  Tile* d_tiles = nullptr;
+  int ntiles = 0;
+  int block = 256, grid_per_cu = 4, cus = 256;
+  int mode = 0;                // VLBM_BATCH_*
+  hipGraphExec_t exec[2] = {nullptr, nullptr};   // per starting parity
+  int graph_steps = 32;
+  int64_t t = 0;
+  int64_t total_cells = 0;
+};
+
+hipError_t batch_launch(BatchObj* b, int parity);
+hipError_t batch_upload(BatchObj* b);
+hipError_t batch_capture(BatchObj* b, int p, bool per_member);
+void batch_drop_graphs(BatchObj* b);
+
+}  // namespace vlbm

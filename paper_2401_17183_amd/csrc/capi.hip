@@ -14,6 +14,11 @@ int audit_partial_blocks(const MeshObj* m);
 int audit_words();
 }  // namespace vlbm
 
+#include "batch.hpp"
+
+#include <string>
+#include <vector>
+
 using namespace vlbm;
 
 namespace {
@@ -255,8 +260,11 @@ int vlbm_sim_destroy(vlbm_sim sh) {
   return ok();
 }
 
-int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const double* u, void* stream, vlbm_sim* out) {
-  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+
+}  // extern "C"
+
+static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const double* u, hipStream_t stream,
+                      SimObj** out) {
   if (!m || !p || !out) return fail(VLBM_ERR_ARG, "vlbm_init: null argument");
   *out = nullptr;
   if (!m->have_geometry) return fail(VLBM_ERR_STATE, "vlbm_init before vlbm_geometry_precompute");
@@ -272,7 +280,7 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   if (s->p.fp_tol < 0)
     s->p.fp_tol = s->p.precision == VLBM_FP64 ? 1e-14 : (s->p.precision == VLBM_FP32 ? 1e-10 : 1e-7);
   // (FP16S / BF16S use FP32 arithmetic, like FP32C)
-  s->stream = static_cast<hipStream_t>(stream);
+  s->stream = stream;
   const int d = m->d;
   for (int k = 0; k < d; ++k)
     if (p->body_force[k] != 0.0) s->has_force = 1;
@@ -323,7 +331,37 @@ int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const doubl
   (void)hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream);
   s->buf = 0;
   s->t = 0;
+  *out = s;
+  return ok();
+}
+
+extern "C" {
+
+int vlbm_init(vlbm_mesh mh, const vlbm_params* p, const double* rho, const double* u, void* stream, vlbm_sim* out) {
+  if (!out) return fail(VLBM_ERR_ARG, "vlbm_init: null argument");
+  SimObj* s = nullptr;
+  const int rc = create_sim(reinterpret_cast<MeshObj*>(mh), p, rho, u, static_cast<hipStream_t>(stream), &s);
   *out = reinterpret_cast<vlbm_sim>(s);
+  return rc;
+}
+
+int vlbm_reinit(vlbm_sim sh, const double* rho, const double* u) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  const size_t nc = s->mesh->box.ncells;
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream));
+  HIP_TRY(hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream));
+  HIP_TRY(hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream));
+  s->buf = 0;
+  HIP_TRY(launch_init(s, rho, u, s->flags));
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  (void)nc;
+  if (hflag) return fail(VLBM_ERR_NOCONVERGE, "initial-state fixed point did not converge in %d cells", hflag);
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream));
+  s->t = 0;
+  s->have_u_prev = 0;
   return ok();
 }
 
@@ -445,6 +483,292 @@ int vlbm_sim_step_count(vlbm_sim sh, int64_t* t) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s || !t) return fail(VLBM_ERR_ARG, "null argument");
   *t = s->t;
+  return ok();
+}
+
+
+/* ---------------------------- batches of meshes ---------------------------- */
+
+static int batch_cus() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus > 0 ? cus : 256;
+}
+
+int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int count, void* stream, vlbm_batch* out) {
+  if (!meshes || !params || !out || count <= 0) return fail(VLBM_ERR_ARG, "vlbm_batch_create: bad argument");
+  *out = nullptr;
+  const int lat = reinterpret_cast<MeshObj*>(meshes[0])->lattice;
+  const int prec = params[0].precision;
+  if (prec != VLBM_FP64 && prec != VLBM_FP32 && prec != VLBM_FP32C)
+    return fail(VLBM_ERR_UNSUPPORTED, "batches are built for FP64, FP32 and FP32C");
+  BatchObj* b = new (std::nothrow) BatchObj();
+  if (!b) return fail(VLBM_ERR_NOMEM, "host allocation failed");
+  b->lattice = lat;
+  b->precision = prec;
+  b->cus = batch_cus();
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return fail(VLBM_ERR_DEVICE, "stream creation failed");
+  } else {
+    b->own_stream = true;
+  }
+  auto bail = [&](int rc) {
+    vlbm_batch_destroy(reinterpret_cast<vlbm_batch>(b));
+    return rc;
+  };
+  for (int i = 0; i < count; ++i) {
+    MeshObj* m = reinterpret_cast<MeshObj*>(meshes[i]);
+    if (!m || m->lattice != lat || params[i].precision != prec) {
+      fail(VLBM_ERR_ARG, "member %d: every member needs the same lattice and precision", i);
+      return bail(VLBM_ERR_ARG);
+    }
+    SimObj* s = nullptr;
+    const int rc = create_sim(m, &params[i], nullptr, nullptr, b->stream, &s);
+    if (rc) return bail(rc);
+    b->members.push_back(s);
+    b->total_cells += m->box.ncells;
+  }
+  if (batch_upload(b) != hipSuccess) {
+    fail(VLBM_ERR_DEVICE, "batch upload failed");
+    return bail(VLBM_ERR_DEVICE);
+  }
+  *out = reinterpret_cast<vlbm_batch>(b);
+  return ok();
+}
+
+int vlbm_batch_destroy(vlbm_batch bh) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b) return VLBM_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_drop_graphs(b);
+  for (SimObj* s : b->members) free_sim(s);
+  dev_free(b->d_args);
+  dev_free(b->d_tiles);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return VLBM_OK;
+}
+
+int vlbm_batch_member(vlbm_batch bh, int i, vlbm_sim* out) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b || !out || i < 0 || i >= (int)b->members.size()) return fail(VLBM_ERR_ARG, "vlbm_batch_member: bad argument");
+  *out = reinterpret_cast<vlbm_sim>(b->members[i]);
+  return ok();
+}
+
+int vlbm_batch_info(vlbm_batch bh, int* count, int64_t* cells, void** stream, int* block, int* grid_per_cu) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b) return fail(VLBM_ERR_ARG, "null batch");
+  if (count) *count = (int)b->members.size();
+  if (cells) *cells = b->total_cells;
+  if (stream) *stream = b->stream;
+  if (block) *block = b->block;
+  if (grid_per_cu) *grid_per_cu = b->grid_per_cu;
+  return ok();
+}
+
+int vlbm_batch_set_mode(vlbm_batch bh, int mode) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b || mode < 0 || mode > 3) return fail(VLBM_ERR_ARG, "vlbm_batch_set_mode: bad argument");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  batch_drop_graphs(b);
+  b->mode = mode;
+  return ok();
+}
+
+int vlbm_batch_config(vlbm_batch bh, int block, int grid_per_cu) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b || (block != 64 && block != 128 && block != 256) || grid_per_cu < 0)
+    return fail(VLBM_ERR_ARG, "vlbm_batch_config: block must be 64, 128 or 256 and grid_per_cu >= 0");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  batch_drop_graphs(b);
+  const bool rebuild = block != b->block;
+  b->block = block;
+  b->grid_per_cu = grid_per_cu;
+  if (rebuild && batch_upload(b) != hipSuccess) return fail(VLBM_ERR_DEVICE, "batch upload failed");
+  return ok();
+}
+
+static int batch_one_step_eager(BatchObj* b, int parity, bool per_member) {
+  if (!per_member) {
+    HIP_TRY(batch_launch(b, parity));
+  } else {
+    for (SimObj* s : b->members) HIP_TRY(launch_step(s));
+  }
+  return VLBM_OK;
+}
+
+static void batch_advance(BatchObj* b, int64_t k) {
+  for (SimObj* s : b->members) {
+    s->t += k;
+    if (k & 1) s->buf ^= 1;
+  }
+  b->t += k;
+}
+
+int vlbm_batch_step(vlbm_batch bh, int64_t nsteps) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b || nsteps < 0) return fail(VLBM_ERR_ARG, "vlbm_batch_step: bad argument");
+  for (SimObj* s : b->members)
+    if (s->buf != b->members[0]->buf || s->t != b->members[0]->t)
+      return fail(VLBM_ERR_STATE, "batch members were stepped individually; they must share one step count");
+  const bool per_member = b->mode >= VLBM_BATCH_EAGER;
+  const bool graphs = b->mode == VLBM_BATCH_PERSISTENT_GRAPH || b->mode == VLBM_BATCH_EAGER_GRAPH;
+  int64_t done = 0;
+  if (graphs) {
+    while (nsteps - done >= b->graph_steps) {
+      const int par = b->members[0]->buf;
+      if (!b->exec[par]) {
+        hipError_t e = batch_capture(b, par, per_member);
+        if (e != hipSuccess) return fail(VLBM_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+      }
+      HIP_TRY(hipGraphLaunch(b->exec[par], b->stream));
+      batch_advance(b, b->graph_steps);
+      done += b->graph_steps;
+    }
+  }
+  for (; done < nsteps; ++done) {
+    const int rc = batch_one_step_eager(b, b->members[0]->buf, per_member);
+    if (rc) return rc;
+    batch_advance(b, 1);
+  }
+  return ok();
+}
+
+int vlbm_batch_sync(vlbm_batch bh) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b) return fail(VLBM_ERR_ARG, "null batch");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int unconv = 0;
+  for (SimObj* s : b->members) {
+    int h = 0;
+    HIP_TRY(hipMemcpy(&h, s->flags, sizeof(int), hipMemcpyDeviceToHost));
+    unconv += h;
+  }
+  if (unconv) return fail(VLBM_ERR_NOCONVERGE, "fixed point hit its cap in %d cell-steps", unconv);
+  return ok();
+}
+
+// Measured search over the launch shape of the batched kernel.  The state is
+// snapshotted and restored, so tuning leaves the simulation where it was.
+int vlbm_batch_autotune(vlbm_batch bh, int trial_steps, const char* cache_path, int* block_out, int* grid_out) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b || trial_steps <= 0) return fail(VLBM_ERR_ARG, "vlbm_batch_autotune: bad argument");
+  char key[256];
+  snprintf(key, sizeof(key), "gfx950 lattice=%d precision=%d cells=%lld meshes=%d", b->lattice, b->precision,
+           (long long)b->total_cells, (int)b->members.size());
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof(line), f)) {
+        int bl = 0, gp = 0;
+        char* sep = strstr(line, " | ");
+        if (sep && (size_t)(sep - line) == strlen(key) && strncmp(line, key, strlen(key)) == 0 &&
+            sscanf(sep + 3, "block=%d grid_per_cu=%d", &bl, &gp) == 2) {
+          fclose(f);
+          const int rc = vlbm_batch_config(bh, bl, gp);
+          if (block_out) *block_out = bl;
+          if (grid_out) *grid_out = gp;
+          return rc;
+        }
+      }
+      fclose(f);
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  // Snapshot every member's state (populations of the current parity, force
+  // cache, step count); the trials below advance the members.
+  struct Snap {
+    void* mem;
+    int buf;
+    int64_t t;
+  };
+  std::vector<Snap> snap;
+  auto fc_bytes = [](const SimObj* s) {
+    return s->fcache ? (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision) : (size_t)0;
+  };
+  auto drop = [&]() {
+    for (Snap& x : snap) dev_free(x.mem);
+    snap.clear();
+  };
+  for (SimObj* s : b->members) {
+    void* p = nullptr;
+    const size_t fb = fc_bytes(s);
+    if (dev_alloc((char**)&p, s->pop_bytes + fb)) {
+      drop();
+      return VLBM_ERR_NOMEM;
+    }
+    snap.push_back(Snap{p, s->buf, s->t});
+    hipError_t e = hipMemcpyAsync(p, s->pop[s->buf], s->pop_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && fb)
+      e = hipMemcpyAsync(static_cast<char*>(p) + s->pop_bytes, s->fcache, fb, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) {
+      drop();
+      return fail(VLBM_ERR_DEVICE, "autotune snapshot: %s", hipGetErrorString(e));
+    }
+  }
+  const int keep_mode = b->mode;
+  b->mode = VLBM_BATCH_PERSISTENT;
+  const int blocks[3] = {64, 128, 256};
+  const int grids[5] = {1, 2, 4, 8, 0};
+  float best = 1e30f;
+  int bb = b->block, bg = b->grid_per_cu;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = VLBM_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(VLBM_ERR_DEVICE, "autotune: event creation failed");
+  for (int bl : blocks)
+    for (int gp : grids) {
+      if (rc) break;
+      rc = vlbm_batch_config(bh, bl, gp);
+      if (!rc) rc = vlbm_batch_step(bh, 2);
+      if (!rc && hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(VLBM_ERR_DEVICE, "autotune: event");
+      if (!rc) rc = vlbm_batch_step(bh, trial_steps);
+      float ms = 0;
+      if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(VLBM_ERR_DEVICE, "autotune: timing");
+      if (!rc && ms < best) {
+        best = ms;
+        bb = bl;
+        bg = gp;
+      }
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  // restore the snapshot whatever happened in the trials
+  (void)hipStreamSynchronize(b->stream);
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    SimObj* s = b->members[i];
+    const size_t fb = fc_bytes(s);
+    s->buf = snap[i].buf;
+    s->t = snap[i].t;
+    hipError_t e = hipMemcpyAsync(s->pop[s->buf], snap[i].mem, s->pop_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && fb)
+      e = hipMemcpyAsync(s->fcache, static_cast<char*>(snap[i].mem) + s->pop_bytes, fb, hipMemcpyDeviceToDevice,
+                         b->stream);
+    if (e != hipSuccess && !rc) rc = fail(VLBM_ERR_DEVICE, "autotune restore: %s", hipGetErrorString(e));
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = fail(VLBM_ERR_DEVICE, "autotune restore");
+  drop();
+  b->t = b->members.empty() ? 0 : b->members[0]->t;
+  b->mode = keep_mode;
+  if (rc) return rc;
+  rc = vlbm_batch_config(bh, bb, bg);
+  if (rc) return rc;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s | block=%d grid_per_cu=%d ms_per_step=%.6f\n", key, bb, bg, best / trial_steps);
+      fclose(f);
+    }
+  }
+  if (block_out) *block_out = bb;
+  if (grid_out) *grid_out = bg;
   return ok();
 }
 

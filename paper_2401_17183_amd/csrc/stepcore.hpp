@@ -1,0 +1,185 @@
+// Core of the fused time step shared by the single-mesh and the batched
+// kernels: pull advection (eq. (adv)) + BGK collision with the implicit
+// inertial force (eqs. (lbe), (collide), (compo-constr), (delta-flux),
+// (deltaN), (equilibrium)), one thread per cell, SoA populations.
+#pragma once
+
+#include <type_traits>
+
+#include "dynamics.hpp"
+
+namespace vlbm {
+
+// Two resident waves per SIMD: the LDS staging of A (55 KB per 256-thread
+// block for D3Q19 FP32) allows two blocks per CU, and the register budget is
+// held to that occupancy.
+#ifndef VLBM_STEP_ATTR
+#define VLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 8)))
+#endif
+
+// P: population storage type; S: geometry storage type; T: arithmetic type.
+template <class P, class S, class T> struct StepArgs {
+  Box box;
+  const P* __restrict__ in;
+  P* __restrict__ out;
+  const P* __restrict__ rsrc;   // 16-bit modes: reference of each arriving link
+  const P* __restrict__ rown;   // 16-bit modes: reference of each written slot
+  float scale, inv_scale;
+  const S* __restrict__ geo;
+  T tau, tol, rho_inf;
+  int max_iter, min_iter;
+  int stream_only;
+  int has_force, has_ff;
+  T* __restrict__ fcache;       // [D][cells] starting guess in, converged F out
+  int* flags;
+};
+
+// Word w of a SoA array: the wave-uniform base (w * nc) is formed in scalar
+// registers, lanes carry only their 32-bit cell offset.
+template <class X>
+__device__ __forceinline__ const X* word(const X* __restrict__ base, int w, int nc) {
+  return base + (size_t)w * (size_t)nc;
+}
+template <class X>
+__device__ __forceinline__ X* word(X* __restrict__ base, int w, int nc) {
+  return base + (size_t)w * (size_t)nc;
+}
+
+// Packed geometry of one cell.  With ST > 0 the link coefficients are staged
+// in LDS (this thread's column of lds, stride ST) instead of registers; only
+// this thread reads its column.
+template <class L, class S, class T, int ST>
+__device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ geo, int nc, int cell, int has_force,
+                                                          S* lds) {
+  CellGeo<L, T, S, ST> g;
+  g.J = word(geo, Pack<L>::J, nc)[cell];
+#pragma unroll
+  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = word(geo, Pack<L>::GUP + k, nc)[cell];
+#pragma unroll
+  for (int a = 1; a < L::Q; ++a)
+#pragma unroll
+    for (int i = 0; i < L::D; ++i) {
+      const S v = word(geo, Pack<L>::A + (a - 1) * L::D + i, nc)[cell];
+      if constexpr (ST == 0) g.Areg[a][i] = v;
+      else lds[((a - 1) * L::D + i) * ST] = v;
+    }
+  if constexpr (ST == 0)
+#pragma unroll
+    for (int i = 0; i < L::D; ++i) g.Areg[0][i] = S(0);
+  g.lds = lds;
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? word(geo, Pack<L>::AEXT + i, nc)[cell] : S(0);
+  return g;
+}
+
+// Pull N_a(q) = N'_a(q - c_a) (eq. (adv)).  Every load is unconditional and in
+// bounds (a bounced or far-field link reads the cell's own opposite slot), so
+// no lane diverges; far-field links then take J f^eq(rho_inf, U_inf, U_inf).
+template <class L, class P, class S, class T, class NR, int ST>
+__device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo<L, T, S, ST>& g, int x, int y,
+                                       int z, int cell, NR* N) {
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  using C = PopCodec<P>;
+  const int nc = a.box.ncells;
+  unsigned ff = 0;
+#pragma unroll
+  for (int al = 0; al < Q; ++al) {
+    int src;
+    const int kind = link_source<L>(a.box, al, x, y, z, src);
+    const int dir = kind == LINK_INTERIOR ? al : opp(al);
+    const P h = word(a.in, 0, nc)[(size_t)dir * nc + src];
+    if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rsrc, al, nc)[cell], a.inv_scale);
+    else N[al] = h;
+    ff |= (kind == LINK_FARFIELD ? 1u : 0u) << al;
+  }
+  if (a.has_ff) {   // wave-uniform
+    T Uinf[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) Uinf[i] = T(word(a.geo, Pack<L>::UINF + i, nc)[cell]);
+    T fe[Q];
+    feq_farfield<L, T>(g, a.rho_inf, Uinf, fe);
+#pragma unroll
+    for (int al = 0; al < Q; ++al) N[al] = (ff >> al) & 1u ? NR(g.j() * fe[al]) : N[al];
+  }
+}
+
+template <class L, class P, class S, class T, class V>
+__device__ __forceinline__ void store_slot(const StepArgs<P, S, T>& a, int al, int cell, V v) {
+  using C = PopCodec<P>;
+  const int nc = a.box.ncells;
+  if constexpr (C::shifted) word(a.out, al, nc)[cell] = C::template encode<T>(T(v), word(a.rown, al, nc)[cell], a.scale);
+  else word(a.out, al, nc)[cell] = P(v);
+}
+
+// One cell of one mesh; BLOCK threads per workgroup share the LDS staging.
+template <class L, class P, class S, class T, int BLOCK>
+__device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) {
+  constexpr int Q = L::Q;
+  constexpr int D = L::D;
+  // registers hold populations in the storage type, or FP32 for 16-bit storage
+  using NR = typename std::conditional<PopCodec<P>::shifted, float, P>::type;
+  if (cell >= a.box.ncells) return;
+  const int nc = a.box.ncells;
+  const int x = cell % a.box.n[0];
+  const int r = cell / a.box.n[0];
+  const int y = r % a.box.n[1];
+  const int z = r / a.box.n[1];
+  // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19)
+  constexpr int ST = sizeof(S) == 4 ? BLOCK : 0;
+  __shared__ S sA[ST ? (Q - 1) * D * BLOCK : 1];
+  NR N[Q];
+  const CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
+  gather<L, P, S, T, NR, ST>(a, g, x, y, z, cell, N);
+  if (a.stream_only) {
+#pragma unroll
+    for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, N[al]);
+    return;
+  }
+  T F[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) F[i] = word(a.fcache, i, nc)[cell];
+  CollState<L, T> st;
+  collide_prepare<L, T, S, ST, NR>(g, N, a.tau, st);
+  collide_iterate<L, T, S, ST>(g, a.tau, a.tol, a.max_iter, F, st, a.min_iter);
+  if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
+#pragma unroll
+  for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
+  // gather again (cache hits) rather than keeping N live across the fixed point
+  int xr = x;
+  pin(xr);
+  gather<L, P, S, T, NR, ST>(a, g, xr, y, z, cell, N);
+  T Np[Q];
+  collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
+#pragma unroll
+  for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, Np[al]);
+}
+
+// Kernel arguments of one simulation's step (current buffer parity).
+template <class P, class S, class T>
+inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
+  StepArgs<P, S, T> a;
+  a.box = s->mesh->box;
+  a.in = static_cast<const P*>(s->pop[s->buf]);
+  a.out = static_cast<P*>(s->pop[s->buf ^ 1]);
+  a.rsrc = static_cast<const P*>(s->rsrc);
+  a.rown = static_cast<const P*>(s->rown);
+  a.scale = pop_scale(s->p.precision);
+  a.inv_scale = 1.0f / a.scale;
+  a.geo = static_cast<const S*>(s->geo);
+  a.tau = T(s->p.tau);
+  a.tol = T(s->p.fp_tol);
+  a.rho_inf = T(s->p.rho_inf);
+  a.max_iter = s->p.fp_max_iter;
+  // FP32 arithmetic cannot resolve a warm-started first update below its own
+  // roundoff: take at least two iterations there.
+  a.min_iter = sizeof(T) == 4 ? 2 : 1;
+  a.stream_only = s->p.stream_only;
+  a.has_force = s->has_force;
+  a.has_ff = s->has_farfield;
+  a.flags = s->flags;
+  a.fcache = static_cast<T*>(s->fcache);
+  return a;
+}
+
+}  // namespace vlbm

@@ -27,6 +27,7 @@ FP64, FP32, FP16S, BF16S, FP32C = 0, 1, 2, 3, 4
 PERIODIC, WALL, FARFIELD = 0, 1, 2
 OK, ERR_ARG, ERR_MESH, ERR_NOMEM, ERR_DEVICE, ERR_NOCONVERGE, ERR_STATE, ERR_NONFINITE, ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
+BATCH_PERSISTENT_GRAPH, BATCH_PERSISTENT, BATCH_EAGER, BATCH_EAGER_GRAPH = 0, 1, 2, 3
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S, "bf16s": BF16S, "fp32c": FP32C}
 
@@ -90,6 +91,17 @@ _SIGS = {
     "vlbm_restore": (C.c_int, [_P, _P, C.c_size_t]),
     "vlbm_sim_step_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "vlbm_sim_destroy": (C.c_int, [_P]),
+    "vlbm_reinit": (C.c_int, [_P, _P, _P]),
+    "vlbm_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(vlbm_params), C.c_int, _P, C.POINTER(_P)]),
+    "vlbm_batch_member": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
+    "vlbm_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(_P),
+                                  C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "vlbm_batch_set_mode": (C.c_int, [_P, C.c_int]),
+    "vlbm_batch_config": (C.c_int, [_P, C.c_int, C.c_int]),
+    "vlbm_batch_step": (C.c_int, [_P, C.c_int64]),
+    "vlbm_batch_sync": (C.c_int, [_P]),
+    "vlbm_batch_autotune": (C.c_int, [_P, C.c_int, C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "vlbm_batch_destroy": (C.c_int, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -148,6 +160,13 @@ def _dev(torch, a, shape=None):
     if shape is not None:
         t = t.reshape(shape)
     return t.to("cuda").contiguous()
+
+
+def _ready(torch):
+    """Finish torch's pending work on its current stream: buffers allocated or
+    filled there are then safe to hand to a library call on another stream
+    (batch members run on the batch's own stream)."""
+    torch.cuda.current_stream().synchronize()
 
 
 class Mesh:
@@ -258,6 +277,7 @@ class Sim:
         rho = torch.empty(nc, dtype=torch.float64, device="cuda")
         u = torch.empty(d * nc, dtype=torch.float64, device="cuda")
         U = torch.empty(d * nc, dtype=torch.float64, device="cuda") if with_U else None
+        _ready(torch)
         vlbm_moments(self.h, _P(rho.data_ptr()), _P(u.data_ptr()), _P(U.data_ptr()) if U is not None else None)
         out = {"rho": rho, "u": u.reshape(d, nc)}
         if U is not None:
@@ -268,16 +288,26 @@ class Sim:
         torch = _torch()
         Q, nc = self.mesh.Q, self.mesh.ncells
         N = torch.empty(Q * nc, dtype=torch.float64, device="cuda")
+        _ready(torch)
         vlbm_populations(self.h, _P(N.data_ptr()))
         return N.reshape(Q, nc)
 
     def set_populations(self, N):
         torch = _torch()
         t = _dev(torch, N, (self.mesh.Q * self.mesh.ncells,))
+        _ready(torch)
         vlbm_set_populations(self.h, _P(t.data_ptr()))
 
     def audit_now(self):
         vlbm_audit_now(self.h)
+
+    def reinit(self, rho=None, u=None):
+        torch = _torch()
+        nc, d = self.mesh.ncells, self.mesh.d
+        r = _dev(torch, rho, (nc,)) if rho is not None else None
+        v = _dev(torch, u, (d, nc)) if u is not None else None
+        _ready(torch)
+        vlbm_reinit(self.h, _P(r.data_ptr()) if r is not None else None, _P(v.data_ptr()) if v is not None else None)
 
     def audits(self, cap=4096, allow_nonfinite=True):
         buf = (vlbm_audit * cap)()
@@ -299,6 +329,75 @@ class Sim:
     def close(self):
         if getattr(self, "h", None):
             vlbm_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Member(Sim):
+    """A borrowed member of a Batch (the batch owns and frees it)."""
+
+    def __init__(self, mesh, params, h):
+        self.mesh = mesh
+        self.params = params
+        self.h = h
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Many meshes advanced together (one persistent launch per step)."""
+
+    def __init__(self, meshes, params, stream=None):
+        _torch()
+        n = len(meshes)
+        hs = (_P * n)(*[m.h for m in meshes])
+        ps = (vlbm_params * n)(*params)
+        h = _P()
+        vlbm_batch_create(hs, ps, n, _P(stream) if stream else None, C.byref(h))
+        self.h = h
+        self.meshes = list(meshes)
+        self.params = list(params)
+        self.members = []
+        for i in range(n):
+            mh = _P()
+            vlbm_batch_member(self.h, i, C.byref(mh))
+            self.members.append(_Member(meshes[i], params[i], mh))
+
+    def info(self):
+        cnt, cells, st, bl, gp = C.c_int(), C.c_int64(), _P(), C.c_int(), C.c_int()
+        vlbm_batch_info(self.h, C.byref(cnt), C.byref(cells), C.byref(st), C.byref(bl), C.byref(gp))
+        return {"count": cnt.value, "cells": cells.value, "stream": st.value, "block": bl.value,
+                "grid_per_cu": gp.value}
+
+    def set_mode(self, mode):
+        vlbm_batch_set_mode(self.h, int(mode))
+
+    def config(self, block, grid_per_cu):
+        vlbm_batch_config(self.h, int(block), int(grid_per_cu))
+
+    def step(self, n=1):
+        vlbm_batch_step(self.h, int(n))
+
+    def sync(self):
+        vlbm_batch_sync(self.h)
+
+    def autotune(self, trial_steps=20, cache_path=None):
+        bl, gp = C.c_int(), C.c_int()
+        vlbm_batch_autotune(self.h, int(trial_steps), cache_path.encode() if cache_path else None,
+                            C.byref(bl), C.byref(gp))
+        return bl.value, gp.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            for m in self.members:
+                m.h = None
+            vlbm_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -124,21 +124,28 @@ def _stretch01(eta, s):
     return 0.5 * (1.0 + np.tanh(sig * (2.0 * eta - 1.0)) / np.tanh(sig))
 
 
-def bump_channel_2d(n1, n2, bump, stretch, tau, G=1e-6, H=1.0):
+def bump_channel_2d(n1, n2, bump, stretch, tau, G=1e-6, H=1.0, max_slope=0.15):
     """Periodic-x channel with a lower wall bump y_b = bump * sin^8(pi x / L)
     and a flat upper wall at H; wall-normal tanh clustering of ratio ~stretch.
-    dx = sqrt(3) * smallest central wall-normal spacing of the flat section;
-    L = n1 * dx."""
+
+    dx = sqrt(2) * the smallest wall-normal spacing anywhere (the bump crest
+    squeezes the first cell by (H - bump) / H), streamwise spacing dx, L = n1 dx.
+    The bump height is capped so that the steepest wall slope,
+    (8 pi / L) * bump * max(sin^7 cos) = 5.59 bump / L, stays at most max_slope:
+    skewed, squeezed cells otherwise leave the window of metrics for which the
+    rest populations stay positive."""
     eta = (np.arange(-NGHOST, n2 + NGHOST) + 0.5) / n2
     prof = _stretch01(eta, stretch)
-    dx = np.sqrt(3.0) * _central_min(prof * H)
+    hmin = _central_min(prof * H)
+    peak = 8.0 * np.pi * (7.0 / 8.0) ** 3.5 * np.sqrt(1.0 / 8.0)
+    bump = min(bump, max_slope * n1 * np.sqrt(2.0) * hmin * (1.0 - bump / H) / peak)
+    dx = np.sqrt(2.0) * hmin * (1.0 - bump / H)
     L = n1 * dx
     x = np.arange(n1) * dx
     yb = bump * np.sin(np.pi * x / L) ** 8
     X = np.empty((len(eta), n1, 2))
     X[..., 0] = x[None, :]
     X[..., 1] = yb[None, :] + (H - yb[None, :]) * prof[:, None]
-    # the tangent vectors need smallest spacing over the bumped section too
     return {
         "name": f"D2Q9 bump channel {n1}x{n2}",
         "lattice": "D2Q9", "n": (n1, n2), "coords": X,
@@ -150,8 +157,9 @@ def bump_channel_2d(n1, n2, bump, stretch, tau, G=1e-6, H=1.0):
 
 
 def batch_meshes(count=256, seed=SEED):
-    """The uneven batch: n1 ~ U{32..256}, n2 ~ U{16..128}, bump ~ U[0, 0.3] H,
-    stretch ~ U[1, 3], tau ~ U[0.55, 1.0]."""
+    """The uneven batch: n1 ~ U{32..256}, n2 ~ U{16..128}, bump ~ U[0, 0.3] H
+    (then capped by the wall-slope limit of bump_channel_2d), stretch ~ U[1, 3],
+    tau ~ U[0.55, 1.0]."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
