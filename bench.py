@@ -166,6 +166,9 @@ def run_batch(args, torch, vlbm):
     meshes = [vlbm.Mesh.from_workload(w) for w in ws]
     params = [vlbm.make_params(w["tau"], body_force=w["body_force"], precision=args.precision) for w in ws]
     b = vlbm.Batch(meshes, params)
+    for w, m in zip(ws, b.members):
+        rho, u = W.channel_vortex_fields(w)
+        m.reinit(rho=rho.ravel(), u=u.reshape(2, -1))
     cells = b.info()["cells"]
     stream = torch.cuda.ExternalStream(b.info()["stream"])
     print("[bench] autotune", file=sys.stderr, flush=True)

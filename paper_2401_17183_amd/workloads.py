@@ -172,6 +172,20 @@ def batch_meshes(count=256, seed=SEED):
     return out
 
 
+def channel_vortex_fields(w, amp=0.02):
+    """A smooth initial state for a 2D channel member: rho = 1 and, with
+    xi = (q^1 + 1/2) / n_1, eta = (q^2 + 1/2) / n_2,
+    u_x = amp sin(pi eta) (1 + 0.3 sin(2 pi xi)), u_y = (amp / 2) sin(2 pi eta) cos(2 pi xi).
+    Returns rho (n_2, n_1) and u (2, n_2, n_1)."""
+    n1, n2 = w["n"]
+    xi = (np.arange(n1) + 0.5) / n1
+    eta = (np.arange(n2) + 0.5) / n2
+    u = np.empty((2, n2, n1))
+    u[0] = amp * np.sin(np.pi * eta)[:, None] * (1.0 + 0.3 * np.sin(2 * np.pi * xi))[None, :]
+    u[1] = 0.5 * amp * np.sin(2 * np.pi * eta)[:, None] * np.cos(2 * np.pi * xi)[None, :]
+    return np.ones((n2, n1)), u
+
+
 def surrogate_meshes(count, seed=SEED, n1=128, n2=64, tau=0.8):
     """Bump channels at n1 x n2 with bump ~ U[0, 0.3] H, stretch ~ U[1, 3],
     Re ~ U[10, 100]; G = 12 nu^2 Re / H^3 (flat-channel bulk velocity relation

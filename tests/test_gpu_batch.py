@@ -182,14 +182,21 @@ def test_reinit_matches_fresh_init():
 @pytest.mark.timeout(600)
 def test_full_batch_sampled_parity_fp32():
     """The 256-mesh uneven batch (2.87 M cells) in FP32 storage, one persistent
-    launch per step, 100 steps; 8 seeded members against the FP64 oracle:
-    velocity relative L2 <= 1e-5 (the FP32-storage bound)."""
+    launch per step, 100 steps from a smooth 0.02-amplitude vortex state; 8
+    seeded members against the FP64 oracle: velocity relative L2 <= 1e-5 (the
+    FP32-storage bound).  At rest-start velocities of ~1e-4 the same absolute
+    error, set by the FP32 rounding of populations of size ~w, is ~1e-4 relative,
+    so the bound is stated at a flow amplitude typical of LBM runs."""
     v = _vlbm()
     ws = W.batch_meshes(256)
     announce("full batch: meshes")
     b, _ = _batch(ws, "fp32")
     assert b.info()["count"] == 256
     assert b.info()["cells"] == sum(int(np.prod(w["n"])) for w in ws)
+    announce("full batch: initial fields")
+    for w, m in zip(ws, b.members):
+        rho, u = W.channel_vortex_fields(w)
+        m.reinit(rho=rho.ravel(), u=u.reshape(2, -1))
     announce("full batch: 100 steps")
     b.step(100)
     b.sync()
@@ -198,10 +205,11 @@ def test_full_batch_sampled_parity_fp32():
         w = ws[k]
         announce(f"full batch: oracle member {k} {w['n']}")
         o = sim_of(w)
-        o.init(None, None)
+        o.init(*W.channel_vortex_fields(w))
         o.step(100)
         uo = o.moments()["u"].reshape(2, -1)
         ug = b.members[k].moments()["u"].cpu().numpy()
         rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+        print(f"member {k} {w['n']} velocity rel L2 {rel:.3e}")
         assert rel <= 1e-5, (k, w["n"], rel)
     b.close()
