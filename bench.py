@@ -91,6 +91,33 @@ def cpu_baseline(workload="channel", seconds_target=12.0):
             "sample": f"{label}, FP64, {steps} steps, {dt:.1f} s, 1 thread"}
 
 
+STEP_SOURCES = ["paper_2401_17183_amd/csrc/common.hpp", "paper_2401_17183_amd/csrc/dynamics.hpp",
+                "paper_2401_17183_amd/csrc/stepcore.hpp", "paper_2401_17183_amd/csrc/step.hip"]
+
+
+def profiled_traffic(profile, sources):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None when
+    there is no summary or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if " = " in line:
+                k, v = line.split(" = ", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def _event_pair(torch, stream):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -144,6 +171,9 @@ def run_single(args, torch, vlbm):
     achieved = bpc * cells / (ms_per_step / 1e3) / 1e9
     mo = sim.moments()
     finite = bool(torch.isfinite(mo["u"]).all().item())
+    traffic = None
+    if args.workload == "channel" and args.precision in ("fp32", "fp32c"):
+        traffic = profiled_traffic(f"k_step_d3q19_channel_256x128x128_{args.precision}.md", STEP_SOURCES)
     return {
         "metric": METRIC,
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -154,7 +184,10 @@ def run_single(args, torch, vlbm):
                    "tau": w["tau"], "storage": STORAGE[args.precision],
                    "wall_s": round(wall, 3), "finite": finite},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": bpc * cells,
                      "bytes_per_cell": bpc, "kernel": "k_step"},
     }
 
