@@ -243,6 +243,89 @@ int vlbm_batch_sync(vlbm_batch b);
  * cache_path (nullable; a cached entry for the same key is reused). */
 int vlbm_batch_autotune(vlbm_batch b, int trial_steps, const char* cache_path, int* block, int* grid_per_cu);
 int vlbm_batch_destroy(vlbm_batch b);
+/* Audit every member now (as vlbm_audit_now) and write each member's
+ * steady-state residual r = ||u - u_prev||_2 / ||u||_2 (u = output velocity,
+ * u_prev = that of the member's previous audit; NaN at a member's first audit)
+ * to residual[count] (host).  Synchronises the batch stream. */
+int vlbm_batch_residuals(vlbm_batch b, double* residual);
+
+/* ---- Learned warm start: a convolutional surrogate on BF16 MFMA ----------
+ *
+ * Not part of the paper: a small network that maps a mesh (node coordinates)
+ * and a Reynolds number to an approximate steady state, used only as the
+ * initial state of a solve that the method then finishes (vlbm_reinit).
+ *
+ * Tensors are NHWC.  BF16 tensors are passed as raw 16-bit words (uint16_t,
+ * the upper half of an IEEE single); FP32 and BF16 pointers are device
+ * pointers; weights are [c_out][3][3][c_in + c_skip] and the transposed copy
+ * used for input gradients [c_in + c_skip][3][3][c_out].  Calls are
+ * asynchronous on `stream` unless stated otherwise.  Channel counts must be
+ * multiples of 8 (VLBM_ERR_ARG otherwise). */
+typedef struct vlbm_conv_desc {
+  int batch, height, width; /* full-resolution input of the convolution */
+  int c_in;                 /* channels of the primary input */
+  int c_skip;               /* channels of a skip input (height x width) appended after them, or 0 */
+  int upsample;             /* 1: the primary input is stored at height/2 x width/2 and read through a
+                               nearest-neighbour 2x upsampling (stride must be 1) */
+  int stride;               /* 1 or 2; zero padding 1, output ceil(height/stride) x ceil(width/stride) */
+  int c_out, relu;
+} vlbm_conv_desc;
+
+/* y = relu?(conv3x3(x ++ skip, w) + bias), written as BF16 (y_bf16) and/or FP32
+ * (y_f32); either output may be NULL, not both; bias may be NULL. */
+int vlbm_conv2d_forward(const vlbm_conv_desc* d, const uint16_t* x, const uint16_t* skip, const uint16_t* w,
+                        const float* bias, uint16_t* y_bf16, float* y_f32, void* stream);
+/* Input gradients of sum(gy * conv3x3(...)) given gy (BF16, the gradient with
+ * respect to the pre-activation output) and the transposed weights:
+ * gx += d/dx (at the stored resolution of x, i.e. summed over each 2x2 block
+ * when upsampled) and gskip += d/dskip; FP32, either may be NULL. */
+int vlbm_conv2d_backward_data(const vlbm_conv_desc* d, const uint16_t* gy, const uint16_t* wt, float* gx,
+                              float* gskip, void* stream);
+/* gw += d/dw, gb += d/dbias (FP32, accumulated with atomics). */
+int vlbm_conv2d_backward_weight(const vlbm_conv_desc* d, const uint16_t* x, const uint16_t* skip,
+                                const uint16_t* gy, float* gw, float* gb, void* stream);
+/* BF16 copies (round to nearest even) of FP32 weights w: w_bf16 in the same
+ * layout and wt_bf16 transposed. */
+int vlbm_conv2d_pack_weights(const vlbm_conv_desc* d, const float* w, uint16_t* w_bf16, uint16_t* wt_bf16,
+                             void* stream);
+
+typedef struct vlbm_adam {
+  double lr, beta1, beta2, eps;
+} vlbm_adam;
+/* One Adam update (Kingma and Ba) of n FP32 parameters p with gradient g and
+ * moments m, v at step >= 1 (bias-corrected). */
+int vlbm_adam_step(float* p, const float* g, float* m, float* v, int64_t n, const vlbm_adam* hp, int64_t step,
+                   void* stream);
+
+/* The network: 5 levels with 32, 64, 128, 256, 256 channels; two 3x3 convs
+ * with ReLU per level, stride-2 convs down, nearest 2x upsampling up with the
+ * encoder output of each level appended (skip), a 3x3 head.  Input
+ * [batch][height][width][3] FP32 features, output [batch][height][width][3]
+ * FP32; height and width multiples of 16.  The parameter vector holds, layer
+ * by layer (encoder levels 0..4, decoder levels 3..0, head), the FP32 weights
+ * [c_out][3][3][c_in + c_skip] and the bias [c_out]; the first layer has 8
+ * input channels (features 3..7 are zero) and the head 16 outputs (only the
+ * first 3 are trained). */
+typedef struct vlbm_surrogate_s* vlbm_surrogate;
+int vlbm_surrogate_param_count(int height, int width, int64_t* n);
+/* params: device or host FP32 vector of param_count values (copied).  The
+ * object owns all its device memory; max_batch bounds the batch of later calls. */
+int vlbm_surrogate_create(int height, int width, int max_batch, const float* params, void* stream,
+                          vlbm_surrogate* out);
+int vlbm_surrogate_forward(vlbm_surrogate s, const float* x, int batch, float* y);
+/* Forward + mean squared error over the 3 outputs + backward.  loss (host,
+ * nullable; synchronises when given), grad (device, nullable) receives the
+ * gradient with respect to the parameter vector. */
+int vlbm_surrogate_gradient(vlbm_surrogate s, const float* x, const float* target, int batch, double* loss,
+                            float* grad);
+/* Adam update with the last gradient (step count kept by the object). */
+int vlbm_surrogate_adam(vlbm_surrogate s, const vlbm_adam* hp);
+/* gradient + adam. */
+int vlbm_surrogate_train_step(vlbm_surrogate s, const float* x, const float* target, int batch,
+                              const vlbm_adam* hp, double* loss);
+/* Copy the FP32 parameter vector out (synchronises); step (nullable) = Adam steps taken. */
+int vlbm_surrogate_params(vlbm_surrogate s, float* out, int64_t* step);
+int vlbm_surrogate_destroy(vlbm_surrogate s);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* vlbm_last_error(void);

@@ -87,6 +87,17 @@ def relu(z):
     return np.maximum(z, 0.0)
 
 
+def round_bf16(a):
+    """Round to the nearest bfloat16 value (ties to even), returned as float64:
+    round to float32 first, then keep the upper 16 bits of the IEEE single after
+    adding half an ulp of the kept part (plus one when the kept part is odd).
+    NaN and infinity are not expected here."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def mse(y, t):
     """Mean of (y - t)^2 over the first TARGET_CHANNELS channels of y (t holds
     exactly those); returns the loss and its gradient with respect to y."""
@@ -146,9 +157,15 @@ class Surrogate:
         self.layers = unpack(self.params)
         self.table = layer_table()
 
-    def forward(self, x):
+    def forward(self, x, q=None):
         """x: (N, H, W, IN_CHANNELS), H and W divisible by 16.  Returns the
-        (N, H, W, OUT_CHANNELS) output and keeps what backward needs."""
+        (N, H, W, OUT_CHANNELS) output and keeps what backward needs.
+
+        q (optional) is applied to every stored activation of the hidden layers
+        (not the head output) -- with q = round_bf16 this models a network that
+        keeps its activations in bfloat16 between layers."""
+        self._q = q if q is not None else (lambda a: a)
+        qf = self._q
         acts = {}
         inputs = []
         h = x
@@ -160,7 +177,7 @@ class Surrogate:
                 w, b = self.layers[k]
                 inputs.append(h)
                 z = conv3x3(h, w, b, s)
-                h = relu(z) if r else z
+                h = qf(relu(z) if r else z)
                 acts[name] = h
                 k += 1
             enc.append(h)
@@ -169,13 +186,13 @@ class Surrogate:
             w, b = self.layers[k]
             xin = np.concatenate([upsample2(h), enc[lvl]], axis=-1)
             inputs.append(xin)
-            h = relu(conv3x3(xin, w, b, s))
+            h = qf(relu(conv3x3(xin, w, b, s)))
             acts[name] = h
             k += 1
             name, ci, cs, up, s, co, r = self.table[k]
             w, b = self.layers[k]
             inputs.append(h)
-            h = relu(conv3x3(h, w, b, s))
+            h = qf(relu(conv3x3(h, w, b, s)))
             acts[name] = h
             k += 1
         name, ci, cs, up, s, co, r = self.table[k]
@@ -187,9 +204,11 @@ class Surrogate:
 
     def backward(self, gy):
         """Gradient of sum(gy * forward(x)) with respect to the flat parameters
-        (same order as the parameter vector)."""
+        (same order as the parameter vector).  The q given to forward is also
+        applied to the gradient entering each layer (after the ReLU mask)."""
+        qf = self._q
         grads = [None] * len(self.table)
-        g = gy
+        g = qf(gy)
         genc = [None] * 5
         k = len(self.table) - 1
         # head
@@ -202,14 +221,14 @@ class Surrogate:
         for lvl in (0, 1, 2, 3):
             name, ci, cs, up, s, co, r = self.table[k]
             assert name == f"dec{lvl}b"
-            g = g * (self._acts[name] > 0)
+            g = qf(g * (self._acts[name] > 0))
             gx, gw, gb = conv3x3_backward(self._inputs[k], self.layers[k][0], g, s)
             grads[k] = (gw, gb)
             g = gx
             k -= 1
             name, ci, cs, up, s, co, r = self.table[k]
             assert name == f"dec{lvl}a"
-            g = g * (self._acts[name] > 0)
+            g = qf(g * (self._acts[name] > 0))
             gx, gw, gb = conv3x3_backward(self._inputs[k], self.layers[k][0], g, s)
             grads[k] = (gw, gb)
             genc[lvl] = gx[..., ci:]
@@ -222,7 +241,7 @@ class Surrogate:
             for part in ("b", "a"):
                 name, ci, cs, up, s, co, r = self.table[k]
                 assert name == f"enc{lvl}{part}"
-                g = g * (self._acts[name] > 0)
+                g = qf(g * (self._acts[name] > 0))
                 gx, gw, gb = conv3x3_backward(self._inputs[k], self.layers[k][0], g, s)
                 grads[k] = (gw, gb)
                 g = gx

@@ -30,6 +30,11 @@ __global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_batch(const StepArgs<P
   }
 }
 
+__global__ void k_gather(const double* const* __restrict__ src, double* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = *src[i];
+}
+
 }  // namespace
 
 namespace {
@@ -116,6 +121,12 @@ hipError_t batch_upload(BatchObj* b) {
   hipError_t e = b->lattice == VLBM_D2Q9 ? upload_lattice<D2Q9>(b) : upload_lattice<D3Q19>(b);
   if (e != hipSuccess) return e;
   return build_tiles(b);
+}
+
+hipError_t batch_gather(BatchObj* b, const double* const* src, double* dst, int n) {
+  if (n <= 0) return hipSuccess;
+  k_gather<<<(n + 255) / 256, 256, 0, b->stream>>>(src, dst, n);
+  return hipGetLastError();
 }
 
 void batch_drop_graphs(BatchObj* b) {

@@ -26,11 +26,15 @@ struct BatchObj {
   int graph_steps = 32;
   int64_t t = 0;
   int64_t total_cells = 0;
+  const double** d_rsrc = nullptr;   // per member: address of its latest audit's residual
+  double* d_resid = nullptr;         // gathered residuals [count]
 };
 
 hipError_t batch_launch(BatchObj* b, int parity);
 hipError_t batch_upload(BatchObj* b);
 hipError_t batch_capture(BatchObj* b, int p, bool per_member);
 void batch_drop_graphs(BatchObj* b);
+// dst[i] = *src[i] for i < n, on the batch stream
+hipError_t batch_gather(BatchObj* b, const double* const* src, double* dst, int n);
 
 }  // namespace vlbm

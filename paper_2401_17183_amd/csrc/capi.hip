@@ -38,6 +38,22 @@ int ok() {
   return VLBM_OK;
 }
 
+}  // namespace
+
+namespace vlbm {
+// Error reporting shared with the other translation units of the C ABI:
+// records the message in the thread-local error string and returns `code`.
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+}  // namespace vlbm
+
+namespace {
+
 #define HIP_TRY(expr)                                                                          \
   do {                                                                                          \
     hipError_t _e = (expr);                                                                     \
@@ -547,9 +563,35 @@ int vlbm_batch_destroy(vlbm_batch bh) {
   for (SimObj* s : b->members) free_sim(s);
   dev_free(b->d_args);
   dev_free(b->d_tiles);
+  dev_free(b->d_rsrc);
+  dev_free(b->d_resid);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return VLBM_OK;
+}
+
+int vlbm_batch_residuals(vlbm_batch bh, double* residual) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b || !residual) return fail(VLBM_ERR_ARG, "vlbm_batch_residuals: null argument");
+  const int n = (int)b->members.size();
+  if (!b->d_rsrc) {
+    if (dev_alloc(&b->d_rsrc, sizeof(double*) * n) || dev_alloc(&b->d_resid, sizeof(double) * n))
+      return VLBM_ERR_NOMEM;
+  }
+  std::vector<const double*> src(n);
+  for (int i = 0; i < n; ++i) {
+    SimObj* s = b->members[i];
+    const int slot = (int)(s->audit_head % s->audit_cap);
+    HIP_TRY(launch_audit(s, slot));
+    s->audit_head++;
+    if (s->audit_head - s->audit_tail > s->audit_cap) s->audit_tail = s->audit_head - s->audit_cap;
+    src[i] = &static_cast<const vlbm_audit*>(s->audit_ring)[slot].residual;
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_rsrc, src.data(), sizeof(double*) * n, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(batch_gather(b, b->d_rsrc, b->d_resid, n));
+  HIP_TRY(hipMemcpyAsync(residual, b->d_resid, sizeof(double) * n, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return ok();
 }
 
 int vlbm_batch_member(vlbm_batch bh, int i, vlbm_sim* out) {

@@ -70,6 +70,16 @@ class vlbm_audit(C.Structure):
         return out
 
 
+class vlbm_conv_desc(C.Structure):
+    _fields_ = [("batch", C.c_int), ("height", C.c_int), ("width", C.c_int), ("c_in", C.c_int),
+                ("c_skip", C.c_int), ("upsample", C.c_int), ("stride", C.c_int), ("c_out", C.c_int),
+                ("relu", C.c_int)]
+
+
+class vlbm_adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "vlbm_last_error": (C.c_char_p, []),
@@ -102,6 +112,20 @@ _SIGS = {
     "vlbm_batch_sync": (C.c_int, [_P]),
     "vlbm_batch_autotune": (C.c_int, [_P, C.c_int, C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "vlbm_batch_destroy": (C.c_int, [_P]),
+    "vlbm_batch_residuals": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "vlbm_conv2d_forward": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P, _P, _P, _P]),
+    "vlbm_conv2d_backward_data": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P, _P]),
+    "vlbm_conv2d_backward_weight": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P, _P, _P]),
+    "vlbm_conv2d_pack_weights": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P]),
+    "vlbm_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(vlbm_adam), C.c_int64, _P]),
+    "vlbm_surrogate_param_count": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int64)]),
+    "vlbm_surrogate_create": (C.c_int, [C.c_int, C.c_int, C.c_int, _P, _P, C.POINTER(_P)]),
+    "vlbm_surrogate_forward": (C.c_int, [_P, _P, C.c_int, _P]),
+    "vlbm_surrogate_gradient": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(C.c_double), _P]),
+    "vlbm_surrogate_adam": (C.c_int, [_P, C.POINTER(vlbm_adam)]),
+    "vlbm_surrogate_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(vlbm_adam), C.POINTER(C.c_double)]),
+    "vlbm_surrogate_params": (C.c_int, [_P, _P, C.POINTER(C.c_int64)]),
+    "vlbm_surrogate_destroy": (C.c_int, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -387,6 +411,13 @@ class Batch:
     def sync(self):
         vlbm_batch_sync(self.h)
 
+    def residuals(self):
+        """Audit every member now; numpy array of steady-state residuals
+        ||u - u_prev|| / ||u|| against each member's previous audit (NaN at the first)."""
+        out = (C.c_double * len(self.members))()
+        vlbm_batch_residuals(self.h, out)
+        return np.array(out[:])
+
     def autotune(self, trial_steps=20, cache_path=None):
         bl, gp = C.c_int(), C.c_int()
         vlbm_batch_autotune(self.h, int(trial_steps), cache_path.encode() if cache_path else None,
@@ -398,6 +429,124 @@ class Batch:
             for m in self.members:
                 m.h = None
             vlbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return None if t is None else _P(t.data_ptr())
+
+
+def conv_desc(batch, height, width, c_in, c_out, c_skip=0, upsample=False, stride=1, relu=True):
+    return vlbm_conv_desc(batch, height, width, c_in, c_skip, int(bool(upsample)), stride, c_out, int(bool(relu)))
+
+
+def _cur_stream():
+    return _stream_ptr(_torch())
+
+
+def conv2d_forward(d, x, skip, w, bias, y_bf16=None, y_f32=None):
+    """BF16 tensors as torch.bfloat16 (raw words), FP32 as torch.float32; async
+    on torch's current stream."""
+    vlbm_conv2d_forward(C.byref(d), _ptr(x), _ptr(skip), _ptr(w), _ptr(bias), _ptr(y_bf16), _ptr(y_f32),
+                        _cur_stream())
+
+
+def conv2d_backward_data(d, gy, wt, gx=None, gskip=None):
+    vlbm_conv2d_backward_data(C.byref(d), _ptr(gy), _ptr(wt), _ptr(gx), _ptr(gskip), _cur_stream())
+
+
+def conv2d_backward_weight(d, x, skip, gy, gw, gb):
+    vlbm_conv2d_backward_weight(C.byref(d), _ptr(x), _ptr(skip), _ptr(gy), _ptr(gw), _ptr(gb), _cur_stream())
+
+
+def conv2d_pack_weights(d, w, w_bf16, wt_bf16):
+    vlbm_conv2d_pack_weights(C.byref(d), _ptr(w), _ptr(w_bf16), _ptr(wt_bf16), _cur_stream())
+
+
+def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    hp = vlbm_adam(lr, beta1, beta2, eps)
+    vlbm_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), C.byref(hp), int(step), _cur_stream())
+
+
+def surrogate_param_count(height, width):
+    n = C.c_int64()
+    vlbm_surrogate_param_count(int(height), int(width), C.byref(n))
+    return n.value
+
+
+class Surrogate:
+    """The BF16-MFMA encoder-decoder (include/vlbm.h).  Inputs and outputs are
+    torch float32 device tensors [batch][height][width][3]; runs on torch's
+    current stream at creation."""
+
+    def __init__(self, height, width, max_batch, params):
+        torch = _torch()
+        self.height, self.width, self.max_batch = int(height), int(width), int(max_batch)
+        self.nparams = surrogate_param_count(height, width)
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1).to("cuda").contiguous()
+        if p.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {p.numel()}")
+        h = _P()
+        _ready(torch)
+        vlbm_surrogate_create(self.height, self.width, self.max_batch, _ptr(p), _stream_ptr(torch), C.byref(h))
+        self.h = h
+        torch.cuda.current_stream().synchronize()
+
+    def _in(self, x, channels=3):
+        torch = _torch()
+        t = torch.as_tensor(x, dtype=torch.float32).to("cuda").contiguous()
+        if t.dim() != 4 or tuple(t.shape[1:]) != (self.height, self.width, channels):
+            raise ValueError(f"expected [batch][{self.height}][{self.width}][{channels}], got {tuple(t.shape)}")
+        return t
+
+    def forward(self, x):
+        torch = _torch()
+        x = self._in(x)
+        y = torch.empty_like(x)
+        _ready(torch)
+        vlbm_surrogate_forward(self.h, _ptr(x), x.shape[0], _ptr(y))
+        return y
+
+    def gradient(self, x, target, with_grad=True):
+        torch = _torch()
+        x, t = self._in(x), self._in(target)
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda") if with_grad else None
+        loss = C.c_double()
+        _ready(torch)
+        vlbm_surrogate_gradient(self.h, _ptr(x), _ptr(t), x.shape[0], C.byref(loss), _ptr(g))
+        return loss.value, g
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        hp = vlbm_adam(lr, beta1, beta2, eps)
+        vlbm_surrogate_adam(self.h, C.byref(hp))
+
+    def train_step(self, x, target, lr, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=True):
+        torch = _torch()
+        x, t = self._in(x), self._in(target)
+        hp = vlbm_adam(lr, beta1, beta2, eps)
+        loss = C.c_double()
+        _ready(torch)
+        vlbm_surrogate_train_step(self.h, _ptr(x), _ptr(t), x.shape[0], C.byref(hp),
+                                  C.byref(loss) if want_loss else None)
+        return loss.value if want_loss else None
+
+    def params(self):
+        torch = _torch()
+        out = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        step = C.c_int64()
+        _ready(torch)
+        vlbm_surrogate_params(self.h, _ptr(out), C.byref(step))
+        return out, step.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            vlbm_surrogate_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,252 @@
+"""BF16-MFMA surrogate kernels (HIP, through the C-ABI) against the FP64 oracle.
+
+Inputs are rounded to BF16 first and the oracle computes in FP64 on exactly
+those values, so the only differences are FP32 accumulation (bounded by
+K * 2^-24 * sum |a b| for a K-term dot product in any order) and the final
+roundings the kernels state.  The whole network runs BF16 activations between
+layers, so it is held to a relative bound instead."""
+import numpy as np
+import pytest
+
+from oracle import nn as onn
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+
+
+def _vlbm():
+    from paper_2401_17183_amd import vlbm
+    return vlbm
+
+
+def announce(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def bf16(rng, *shape, scale=1.0):
+    """Seeded normal values rounded to BF16 (device tensor) and the same values in FP64."""
+    t = torch.tensor(scale * rng.standard_normal(shape), dtype=torch.float32).to(torch.bfloat16).cuda()
+    return t, t.float().double().cpu().numpy()
+
+
+CONVS = [  # (N, H, W, c_in, c_skip, up, stride, c_out, relu)
+    (2, 12, 20, 16, 0, False, 1, 32, True),
+    (2, 10, 14, 8, 0, False, 2, 16, True),
+    (1, 8, 12, 24, 16, True, 1, 40, True),
+    (3, 8, 8, 256, 0, False, 1, 64, False),
+    (2, 6, 10, 64, 0, False, 2, 72, True),
+]
+
+
+def _layer(cfg, seed):
+    N, H, W, ci, cs, up, s, co, relu = cfg
+    v = _vlbm()
+    rng = np.random.default_rng(seed)
+    hs, ws = (H // 2, W // 2) if up else (H, W)
+    x, xo = bf16(rng, N, hs, ws, ci)
+    sk, sko = bf16(rng, N, H, W, cs) if cs else (None, None)
+    w32 = torch.tensor(rng.standard_normal((co, 3, 3, ci + cs)) / np.sqrt(9 * (ci + cs)), dtype=torch.float32).cuda()
+    b = torch.tensor(0.1 * rng.standard_normal(co), dtype=torch.float32).cuda()
+    d = v.conv_desc(N, H, W, ci, co, c_skip=cs, upsample=up, stride=s, relu=relu)
+    w16 = torch.empty(w32.shape, dtype=torch.bfloat16, device="cuda")
+    wt16 = torch.empty((ci + cs, 3, 3, co), dtype=torch.bfloat16, device="cuda")
+    v.conv2d_pack_weights(d, w32, w16, wt16)
+    torch.cuda.synchronize()
+    assert torch.equal(w16.view(torch.int16), w32.to(torch.bfloat16).view(torch.int16))
+    assert torch.equal(wt16.view(torch.int16), w16.permute(3, 1, 2, 0).contiguous().view(torch.int16))
+    wo = w16.float().double().cpu().numpy()
+    xin = onn.upsample2(xo) if up else xo
+    if cs:
+        xin = np.concatenate([xin, sko], axis=-1)
+    return d, rng, x, sk, w16, wt16, b, wo, xin
+
+
+def _name(cfg):
+    N, H, W, ci, cs, up, s, co, relu = cfg
+    return f"N{N}_{H}x{W}_ci{ci}_cs{cs}_up{int(up)}_s{s}_co{co}"
+
+
+@pytest.mark.parametrize("cfg", CONVS, ids=_name)
+def test_conv_forward(cfg):
+    v = _vlbm()
+    announce(f"conv forward {_name(cfg)}")
+    d, rng, x, sk, w16, wt16, b, wo, xin = _layer(cfg, 11)
+    N, H, W, ci, cs, up, s, co, relu = cfg
+    OH, OW = (H + s - 1) // s, (W + s - 1) // s
+    y32 = torch.empty((N, OH, OW, co), dtype=torch.float32, device="cuda")
+    y16 = torch.empty((N, OH, OW, co), dtype=torch.bfloat16, device="cuda")
+    v.conv2d_forward(d, x, sk, w16, b, y16, y32)
+    torch.cuda.synchronize()
+    bo = b.double().cpu().numpy()
+    ref = onn.conv3x3(xin, wo, bo, s)
+    mag = onn.conv3x3(np.abs(xin), np.abs(wo), np.abs(bo), s)
+    if relu:
+        ref = onn.relu(ref)
+    K = 9 * (ci + cs) + 1
+    err = np.abs(y32.double().cpu().numpy() - ref)
+    assert np.all(err <= K * U32 * mag + 1e-30), float((err / (mag + 1e-30)).max())
+    assert torch.equal(y16.view(torch.int16), y32.to(torch.bfloat16).view(torch.int16))
+
+
+@pytest.mark.parametrize("cfg", CONVS, ids=_name)
+def test_conv_backward_data(cfg):
+    v = _vlbm()
+    announce(f"conv backward-data {_name(cfg)}")
+    d, rng, x, sk, w16, wt16, b, wo, xin = _layer(cfg, 12)
+    N, H, W, ci, cs, up, s, co, relu = cfg
+    OH, OW = (H + s - 1) // s, (W + s - 1) // s
+    gy, gyo = bf16(rng, N, OH, OW, co)
+    hs, ws = (H // 2, W // 2) if up else (H, W)
+    g0 = rng.standard_normal((N, hs, ws, ci))
+    gx = torch.tensor(g0, dtype=torch.float32).cuda()
+    gs0 = rng.standard_normal((N, H, W, cs)) if cs else None
+    gs = torch.tensor(gs0, dtype=torch.float32).cuda() if cs else None
+    v.conv2d_backward_data(d, gy, wt16, gx, gs)
+    torch.cuda.synchronize()
+    gfull = onn.conv3x3_backward(xin, wo, gyo, s)[0]
+    afull = onn.conv3x3_backward(np.abs(xin), np.abs(wo), np.abs(gyo), s)[0]
+    K = 9 * co * (4 if up else 1) + 1
+    parts = [(gx, np.float32(g0).astype(np.float64), gfull[..., :ci], afull[..., :ci])]
+    if cs:
+        parts.append((gs, np.float32(gs0).astype(np.float64), gfull[..., ci:], afull[..., ci:]))
+    for t, base, g, a in parts:
+        if up and t is gx:
+            g, a = onn.pool2_sum(g), onn.pool2_sum(a)
+        ref = base + g
+        err = np.abs(t.double().cpu().numpy() - ref)
+        assert np.all(err <= K * U32 * (a + np.abs(base)) + 1e-30), float(err.max())
+
+
+@pytest.mark.parametrize("cfg", CONVS, ids=_name)
+def test_conv_backward_weight(cfg):
+    v = _vlbm()
+    announce(f"conv backward-weight {_name(cfg)}")
+    d, rng, x, sk, w16, wt16, b, wo, xin = _layer(cfg, 13)
+    N, H, W, ci, cs, up, s, co, relu = cfg
+    OH, OW = (H + s - 1) // s, (W + s - 1) // s
+    gy, gyo = bf16(rng, N, OH, OW, co)
+    gw0 = rng.standard_normal((co, 3, 3, ci + cs))
+    gb0 = rng.standard_normal(co)
+    gw = torch.tensor(gw0, dtype=torch.float32).cuda()
+    gb = torch.tensor(gb0, dtype=torch.float32).cuda()
+    v.conv2d_backward_weight(d, x, sk, gy, gw, gb)
+    torch.cuda.synchronize()
+    _, rw, rb = onn.conv3x3_backward(xin, wo, gyo, s)
+    _, aw, ab = onn.conv3x3_backward(np.abs(xin), wo * 0 + 1.0, np.abs(gyo), s)
+    K = N * OH * OW + 4096   # terms per sum plus the partial tiles added atomically
+    for t, base, r, a in ((gw, np.float32(gw0).astype(np.float64), rw, aw),
+                          (gb, np.float32(gb0).astype(np.float64), rb, ab)):
+        err = np.abs(t.double().cpu().numpy() - (base + r))
+        assert np.all(err <= K * U32 * (a + np.abs(base)) + 1e-30), float(err.max())
+
+
+def test_adam_matches_oracle():
+    v = _vlbm()
+    announce("adam")
+    rng = np.random.default_rng(14)
+    n = 10007
+    p0, g0 = rng.standard_normal(n), rng.standard_normal(n)
+    p = torch.tensor(p0, dtype=torch.float32).cuda()
+    m = torch.zeros(n, dtype=torch.float32, device="cuda")
+    vv = torch.zeros(n, dtype=torch.float32, device="cuda")
+    po, mo, vo = np.float32(p0).astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 4):
+        g = rng.standard_normal(n)
+        gt = torch.tensor(g, dtype=torch.float32).cuda()
+        v.adam_step(p, gt, m, vv, t, 1e-3)
+        po, mo, vo = onn.adam_step(po, np.float32(g).astype(np.float64), mo, vo, t, 1e-3)
+    torch.cuda.synchronize()
+    assert np.allclose(p.double().cpu().numpy(), po, rtol=0, atol=1e-6)
+
+
+def he_params(rng, height=16, width=32):
+    parts = []
+    for _, ci, cs, _, _, co, _ in onn.layer_table():
+        fan = 9 * (ci + cs)
+        parts.append(rng.standard_normal(co * fan) * np.sqrt(2.0 / fan))
+        parts.append(0.01 * rng.standard_normal(co))
+    return np.concatenate(parts)
+
+
+def test_surrogate_forward_and_gradient_vs_oracle():
+    """Whole network, 2 x 16 x 32, against the FP64 oracle on the same BF16
+    inputs and weights.  The kernels keep activations and layer gradients in
+    BF16 between layers; a randomly initialised 19-layer network turns a 1e-6
+    relative perturbation before that rounding into ~0.5 % at its output, so the
+    network-level check is a relative bound (the per-layer tests above carry the
+    tight parity).  It is also held to the oracle that rounds to BF16 where the
+    kernels do: the distance may not exceed that oracle's own distance from the
+    FP64 network by more than a factor 2."""
+    v = _vlbm()
+    announce("surrogate forward/gradient 2x16x32")
+    rng = np.random.default_rng(15)
+    H, W, N = 16, 32, 2
+    assert v.surrogate_param_count(H, W) == onn.param_count()
+    params = np.float32(he_params(rng)).astype(np.float64)
+    x = np.float32(rng.uniform(-1, 1, (N, H, W, 3))).astype(np.float64)
+    t = np.float32(0.5 * rng.standard_normal((N, H, W, 3))).astype(np.float64)
+    s = v.Surrogate(H, W, 4, params)
+    y = s.forward(torch.tensor(x, dtype=torch.float32)).double().cpu().numpy()
+    loss, g = s.gradient(torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32))
+    gg = g.double().cpu().numpy()
+    s.close()
+    pq = params.copy()
+    o = 0
+    for _, ci, cs, _, _, co, _ in onn.layer_table():
+        nw = co * 9 * (ci + cs)
+        pq[o:o + nw] = onn.round_bf16(params[o:o + nw])
+        o += nw + co
+    x8 = np.zeros((N, H, W, onn.IN_CHANNELS))
+    x8[..., :3] = onn.round_bf16(x)
+    out = {}
+    for label, q in (("fp64", None), ("bf16", onn.round_bf16)):
+        net = onn.Surrogate(pq)
+        yo = net.forward(x8, q=q)
+        lo, go = onn.mse(yo, t)
+        out[label] = (yo[..., :3], lo, net.backward(go))
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    y64, l64, g64 = out["fp64"]
+    yq, lq, gq = out["bf16"]
+    print(f"forward rel L2: gpu-fp64 {rel(y, y64):.2e}, gpu-bf16oracle {rel(y, yq):.2e}, "
+          f"bf16oracle-fp64 {rel(yq, y64):.2e}")
+    print(f"gradient rel L2: gpu-fp64 {rel(gg, g64):.2e}, gpu-bf16oracle {rel(gg, gq):.2e}, "
+          f"bf16oracle-fp64 {rel(gq, g64):.2e}; loss {loss:.6e} vs {l64:.6e}")
+    assert rel(y, y64) <= 2e-2 and rel(gg, g64) <= 5e-2
+    assert abs(loss - l64) <= 2e-2 * l64
+    assert rel(y, yq) <= 2 * rel(yq, y64) + 1e-3
+    assert rel(gg, gq) <= 2 * rel(gq, g64) + 1e-3
+    o = 0
+    for name, ci, cs, _, _, co, _ in onn.layer_table():
+        n = co * 9 * (ci + cs) + co
+        r = rel(gg[o:o + n], g64[o:o + n])
+        assert r <= 2e-1, (name, r)
+        o += n
+
+
+def test_surrogate_training_reduces_loss():
+    v = _vlbm()
+    announce("surrogate training 60 steps")
+    rng = np.random.default_rng(16)
+    H, W, N = 16, 32, 8
+    s = v.Surrogate(H, W, N, he_params(rng))
+    yy, xx = np.meshgrid(np.linspace(0, 1, H), np.linspace(0, 1, W), indexing="ij")
+    re = rng.uniform(-1, 1, N)
+    x = np.zeros((N, H, W, 3))
+    x[..., 0], x[..., 1], x[..., 2] = xx, yy, re[:, None, None]
+    t = np.zeros((N, H, W, 3))
+    t[..., 0] = (1 + 0.5 * re[:, None, None]) * 4 * yy * (1 - yy)
+    t[..., 1] = 0.2 * np.sin(2 * np.pi * xx) * re[:, None, None]
+    t[..., 2] = 0.1 * (xx - 0.5)
+    xt, tt = torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32)
+    first = s.train_step(xt, tt, 1e-3)
+    for _ in range(58):
+        s.train_step(xt, tt, 1e-3, want_loss=False)
+    last = s.train_step(xt, tt, 1e-3)
+    _, steps = s.params()
+    print("loss", first, "->", last)
+    assert steps == 60
+    assert np.isfinite(last) and last < 0.1 * first
+    s.close()

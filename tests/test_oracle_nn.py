@@ -149,3 +149,29 @@ def test_network_gradient_finite_differences():
         e[offs[layer] + j] = 1.0
         fd = (f(params + h * e) - f(params - h * e)) / (2 * h)
         assert abs(fd - g[offs[layer] + j]) <= 1e-6 * max(1.0, abs(fd)), (layer, fd, g[offs[layer] + j])
+
+
+def test_round_bf16_matches_library_conversion():
+    import torch
+    rng = np.random.default_rng(8)
+    a = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [0.0, -0.0, 1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 3.0e38, -1e-40]])
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    got = nn.round_bf16(a)
+    assert np.array_equal(got, ref)
+    # ties go to the even neighbour: 1 + 2^-8 -> 1, 1 + 3 * 2^-8 -> 1 + 2^-6
+    assert got[-4] == 1.0 and got[-3] == 1.0 + 2 ** -6
+
+
+def test_quantized_network_is_the_plain_one_on_representable_values():
+    """With q = round_bf16 the network only differs by the rounding of stored
+    activations and gradients: on a tiny input the outputs stay within a few
+    bfloat16 ulps relative to the FP64 network."""
+    rng = np.random.default_rng(9)
+    params = _init(rng)
+    x = _rand(rng, 1, 16, 16, nn.IN_CHANNELS)
+    x[..., 3:] = 0.0
+    y = nn.Surrogate(params).forward(x)
+    yq = nn.Surrogate(params).forward(x, q=nn.round_bf16)
+    rel = np.linalg.norm(yq - y) / np.linalg.norm(y)
+    assert 0 < rel < 5e-2
