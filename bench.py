@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -241,6 +243,109 @@ def run_batch(args, torch, vlbm):
     return out
 
 
+def surrogate_flops_per_sample(H, W):
+    """Multiply-adds x 2 of the conv layers of one forward pass (the network
+    of paper_2401_17183_amd.surrogate), from the layer shapes."""
+    from paper_2401_17183_amd import surrogate as S
+    C = S.LEVEL_CHANNELS
+    total = 0
+    res = [(H >> l) * (W >> l) for l in range(5)]
+    shapes = S.layer_shapes()
+    out_res = [res[0], res[0], res[1], res[1], res[2], res[2], res[3], res[3], res[4], res[4],
+               res[3], res[3], res[2], res[2], res[1], res[1], res[0], res[0], res[0]]
+    for (co, ci), px in zip(shapes, out_res):
+        total += 2 * px * co * 9 * ci
+    return total
+
+
+def run_surrogate(args, torch, vlbm):
+    """Steady states of bump channels from the batched solver, training of the
+    BF16-MFMA surrogate, then the test meshes solved to r <= 1e-6 from rest
+    (cold) and from the surrogate's prediction (warm, inference included)."""
+    from paper_2401_17183_amd import surrogate as S
+    from paper_2401_17183_amd import workloads as W
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    ntr, nva, nte = args.train, args.val, args.test
+    ws = W.surrogate_meshes(ntr + nva + nte)
+    wtr, wva, wte = ws[:ntr], ws[ntr:ntr + nva], ws[ntr + nva:]
+    H, Wd = ws[0]["n"][1], ws[0]["n"][0]
+    log(f"steady states of {ntr + nva} training/validation meshes")
+    b, _ = S.make_batch(wtr + wva)
+    gen_steps, gen_total, gen_wall = S.solve_steady(b, tol=args.tol, log=log)
+    F = S.fields(b, wtr + wva)
+    b.close()
+    del b
+    log(f"generated in {gen_wall:.1f} s, {gen_total} steps; unconverged {(gen_steps < 0).sum()}")
+    norm = S.Normaliser.fit(F[:ntr], ws[0]["u_bulk"])
+    Xall = np.stack([S.features(w) for w in wtr + wva])
+    X = torch.tensor(Xall[:ntr]).cuda()
+    T = torch.tensor(norm.encode(F[:ntr])).cuda()
+    Xv = torch.tensor(Xall[ntr:]).cuda()
+    Tv = torch.tensor(norm.encode(F[ntr:])).cuda()
+    net = vlbm.Surrogate(H, Wd, args.batch, S.he_init(2401))
+    log(f"training {args.epochs} epochs")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = S.train(net, X, T, Xv, Tv, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    torch.cuda.synchronize()
+    train_wall = time.perf_counter() - t0
+    train_steps = args.epochs * max(1, ntr // args.batch)
+    flops = 3 * surrogate_flops_per_sample(H, Wd) * args.batch * train_steps
+    # cold
+    log(f"cold solves of {nte} test meshes")
+    bc, _ = S.make_batch(wte)
+    cold_steps, cold_total, cold_wall = S.solve_steady(bc, tol=args.tol, log=log)
+    Fte = S.fields(bc, wte)
+    bc.close()
+    del bc
+    # warm (inference timed with the solve)
+    log(f"warm solves of {nte} test meshes")
+    bw, mw = S.make_batch(wte)
+    Xte = torch.tensor(np.stack([S.features(w) for w in wte])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = S.predict(net, norm, Xte, args.batch)
+    S.warm_start(bw, P, mw)
+    torch.cuda.synchronize()
+    infer_wall = time.perf_counter() - t0
+    warm_steps, warm_total, warm_solve = S.solve_steady(bw, tol=args.tol, log=log)
+    Fw = S.fields(bw, wte)
+    bw.close()
+    warm_wall = infer_wall + warm_solve
+    uerr = [float(np.linalg.norm(P[k, ..., :2] - Fte[k, ..., :2]) / np.linalg.norm(Fte[k, ..., :2]))
+            for k in range(nte)]
+    agree = [float(np.linalg.norm(Fw[k, ..., :2] - Fte[k, ..., :2]) / np.linalg.norm(Fte[k, ..., :2]))
+             for k in range(nte)]
+    ok = (cold_steps > 0) & (warm_steps > 0)
+    ratio = cold_steps[ok] / warm_steps[ok]
+    out = {
+        "metric": METRIC, "value": round(cold_wall / warm_wall, 3),
+        "unit": "x (cold / warm wall time to r <= 1e-6, inference included)",
+        "n_gpus": 1, "steps": int(warm_total), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"surrogate warm start, {nte} test bump channels {Wd}x{H} (D2Q9 FP32 storage)",
+                   "train": ntr, "val": nva, "test": nte, "epochs": args.epochs, "batch": args.batch,
+                   "tol": args.tol, "generation_wall_s": round(gen_wall, 2), "generation_steps": int(gen_total),
+                   "train_wall_s": round(train_wall, 2), "final_train_loss": hist[-1][0],
+                   "final_val_loss": hist[-1][1],
+                   "cold_wall_s": round(cold_wall, 3), "warm_wall_s": round(warm_wall, 3),
+                   "inference_wall_s": round(infer_wall, 4),
+                   "cold_steps_median": float(np.median(cold_steps[cold_steps > 0])) if (cold_steps > 0).any() else None,
+                   "warm_steps_median": float(np.median(warm_steps[warm_steps > 0])) if (warm_steps > 0).any() else None,
+                   "steps_ratio_median": float(np.median(ratio)) if ratio.size else None,
+                   "steps_ratio_min": float(np.min(ratio)) if ratio.size else None,
+                   "steps_ratio_max": float(np.max(ratio)) if ratio.size else None,
+                   "unconverged": {"cold": int((cold_steps < 0).sum()), "warm": int((warm_steps < 0).sum())},
+                   "surrogate_u_rel_l2_median": float(np.median(uerr)), "surrogate_u_rel_l2_max": float(np.max(uerr)),
+                   "warm_vs_cold_final_u_rel_l2_max": float(np.max(agree))},
+        "roofline": {"bound": "mfma", "achieved": round(flops / train_wall / 1e12, 2), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(flops / train_wall / 1e12 / 2500.0, 5), "traffic": None,
+                     "kernel": "k_conv_gemm / k_wgrad (whole training loop, BF16 MFMA)"},
+    }
+    net.close()
+    return out
+
+
 METRIC = "MLUPS + % HBM roofline (D3Q19 FP32); warm vs cold time-to-1e-6 residual"
 # the arithmetic type of each storage mode: fp32 storage computes in FP64 registers
 ARITH = {"fp32": "f64", "fp32c": "f32", "fp64": "f64", "fp16s": "f32", "bf16s": "f32"}
@@ -252,10 +357,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch"])
+    ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch", "surrogate"])
     ap.add_argument("--precision", default="fp32", choices=sorted(STORAGE_BYTES))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file for --workload batch")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--train", type=int, default=1024, help="surrogate: training meshes")
+    ap.add_argument("--val", type=int, default=128, help="surrogate: validation meshes")
+    ap.add_argument("--test", type=int, default=64, help="surrogate: test meshes")
+    ap.add_argument("--epochs", type=int, default=60, help="surrogate: training epochs")
+    ap.add_argument("--batch", type=int, default=32, help="surrogate: minibatch")
+    ap.add_argument("--lr", type=float, default=1e-3, help="surrogate: peak learning rate")
+    ap.add_argument("--tol", type=float, default=1e-6, help="surrogate: steady residual target")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -269,10 +381,15 @@ def main():
     from paper_2401_17183_amd import vlbm
 
     torch.cuda.set_device(0)
-    out = run_batch(args, torch, vlbm) if args.workload == "batch" else run_single(args, torch, vlbm)
+    if args.workload == "batch":
+        out = run_batch(args, torch, vlbm)
+    elif args.workload == "surrogate":
+        out = run_surrogate(args, torch, vlbm)
+    else:
+        out = run_single(args, torch, vlbm)
     if args.copy_ref:
         _copy_ref(torch, out)
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "surrogate":
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

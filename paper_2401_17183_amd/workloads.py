@@ -186,22 +186,26 @@ def channel_vortex_fields(w, amp=0.02):
     return np.ones((n2, n1)), u
 
 
-def surrogate_meshes(count, seed=SEED, n1=128, n2=64, tau=0.8):
-    """Bump channels at n1 x n2 with bump ~ U[0, 0.3] H, stretch ~ U[1, 3],
-    Re ~ U[10, 100]; G = 12 nu^2 Re / H^3 (flat-channel bulk velocity relation
-    U_b = G H^2 / (12 nu) with H the channel height in units of dx)."""
+def surrogate_meshes(count, seed=SEED, n1=128, n2=64, u_bulk=0.05, re_range=(10.0, 100.0)):
+    """Bump channels at n1 x n2 with bump ~ U[0, 0.3] H (slope-capped as in
+    bump_channel_2d), stretch ~ U[1, 3], Re ~ U[re_range].  The bulk velocity is
+    held at u_bulk (Mach ~0.1 at the centreline) and the viscosity follows from
+    Re = u_bulk H / nu with H the channel height in units of dx:
+    nu = u_bulk H / Re, tau = 1/2 + 3 nu, and G = 12 nu u_bulk / H^2 from the
+    flat-channel relation u_bulk = G H^2 / (12 nu)."""
     rng = np.random.default_rng(seed)
     out = []
-    nu = (tau - 0.5) / 3.0
     for _ in range(count):
         bump = float(rng.uniform(0.0, 0.3))
         s = float(rng.uniform(1.0, 3.0))
-        Re = float(rng.uniform(10.0, 100.0))
-        w = bump_channel_2d(n1, n2, bump, s, tau)
+        Re = float(rng.uniform(*re_range))
+        w = bump_channel_2d(n1, n2, bump, s, 0.8)
         Hl = w["H"] / w["dx"]
-        G = 12.0 * nu * nu * Re / Hl ** 3
-        w["body_force"] = (G, 0.0)
+        nu = u_bulk * Hl / Re
+        w["tau"] = 0.5 + 3.0 * nu
+        w["body_force"] = (12.0 * nu * u_bulk / Hl ** 2, 0.0)
         w["Re"] = Re
+        w["u_bulk"] = u_bulk
         out.append(w)
     return out
 
