@@ -138,12 +138,16 @@ def _timed(torch, stream, fn, steps):
 
 
 def _copy_ref(torch, out):
+    """One plain 1 GiB device-to-device copy (the reference the HBM counters are
+    scaled by), timed with HIP events: its achieved GB/s is the practical copy
+    ceiling on this device."""
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    dst.copy_(src)   # warm
+    ms = _timed(torch, stream, lambda n: [dst.copy_(src) for _ in range(n)], 5) / 5
     out["config"]["copy_ref_bytes"] = 2 * src.numel() * 4
+    out["config"]["copy_ref_GBps"] = round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)
 
 
 def run_single(args, torch, vlbm):
@@ -171,8 +175,13 @@ def run_single(args, torch, vlbm):
     has_ff = any(f == vlbm.FARFIELD for face in w["faces"] for f in face)
     bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, args.precision, has_force, has_ff)
     achieved = bpc * cells / (ms_per_step / 1e3) / 1e9
-    mo = sim.moments()
-    finite = bool(torch.isfinite(mo["u"]).all().item())
+    state = "ok"
+    try:
+        mo = sim.moments()
+        finite = bool(torch.isfinite(mo["u"]).all().item())
+    except vlbm.VlbmError as e:   # the timed steps ran; the state they reached is reported
+        finite = False
+        state = str(e)
     traffic = None
     if args.workload == "channel" and args.precision in ("fp32", "fp32c"):
         traffic = profiled_traffic(f"k_step_d3q19_channel_256x128x128_{args.precision}.md", STEP_SOURCES)
@@ -184,7 +193,7 @@ def run_single(args, torch, vlbm):
         "data": "synthetic",
         "config": {"workload": w["name"] + f" {args.precision.upper()}", "cells": cells, "lattice": w["lattice"],
                    "tau": w["tau"], "storage": STORAGE[args.precision],
-                   "wall_s": round(wall, 3), "finite": finite},
+                   "wall_s": round(wall, 3), "finite": finite, "state": state},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),

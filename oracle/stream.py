@@ -9,8 +9,10 @@ puts boundary treatment out of its scope):
 * a link leaving through both a far-field and a wall face counts as far-field.
 
 Pinned by: streaming alone is a permutation (every post-collision population
-lands in exactly one slot), and n pure-streaming steps on an n-periodic axis
-return the state unchanged, bit for bit (tests/test_oracle_stream.py).
+lands in exactly one slot), n pure-streaming steps on an n-periodic axis
+return the state unchanged, bit for bit, and a uniform state equal to the
+far-field state stays unchanged on a uniform lattice with far-field faces
+(tests/test_oracle_stream.py).
 """
 import numpy as np
 

@@ -39,3 +39,28 @@ def test_bounce_back_period_in_a_channel():
     s.set_state(N0)
     s.step(8)
     assert np.array_equal(s.N, N0)
+
+
+@pytest.mark.parametrize("lat_name,n", [("D2Q9", (6, 5)), ("D3Q19", (4, 5, 3))])
+def test_uniform_far_field_state_is_steady(lat_name, n):
+    """Far-field reading pinned by an invariant: on a uniform (sheared) lattice
+    Theta = 0, so a uniform state rho_inf, u_inf is a fixed point of the interior
+    update, and the populations imposed on far-field links must be exactly the
+    ones that state streams in; twenty steps leave it unchanged."""
+    from paper_2401_17183_amd import workloads as W
+    from tests.oracle_helpers import sim_of
+    d = len(n)
+    A = np.eye(d) + 0.15 * np.roll(np.eye(d), 1, axis=1)
+    w = W.affine_mesh(lat_name, n, A, periodic=False)
+    w["faces"] = [f if i != 1 else (W.FARFIELD, W.FARFIELD) for i, f in enumerate(w["faces"])]
+    w["rho_inf"] = 1.02
+    w["u_inf"] = tuple([0.03, -0.02, 0.01][:d])
+    s = sim_of(w)
+    rho = np.full(s.mesh.shape, 1.02)
+    u = np.broadcast_to(np.array(w["u_inf"]).reshape((d,) + (1,) * d), (d,) + s.mesh.shape).copy()
+    s.init(rho, u)
+    N0 = s.N.copy()
+    s.step(20)
+    assert np.max(np.abs(s.N - N0)) <= 1e-14 * np.max(np.abs(N0))
+    m = s.moments()
+    assert np.allclose(m["u"], u, rtol=0, atol=1e-14)
