@@ -19,11 +19,12 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   AT aext[L::D];           // a_ext^i = G . g^i
   AT Areg[STRIDE ? 1 : L::Q][L::D];
   const AT* lds;
+  int lofs;                // added to every LDS index (0); re-defined per fixed-point iteration
   __device__ __forceinline__ T j() const { return T(J); }
   __device__ __forceinline__ T ae(int i) const { return T(aext[i]); }
   __device__ __forceinline__ AT a(int al, int i) const {
     if constexpr (STRIDE == 0) return Areg[al][i];
-    else return al == 0 ? AT(0) : lds[((al - 1) * L::D + i) * STRIDE];
+    else return al == 0 ? AT(0) : lds[lofs + ((al - 1) * L::D + i) * STRIDE];
   }
 };
 
@@ -58,6 +59,24 @@ template <class T, class AT>
 __device__ __forceinline__ T widen(AT v) {
   if constexpr (sizeof(AT) < sizeof(T)) asm volatile("" : "+v"(v));
   return T(v);
+}
+
+// A_p and A_q (all components) in the arithmetic type, the narrow values
+// loaded together before any is widened: the loads of a group are in flight
+// at once instead of one LDS round trip per value.
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void a_pair(const CellGeo<L, T, AT, ST>& g, int p, int q, T* ap, T* aq) {
+  AT v[2 * L::D];
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    v[i] = g.a(p, i);
+    v[L::D + i] = g.a(q, i);
+  }
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    ap[i] = widen<T>(v[i]);
+    aq[i] = widen<T>(v[L::D + i]);
+  }
 }
 
 // Per-cell scalars of the equilibrium that do not depend on the direction.
@@ -164,21 +183,22 @@ template <class L, class T, class AT, int ST, bool WITH_XO, int p = 1>
 __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, T* X, T* Xo,
                                          T (*M)[L::D]) {
   if constexpr (p < L::Q) {
+    T ap[L::D], am[L::D];
+    a_pair<L, T, AT, ST>(g, p, p + 1, ap, am);
     const T fp = feq_dir<L, T, AT, ST, p>(g, e);
     const T fm = feq_dir<L, T, AT, ST, p + 1>(g, e);
     const T df = fp - fm;
 #pragma unroll
     for (int i = 0; i < L::D; ++i) {
-      const T ap = widen<T>(g.a(p, i)), am = widen<T>(g.a(p + 1, i));
-      X[i] += ap * fp + am * fm;
-      if constexpr (WITH_XO) Xo[i] += am * fp + ap * fm;
+      X[i] += ap[i] * fp + am[i] * fm;
+      if constexpr (WITH_XO) Xo[i] += am[i] * fp + ap[i] * fm;
     }
 #pragma unroll
     for (int i = 0; i < L::D; ++i) {
       const int ci = L::c(p, i);
       if (ci == 0) continue;
 #pragma unroll
-      for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * (widen<T>(g.a(p, j)) + widen<T>(g.a(p + 1, j))) * df;
+      for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * (ap[j] + am[j]) * df;
     }
     pass_feq<L, T, AT, ST, WITH_XO, p + 2>(g, e, X, Xo, M);
   }
@@ -188,10 +208,13 @@ __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const E
 template <class L, class T, class AT, int ST, int a = 1>
 __device__ __forceinline__ void pass_dn(const CellGeo<L, T, AT, ST>& g, const T* Ft, const T* dpi, T trdpi, T* Y) {
   if constexpr (a < L::Q) {
-    const T dn = delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
+    T ap[L::D], am[L::D];
+    a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
+    const T dp = delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
+    const T dm = delta_n_dir<L, T, a + 1>(g.j(), Ft, dpi, trdpi);
 #pragma unroll
-    for (int i = 0; i < L::D; ++i) Y[i] += widen<T>(g.a(a, i)) * dn;
-    pass_dn<L, T, AT, ST, a + 1>(g, Ft, dpi, trdpi, Y);
+    for (int i = 0; i < L::D; ++i) Y[i] += ap[i] * dp + am[i] * dm;
+    pass_dn<L, T, AT, ST, a + 2>(g, Ft, dpi, trdpi, Y);
   }
 }
 

@@ -67,6 +67,7 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
 #pragma unroll
     for (int i = 0; i < L::D; ++i) g.Areg[0][i] = S(0);
   g.lds = lds;
+  g.lofs = 0;
 #pragma unroll
   for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? word(geo, Pack<L>::AEXT + i, nc)[cell] : S(0);
   return g;
