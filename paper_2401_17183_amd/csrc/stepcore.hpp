@@ -146,10 +146,14 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
 #pragma unroll
   for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
-  // gather again (cache hits) rather than keeping N live across the fixed point
-  int xr = x;
-  pin(xr);
-  gather<L, P, S, T, NR, ST>(a, g, xr, y, z, cell, N);
+  // gather again (cache hits) rather than keeping N live across the fixed point;
+  // decoded 16-bit populations stay in registers (their re-gather would also
+  // re-read and re-apply the link references)
+  if constexpr (!PopCodec<P>::shifted && sizeof(T) == 8) {
+    int xr = x;
+    pin(xr);
+    gather<L, P, S, T, NR, ST>(a, g, xr, y, z, cell, N);
+  }
   T Np[Q];
   collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
 #pragma unroll
