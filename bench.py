@@ -218,10 +218,11 @@ def run_batch(args, torch, vlbm):
     print("[bench] autotune", file=sys.stderr, flush=True)
     block, gpc = b.autotune(trial_steps=10, cache_path=args.tune_cache)
     modes = {}
-    for name, mode, steps in (("persistent_graph", vlbm.BATCH_PERSISTENT_GRAPH, args.steps),
-                              ("persistent", vlbm.BATCH_PERSISTENT, max(32, args.steps // 4)),
-                              ("eager_per_mesh", vlbm.BATCH_EAGER, max(32, args.steps // 10)),
-                              ("graph_per_mesh", vlbm.BATCH_EAGER_GRAPH, max(32, args.steps // 10))):
+    plan = [("persistent_graph", vlbm.BATCH_PERSISTENT_GRAPH, args.steps),
+            ("persistent", vlbm.BATCH_PERSISTENT, max(32, args.steps // 4)),
+            ("eager_per_mesh", vlbm.BATCH_EAGER, max(32, args.steps // 10)),
+            ("graph_per_mesh", vlbm.BATCH_EAGER_GRAPH, max(32, args.steps // 10))]
+    for name, mode, steps in plan[:1] if args.persistent_only else plan:
         b.set_mode(mode)
         print(f"[bench] {name}: warmup {args.warmup + 32}, timing {steps} steps", file=sys.stderr, flush=True)
         b.step(args.warmup + 32)   # includes the graph capture
@@ -369,6 +370,8 @@ def main():
     ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch", "surrogate"])
     ap.add_argument("--precision", default="fp32", choices=sorted(STORAGE_BYTES))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file for --workload batch")
+    ap.add_argument("--persistent-only", action="store_true",
+                    help="--workload batch: time only the persistent graph-replayed mode (for counter runs)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train", type=int, default=1024, help="surrogate: training meshes")
     ap.add_argument("--val", type=int, default=128, help="surrogate: validation meshes")

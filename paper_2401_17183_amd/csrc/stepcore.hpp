@@ -150,9 +150,14 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   // decoded 16-bit populations stay in registers (their re-gather would also
   // re-read and re-apply the link references)
   if constexpr (!PopCodec<P>::shifted && sizeof(T) == 8) {
-    int xr = x;
+    // opaque copies of the coordinates: the source addresses are recomputed
+    // here instead of being kept (or spilled) across the fixed point
+    int xr = x, yr = y, zr = z, cr = cell;
     pin(xr);
-    gather<L, P, S, T, NR, ST>(a, g, xr, y, z, cell, N);
+    pin(yr);
+    pin(zr);
+    pin(cr);
+    gather<L, P, S, T, NR, ST>(a, g, xr, yr, zr, cr, N);
   }
   T Np[Q];
   collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
