@@ -127,6 +127,60 @@ __device__ __forceinline__ int link_source(const Box& b, int a, int x, int y, in
   return far ? LINK_FARFIELD : (wall ? LINK_WALL : LINK_INTERIOR);
 }
 
+// The same rule prepared once per cell: along each axis the linear offset of
+// the source for c^i = +1 (the neighbour at q^i - 1) and for c^i = -1 (at
+// q^i + 1), with the periodic wrap applied, and bit i set in wall/far when that
+// neighbour lies beyond a wall or far-field face.  link_at then resolves a
+// direction with compile-time component tests only.
+struct LinkPlan {
+  int off_lo[3], off_hi[3];
+  unsigned wall_lo, wall_hi, far_lo, far_hi;
+};
+
+template <class L>
+__device__ __forceinline__ LinkPlan link_plan(const Box& b, int x, int y, int z) {
+  const int q[3] = {x, y, z};
+  LinkPlan p;
+  p.wall_lo = p.wall_hi = p.far_lo = p.far_hi = 0u;
+  int stride = 1;
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    const int n = b.n[i];
+    const int at_lo = q[i] == 0, at_hi = q[i] == n - 1;
+    const int flo = b.face[i][0], fhi = b.face[i][1];
+    p.off_lo[i] = at_lo ? (flo == VLBM_PERIODIC ? (n - 1) * stride : 0) : -stride;
+    p.off_hi[i] = at_hi ? (fhi == VLBM_PERIODIC ? -(n - 1) * stride : 0) : stride;
+    p.wall_lo |= (unsigned)(at_lo & (flo == VLBM_WALL)) << i;
+    p.far_lo |= (unsigned)(at_lo & (flo == VLBM_FARFIELD)) << i;
+    p.wall_hi |= (unsigned)(at_hi & (fhi == VLBM_WALL)) << i;
+    p.far_hi |= (unsigned)(at_hi & (fhi == VLBM_FARFIELD)) << i;
+    stride *= n;
+  }
+  return p;
+}
+
+// link_source for compile-time direction a from a prepared plan (cell = own index).
+template <class L, int a>
+__device__ __forceinline__ int link_at(const LinkPlan& p, int cell, int& src) {
+  int off = 0;
+  unsigned lo = 0u, hi = 0u;   // compile-time masks of the axes whose low / high neighbour is the source
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    const int ci = L::c(a, i);
+    if (ci > 0) {
+      off += p.off_lo[i];
+      lo |= 1u << i;
+    } else if (ci < 0) {
+      off += p.off_hi[i];
+      hi |= 1u << i;
+    }
+  }
+  const unsigned far = (p.far_lo & lo) | (p.far_hi & hi);
+  const unsigned wall = (p.wall_lo & lo) | (p.wall_hi & hi);
+  src = (far | wall) ? cell : cell + off;
+  return far ? LINK_FARFIELD : (wall ? LINK_WALL : LINK_INTERIOR);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side objects.
 // ---------------------------------------------------------------------------

@@ -73,6 +73,23 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
   return g;
 }
 
+template <class L, class P, class S, class T, class NR, int al = 0>
+__device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const LinkPlan& plan, int cell, NR* N,
+                                            unsigned& ff) {
+  if constexpr (al < L::Q) {
+    using C = PopCodec<P>;
+    const int nc = a.box.ncells;
+    int src;
+    const int kind = link_at<L, al>(plan, cell, src);
+    const int dir = kind == LINK_INTERIOR ? al : opp(al);
+    const P h = word(a.in, 0, nc)[(size_t)dir * nc + src];
+    if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rsrc, al, nc)[cell], a.inv_scale);
+    else N[al] = h;
+    ff |= (kind == LINK_FARFIELD ? 1u : 0u) << al;
+    gather_dirs<L, P, S, T, NR, al + 1>(a, plan, cell, N, ff);
+  }
+}
+
 // Pull N_a(q) = N'_a(q - c_a) (eq. (adv)).  Every load is unconditional and in
 // bounds (a bounced or far-field link reads the cell's own opposite slot), so
 // no lane diverges; far-field links then take J f^eq(rho_inf, U_inf, U_inf).
@@ -83,17 +100,9 @@ __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo
   constexpr int D = L::D;
   using C = PopCodec<P>;
   const int nc = a.box.ncells;
+  const LinkPlan plan = link_plan<L>(a.box, x, y, z);
   unsigned ff = 0;
-#pragma unroll
-  for (int al = 0; al < Q; ++al) {
-    int src;
-    const int kind = link_source<L>(a.box, al, x, y, z, src);
-    const int dir = kind == LINK_INTERIOR ? al : opp(al);
-    const P h = word(a.in, 0, nc)[(size_t)dir * nc + src];
-    if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rsrc, al, nc)[cell], a.inv_scale);
-    else N[al] = h;
-    ff |= (kind == LINK_FARFIELD ? 1u : 0u) << al;
-  }
+  gather_dirs<L, P, S, T, NR>(a, plan, cell, N, ff);
   if (a.has_ff) {   // wave-uniform
     T Uinf[D];
 #pragma unroll
