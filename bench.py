@@ -95,6 +95,7 @@ def cpu_baseline(workload="channel", seconds_target=12.0):
 
 STEP_SOURCES = ["paper_2401_17183_amd/csrc/common.hpp", "paper_2401_17183_amd/csrc/dynamics.hpp",
                 "paper_2401_17183_amd/csrc/stepcore.hpp", "paper_2401_17183_amd/csrc/step.hip"]
+BATCH_SOURCES = STEP_SOURCES[:3] + ["paper_2401_17183_amd/csrc/batch.hip"]
 
 
 def profiled_traffic(profile, sources):
@@ -236,6 +237,9 @@ def run_batch(args, torch, vlbm):
     bpc = algorithmic_bytes_per_cell(9, 2, args.precision, True)
     achieved = bpc * cells / (main["ms_per_step"] / 1e3) / 1e9
     finite = all(bool(torch.isfinite(m.moments()["u"]).all().item()) for m in b.members[:8])
+    traffic = None
+    if args.precision == "fp32" and (block, gpc) == (256, 0):
+        traffic = profiled_traffic("k_batch_d2q9_bump256_fp32.md", BATCH_SOURCES)
     out = {
         "metric": METRIC,
         "value": main["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": main["steps"], "warmup": args.warmup,
@@ -246,7 +250,10 @@ def run_batch(args, torch, vlbm):
                    "storage": STORAGE[args.precision], "block": block, "grid_per_cu": gpc, "modes": modes,
                    "finite": finite},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": bpc * cells,
                      "bytes_per_cell": bpc, "kernel": "k_batch"},
     }
     b.close()

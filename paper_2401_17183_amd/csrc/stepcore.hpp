@@ -169,9 +169,21 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
     gather<L, P, S, T, NR, ST>(a, g, xr, yr, zr, cr, N);
   }
   T Np[Q];
-  collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
+  if constexpr (PopCodec<P>::shifted) {
+    // the references of the written slots are loaded before the output
+    // arithmetic, so their latency hides behind it
+    P ref[Q];
 #pragma unroll
-  for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, Np[al]);
+    for (int al = 0; al < Q; ++al) ref[al] = word(a.rown, al, nc)[cell];
+    collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
+#pragma unroll
+    for (int al = 0; al < Q; ++al)
+      word(a.out, al, nc)[cell] = PopCodec<P>::template encode<T>(T(Np[al]), ref[al], a.scale);
+  } else {
+    collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
+#pragma unroll
+    for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, Np[al]);
+  }
 }
 
 // Kernel arguments of one simulation's step (current buffer parity).
