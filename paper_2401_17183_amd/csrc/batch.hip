@@ -19,14 +19,15 @@ namespace vlbm {
 
 namespace {
 
-template <class L, class P, class S, class T, int BLOCK>
+// FF = 0 when no member has far-field links, else 2 (per-member run-time test).
+template <class L, class P, class S, class T, int BLOCK, int FF>
 __global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_batch(const StepArgs<P, S, T>* __restrict__ args,
                                                                 const Tile* __restrict__ tiles, int ntiles,
                                                                 int parity) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile tl = tiles[t];
     const StepArgs<P, S, T> a = args[2 * tl.mesh + parity];
-    step_cell<L, P, S, T, BLOCK>(a, tl.first + threadIdx.x);
+    step_cell<L, P, S, T, BLOCK, FF>(a, tl.first + threadIdx.x);
   }
 }
 
@@ -79,8 +80,9 @@ hipError_t build_tiles(BatchObj* b) {
 template <class L, class P, class S, class T, int BLOCK>
 hipError_t launch_batch_typed(BatchObj* b, int parity) {
   const int grid = b->grid_per_cu > 0 ? std::min(b->ntiles, b->grid_per_cu * b->cus) : b->ntiles;
-  k_batch<L, P, S, T, BLOCK><<<grid, BLOCK, 0, b->stream>>>(static_cast<const StepArgs<P, S, T>*>(b->d_args),
-                                                            b->d_tiles, b->ntiles, parity);
+  const StepArgs<P, S, T>* args = static_cast<const StepArgs<P, S, T>*>(b->d_args);
+  if (b->any_ff) k_batch<L, P, S, T, BLOCK, 2><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
+  else k_batch<L, P, S, T, BLOCK, 0><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct BatchObj {
   int graph_steps = 32;
   int64_t t = 0;
   int64_t total_cells = 0;
+  bool any_ff = false;               // some member has far-field links
   const double** d_rsrc = nullptr;   // per member: address of its latest audit's residual
   double* d_resid = nullptr;         // gathered residuals [count]
 };

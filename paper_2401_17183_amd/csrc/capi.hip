@@ -546,6 +546,7 @@ int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int co
     if (rc) return bail(rc);
     b->members.push_back(s);
     b->total_cells += m->box.ncells;
+    b->any_ff = b->any_ff || s->has_farfield;
   }
   if (batch_upload(b) != hipSuccess) {
     fail(VLBM_ERR_DEVICE, "batch upload failed");

@@ -9,15 +9,17 @@ namespace {
 constexpr int kBlock = 256;
 
 // FP32 geometry: two waves per SIMD (see VLBM_STEP_ATTR).
-template <class L, class P, class S, class T>
+// FF = 0 when the mesh has no far-field links, else 2 (wave-uniform run-time
+// test, which keeps the far-field variant free of spills).
+template <class L, class P, class S, class T, int FF>
 __global__ __launch_bounds__(kBlock) VLBM_STEP_ATTR void k_step(StepArgs<P, S, T> a) {
-  step_cell<L, P, S, T, kBlock>(a, blockIdx.x * kBlock + threadIdx.x);
+  step_cell<L, P, S, T, kBlock, FF>(a, blockIdx.x * kBlock + threadIdx.x);
 }
 
 // FP64 storage keeps A in registers and runs at the occupancy the compiler picks.
-template <class L, class P, class S, class T>
+template <class L, class P, class S, class T, int FF>
 __global__ __launch_bounds__(kBlock) void k_step64(StepArgs<P, S, T> a) {
-  step_cell<L, P, S, T, kBlock>(a, blockIdx.x * kBlock + threadIdx.x);
+  step_cell<L, P, S, T, kBlock, FF>(a, blockIdx.x * kBlock + threadIdx.x);
 }
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
@@ -52,10 +54,13 @@ template <class L, class P, class S, class T>
 hipError_t step_typed(SimObj* s) {
   const StepArgs<P, S, T> a = make_step_args<P, S, T>(s);
   const int nb = (a.box.ncells + kBlock - 1) / kBlock;
-  if constexpr (sizeof(S) == 8)
-    k_step64<L, P, S, T><<<nb, kBlock, 0, s->stream>>>(a);
-  else
-    k_step<L, P, S, T><<<nb, kBlock, 0, s->stream>>>(a);
+  if constexpr (sizeof(S) == 8) {
+    if (a.has_ff) k_step64<L, P, S, T, 2><<<nb, kBlock, 0, s->stream>>>(a);
+    else k_step64<L, P, S, T, 0><<<nb, kBlock, 0, s->stream>>>(a);
+  } else {
+    if (a.has_ff) k_step<L, P, S, T, 2><<<nb, kBlock, 0, s->stream>>>(a);
+    else k_step<L, P, S, T, 0><<<nb, kBlock, 0, s->stream>>>(a);
+  }
   return hipGetLastError();
 }
 

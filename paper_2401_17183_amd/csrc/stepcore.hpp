@@ -93,7 +93,9 @@ __device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const Li
 // Pull N_a(q) = N'_a(q - c_a) (eq. (adv)).  Every load is unconditional and in
 // bounds (a bounced or far-field link reads the cell's own opposite slot), so
 // no lane diverges; far-field links then take J f^eq(rho_inf, U_inf, U_inf).
-template <class L, class P, class S, class T, class NR, int ST>
+// FF: 0 = no far-field links, 1 = far-field links, 2 = decided at run time
+// (has_ff); a compile-time choice keeps the fill out of the control flow.
+template <class L, class P, class S, class T, class NR, int ST, int FF = 2>
 __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo<L, T, S, ST>& g, int x, int y,
                                        int z, int cell, NR* N) {
   constexpr int Q = L::Q;
@@ -103,7 +105,7 @@ __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo
   const LinkPlan plan = link_plan<L>(a.box, x, y, z);
   unsigned ff = 0;
   gather_dirs<L, P, S, T, NR>(a, plan, cell, N, ff);
-  if (a.has_ff) {   // wave-uniform
+  if (FF == 1 || (FF == 2 && a.has_ff)) {   // compile-time or wave-uniform
     T Uinf[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) Uinf[i] = T(word(a.geo, Pack<L>::UINF + i, nc)[cell]);
@@ -123,7 +125,7 @@ __device__ __forceinline__ void store_slot(const StepArgs<P, S, T>& a, int al, i
 }
 
 // One cell of one mesh; BLOCK threads per workgroup share the LDS staging.
-template <class L, class P, class S, class T, int BLOCK>
+template <class L, class P, class S, class T, int BLOCK, int FF = 2>
 __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
@@ -140,7 +142,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   __shared__ S sA[ST ? (Q - 1) * D * BLOCK : 1];
   NR N[Q];
   const CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
-  gather<L, P, S, T, NR, ST>(a, g, x, y, z, cell, N);
+  gather<L, P, S, T, NR, ST, FF>(a, g, x, y, z, cell, N);
   if (a.stream_only) {
 #pragma unroll
     for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, N[al]);
@@ -166,7 +168,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
     pin(yr);
     pin(zr);
     pin(cr);
-    gather<L, P, S, T, NR, ST>(a, g, xr, yr, zr, cr, N);
+    gather<L, P, S, T, NR, ST, FF>(a, g, xr, yr, zr, cr, N);
   }
   T Np[Q];
   if constexpr (PopCodec<P>::shifted) {
