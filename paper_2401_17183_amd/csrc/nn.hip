@@ -51,18 +51,23 @@ __device__ __forceinline__ RowF row_fwd(const Conv& c, int64_t m, int64_t M) {
   return r;
 }
 
-// The 8 input channels ch..ch+7 at tap (kh, kw) of a forward row (zero outside).
+// The 8 input channels ch..ch+7 at tap (kh, kw) of a forward row (zero
+// outside).  Branch-free: the load always happens, from the tensor's first
+// element when the tap is outside, and the result is then selected.  Element
+// offsets are 32-bit (check() bounds every tensor below 2^31 elements).
 __device__ __forceinline__ u32x4 gather_fwd(const Conv& c, const uint16_t* x, const uint16_t* skip, const RowF& r,
                                             int kh, int kw, int ch, bool kok) {
   const int ih = r.ih0 + kh, iw = r.iw0 + kw;
   const u32x4 z = {0u, 0u, 0u, 0u};
-  if (!(r.ok && kok) || ih < 0 || ih >= c.H || iw < 0 || iw >= c.W) return z;
-  if (ch < c.cin) {
-    const int hs = c.up ? (c.H >> 1) : c.H, ws = c.up ? (c.W >> 1) : c.W;
-    const int y = c.up ? (ih >> 1) : ih, xx = c.up ? (iw >> 1) : iw;
-    return ld16(x + (((int64_t)r.n * hs + y) * ws + xx) * c.cin + ch);
-  }
-  return ld16(skip + (((int64_t)r.n * c.H + ih) * c.W + iw) * c.cskip + (ch - c.cin));
+  const bool valid = r.ok && kok && (unsigned)ih < (unsigned)c.H && (unsigned)iw < (unsigned)c.W;
+  const bool prim = ch < c.cin;
+  const int hs = c.up ? (c.H >> 1) : c.H, ws = c.up ? (c.W >> 1) : c.W;
+  const int y = c.up ? (ih >> 1) : ih, xx = c.up ? (iw >> 1) : iw;
+  const int offp = ((r.n * hs + y) * ws + xx) * c.cin + ch;
+  const int offs = ((r.n * c.H + ih) * c.W + iw) * c.cskip + (ch - c.cin);
+  const uint16_t* p = prim ? x + offp : skip + offs;
+  const u32x4 v = ld16(valid ? p : x);
+  return valid ? v : z;
 }
 
 // Input-gradient row: pixel (n, y, x) of the tensor whose gradient is formed;
@@ -84,19 +89,20 @@ __device__ __forceinline__ RowB row_bwd(int64_t m, int64_t M, int h, int w) {
   return r;
 }
 
-// gy channels co..co+7 at the output pixel that reads input (ih, iw) through tap (kh, kw).
+// gy channels co..co+7 at the output pixel that reads input (ih, iw) through
+// tap (kh, kw); branch-free like gather_fwd (stride 1 or 2).
 __device__ __forceinline__ u32x4 gather_bwd(const Conv& c, const uint16_t* gy, const RowB& r, int sub4, int sub,
                                             int kh, int kw, int co, bool kok) {
   const u32x4 z = {0u, 0u, 0u, 0u};
   const int ih = sub4 ? 2 * r.y + (sub >> 1) : r.y;
   const int iw = sub4 ? 2 * r.x + (sub & 1) : r.x;
   const int ohn = ih + 1 - kh, own = iw + 1 - kw;
-  if (!(r.ok && kok) || ohn < 0 || own < 0) return z;
-  const int s = c.stride;
-  if ((ohn % s) != 0 || (own % s) != 0) return z;
-  const int oh = ohn / s, ow = own / s;
-  if (oh >= c.OH || ow >= c.OW) return z;
-  return ld16(gy + (((int64_t)r.n * c.OH + oh) * c.OW + ow) * c.cout + co);
+  const int sm = c.stride - 1, sh = c.stride >> 1;   // stride 1 or 2
+  const int oh = ohn >> sh, ow = own >> sh;
+  const bool valid = r.ok && kok && ohn >= 0 && own >= 0 && ((ohn | own) & sm) == 0 && oh < c.OH && ow < c.OW;
+  const int off = ((r.n * c.OH + oh) * c.OW + ow) * c.cout + co;
+  const u32x4 v = ld16(valid ? gy + off : gy);
+  return valid ? v : z;
 }
 
 struct Gemm {
@@ -117,19 +123,19 @@ struct Gemm {
 // C[m][n] = sum_k A(m, k) B[n][k].  FWD: A = im2col of the layer input,
 // B = W; epilogue bias + ReLU, BF16 and/or FP32 store.  BWD: A = the output
 // gradient read through the transposed convolution, B = W^T; epilogue +=.
-template <bool FWD, int WM>
+// Four waves stacked along m, each owning 32 rows x 16 TJ columns: one A
+// gather (the costly, index-heavy operand) feeds 2 TJ MFMAs per K step.
+template <bool FWD, int TJ>
 __global__ __launch_bounds__(kThreads) void k_conv_gemm(Conv c, Gemm g) {
-  constexpr int WN = 4 / WM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave % WM, wn = wave / WM;
-  const int64_t m0 = (int64_t)blockIdx.x * (32 * WM) + wm * 32;
-  const int n0 = blockIdx.y * (32 * WN) + wn * 32;
+  const int64_t m0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int n0 = blockIdx.y * (16 * TJ);
   const int l16 = lane & 15, kq = 8 * (lane >> 4);
-  f32x4 acc[2][2];
+  f32x4 acc[2][TJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   RowF rf[2];
   RowB rb[2];
@@ -142,14 +148,22 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(Conv c, Gemm g) {
   const int ct = c.ctot();
   const int kb = 9 * c.cout;   // backward: reduction indices per sub-position
   const u32x4 z = {0u, 0u, 0u, 0u};
+  const uint16_t* brow[TJ];
+  bool bok[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int col = n0 + 16 * j + l16;
+    bok[j] = col < g.ncols;
+    brow[j] = g.b + (int64_t)(g.b_row0 + (bok[j] ? col : 0)) * g.b_ld;
+  }
   for (int k0 = 0; k0 < g.K; k0 += 32) {
     const int k = k0 + kq;
     const bool kok = k < g.K;
-    u32x4 av[2], bv[2];
+    u32x4 av[2];
     int kbk;   // column of B
     if constexpr (FWD) {
       const int tap = k / ct, ch = k - tap * ct;
-      const int kh = tap / 3, kw = tap - 3 * kh;
+      const int kh = (tap * 11) >> 5, kw = tap - 3 * kh;   // tap / 3 for tap < 9
 #pragma unroll
       for (int i = 0; i < 2; ++i) av[i] = gather_fwd(c, g.a0, g.a1, rf[i], kh, kw, ch, kok);
       kbk = k;
@@ -157,26 +171,25 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(Conv c, Gemm g) {
       const int sub = g.sub4 ? k / kb : 0;
       const int rem = k - sub * kb;
       const int tap = rem / c.cout, co = rem - tap * c.cout;
-      const int kh = tap / 3, kw = tap - 3 * kh;
+      const int kh = (tap * 11) >> 5, kw = tap - 3 * kh;
 #pragma unroll
       for (int i = 0; i < 2; ++i) av[i] = gather_bwd(c, g.a0, rb[i], g.sub4, sub, kh, kw, co, kok);
       kbk = rem;
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + 16 * j + l16;
-      bv[j] = (kok && col < g.ncols) ? ld16(g.b + (int64_t)(g.b_row0 + col) * g.b_ld + kbk) : z;
+    for (int j = 0; j < TJ; ++j) {
+      const bool ok = kok && bok[j];
+      const u32x4 v = ld16(brow[j] + (ok ? kbk : 0));
+      const u32x4 bv = ok ? v : z;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv), acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av[i]), as_bf(bv[j]), acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < TJ; ++j) {
       const int col = n0 + 16 * j + l16;
       if (col >= g.ncols) continue;
 #pragma unroll
@@ -364,12 +377,17 @@ int grid_for(int64_t n) {
 template <bool FWD>
 hipError_t launch_gemm(const Conv& c, const Gemm& g, hipStream_t st) {
   if (g.M <= 0 || g.ncols <= 0) return hipSuccess;
-  if (g.ncols > 32) {
-    dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.ncols + 63) / 64));
-    k_conv_gemm<FWD, 2><<<grid, kThreads, 0, st>>>(c, g);
-  } else {
-    dim3 grid((unsigned)((g.M + 127) / 128), (unsigned)((g.ncols + 31) / 32));
-    k_conv_gemm<FWD, 4><<<grid, kThreads, 0, st>>>(c, g);
+  const unsigned gm = (unsigned)((g.M + 127) / 128);
+  auto cols = [&](int w) { return (unsigned)((g.ncols + w - 1) / w); };
+  // the widest column tile that still gives >= 1024 blocks (4 per CU): small
+  // layers need the parallelism more than the operand reuse
+  int tj = 8;
+  while (tj > 1 && (g.ncols <= 8 * tj || (int64_t)gm * cols(16 * tj) < 1024)) tj >>= 1;
+  switch (tj) {
+    case 8: k_conv_gemm<FWD, 8><<<dim3(gm, cols(128)), kThreads, 0, st>>>(c, g); break;
+    case 4: k_conv_gemm<FWD, 4><<<dim3(gm, cols(64)), kThreads, 0, st>>>(c, g); break;
+    case 2: k_conv_gemm<FWD, 2><<<dim3(gm, cols(32)), kThreads, 0, st>>>(c, g); break;
+    default: k_conv_gemm<FWD, 1><<<dim3(gm, cols(16)), kThreads, 0, st>>>(c, g); break;
   }
   return hipGetLastError();
 }
@@ -383,6 +401,8 @@ const char* check(const Conv& c) {
   if (c.stride != 1 && c.stride != 2) return "stride must be 1 or 2";
   if (c.up && (c.H % 2 || c.W % 2 || c.stride != 1)) return "upsampled inputs need even sizes and stride 1";
   if (c.OH != (c.H + c.stride - 1) / c.stride || c.OW != (c.W + c.stride - 1) / c.stride) return "bad output size";
+  const int64_t cmax = c.cin > c.cskip ? (c.cin > c.cout ? c.cin : c.cout) : (c.cskip > c.cout ? c.cskip : c.cout);
+  if ((int64_t)c.N * c.H * c.W * cmax >= (int64_t)1 << 31) return "tensors must hold fewer than 2^31 elements";
   return nullptr;
 }
 
