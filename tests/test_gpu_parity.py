@@ -302,6 +302,63 @@ def test_full_size_channel_sampled_parity():
     assert worst < 2e-6
 
 
+def test_full_size_ogrid_sampled_parity():
+    """The 256x512x64 D3Q19 O-grid (cylinder wall at r = 1, far field at r = 20,
+    8.4 M cells, FP32 storage) at full size, started from the far-field flow:
+    on 96 sampled cells (wall and far-field rings, theta and z seams, interior)
+    the initial state equals the oracle's consistent equilibrium and one step
+    equals the oracle's collision of the GPU's own arrived populations, found
+    where the GPU streamed them (links leaving through the far field are
+    dropped, bounced links land in the opposite slot)."""
+    from oracle import collide as OC
+    from tests.oracle_helpers import SampleGeometry
+    w = W.ogrid_3d()
+    announce("full-size O-grid 256x512x64 fp32 sampled parity")
+    n1, n2, n3 = w["n"]
+    rng = np.random.default_rng(11)
+    xs = np.r_[0, n1 - 1, 0, n1 - 1, 1, n1 - 2, rng.integers(0, n1, 90)]
+    ys = np.r_[0, n2 - 1, n2 - 1, 0, rng.integers(0, n2, 92)]
+    zs = np.r_[n3 - 1, 0, 0, n3 - 1, rng.integers(0, n3, 92)]
+    cells = (xs + n1 * (ys + n2 * zs)).astype(np.int64)
+    sg = SampleGeometry(w, cells)
+    nc = n1 * n2 * n3
+    rho = np.ones(nc)
+    u = np.zeros((3, nc))
+    u[0] = w["u_inf"][0]
+    s, m = gpu_sim(w, precision="fp32", rho=rho, u=u)
+    lat = sg.lat
+    N0 = s.populations()
+    N0s = cpu(N0[:, torch.as_tensor(cells, device=N0.device)])
+    Ut = np.einsum("k...,ik...->i...", u[:, cells], sg.gco)
+    want0 = OC.consistent_equilibrium(sg, w["tau"], rho[cells], Ut)
+    f_err0 = np.max(np.abs(N0s - want0) / sg.J)
+    print("init max |f err|", f_err0)
+    assert f_err0 < 1e-6
+    del N0
+    s.step(1)
+    N1 = s.populations()
+    Np, info = OC.collide(sg, w["tau"], N0s)
+    assert info["converged"]
+    worst = 0.0
+    checked = 0
+    for a in range(lat.Q):
+        c = lat.c[a]
+        dx = xs + c[0]
+        dy = (ys + c[1]) % n2
+        dz = (zs + c[2]) % n3
+        wall = dx < 0
+        far = dx >= n1
+        keep = ~far
+        dest = np.where(wall, cells, dx.clip(0, n1 - 1) + n1 * (dy + n2 * dz))[keep]
+        slot = np.where(wall, lat.opp[a], a)[keep]
+        got = cpu(N1[torch.as_tensor(slot, device=N1.device), torch.as_tensor(dest, device=N1.device)])
+        worst = max(worst, float(np.max(np.abs(got - Np[a][keep]) / sg.J[keep])))
+        checked += int(keep.sum())
+    print("one step max |f err|", worst, "links checked", checked)
+    assert checked > 90 * lat.Q
+    assert worst < 2e-6
+
+
 @pytest.mark.parametrize("precision,bound", [("fp16s", 5e-3), ("bf16s", 6e-2)])
 def test_shifted_16bit_storage(precision, bound):
     """FP16/BF16 storage of scaled deviations from the post-collision rest state
