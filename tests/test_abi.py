@@ -71,3 +71,42 @@ def test_argument_errors_without_a_device():
         vlbm.vlbm_mesh_create(vlbm.D2Q9, n, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(topo),
                               1.0, ctypes.byref(h))
     assert e.value.code == vlbm.ERR_ARG and "periodic" in str(e.value)
+
+
+@pytest.mark.parametrize("case", ["empty", "huge", "lattice", "dx", "face", "null"])
+def test_mesh_arguments_rejected_without_a_device(case):
+    """Empty and oversized index boxes, unknown lattices and face kinds, a
+    non-positive dx and null pointers fail with VLBM_ERR_ARG on the host."""
+    import numpy as np
+    from paper_2401_17183_amd import vlbm
+    topo = vlbm.vlbm_topology()
+    h = ctypes.c_void_p()
+    lattice, n, dx = vlbm.D2Q9, [4, 4, 1], 1.0
+    if case == "empty":
+        n = [0, 4, 1]
+    elif case == "huge":
+        n = [1 << 21, 4, 1]
+    elif case == "lattice":
+        lattice = 7
+    elif case == "dx":
+        dx = -1.0
+    elif case == "face":
+        topo.face[0][0] = 5
+    nn = (ctypes.c_int64 * 3)(*n)
+    X = np.zeros(16 * 2)
+    ptr = None if case == "null" else X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    with pytest.raises(vlbm.VlbmError) as e:
+        vlbm.vlbm_mesh_create(lattice, nn, ptr, ctypes.byref(topo), dx, ctypes.byref(h))
+    assert e.value.code == vlbm.ERR_ARG
+
+
+def test_conv_descriptor_rejected_without_a_device():
+    """Channel counts off the multiple of 8, bad strides and upsampling with a
+    stride fail before any device call."""
+    from paper_2401_17183_amd import vlbm
+    for d in (vlbm.conv_desc(1, 8, 8, 12, 16), vlbm.conv_desc(1, 8, 8, 16, 16, stride=3),
+              vlbm.conv_desc(1, 8, 8, 16, 16, upsample=True, stride=2), vlbm.conv_desc(0, 8, 8, 16, 16)):
+        with pytest.raises(vlbm.VlbmError) as e:
+            vlbm.vlbm_conv2d_forward(ctypes.byref(d), ctypes.c_void_p(16), None, ctypes.c_void_p(16), None,
+                                     ctypes.c_void_p(16), None, None)
+        assert e.value.code == vlbm.ERR_ARG

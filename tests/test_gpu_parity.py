@@ -228,6 +228,43 @@ def test_checkpoint_restore_is_bit_exact():
     assert np.array_equal(cpu(s2.populations()), ref)
 
 
+# the smallest meshes the library takes: periodic axes of 2 cells, wall axes of 1
+TINY = [W.affine_mesh("D2Q9", (2, 2), np.eye(2) + 0.1 * np.array([[0, 1], [0, 0]])),
+        W.tanh_channel_2d(3, 1), W.tanh_channel_2d(2, 2),
+        W.affine_mesh("D3Q19", (2, 2, 2), np.eye(3) + 0.1 * np.array([[0, 1, 0], [0, 0, 1], [0, 0, 0]])),
+        W.affine_mesh("D3Q19", (2, 1, 3), np.eye(3), periodic=False)]
+
+
+@pytest.mark.parametrize("w", TINY, ids=lambda w: f"{w['lattice']}-{'x'.join(map(str, w['n']))}")
+def test_degenerate_small_meshes_fp64(w):
+    """Two-cell periodic axes (every link wraps onto the neighbour that is also
+    the opposite neighbour) and one-cell wall axes (every normal link bounces):
+    FP64 parity <= 1e-12 after 20 steps from a random state."""
+    announce(f"tiny mesh {w['lattice']} {w['n']}")
+    n = w["n"]
+    d = len(n)
+    rng = np.random.default_rng(1)
+    rho = 1 + 0.01 * rng.standard_normal(tuple(reversed(n)))
+    u = 0.01 * rng.standard_normal((d,) + tuple(reversed(n)))
+    o = sim_of(w)
+    o.init(rho, u)
+    o.step(20)
+    s, m = gpu_sim(w, rho=rho.ravel(), u=u.reshape(d, -1))
+    s.step(20)
+    err = np.max(np.abs(cpu(s.populations()) - o.N.reshape(o.lat.Q, -1)) / o.geom.J.ravel())
+    print("tiny mesh max |f err|", err)
+    assert err <= 1e-12
+
+
+def test_one_cell_periodic_axis_is_rejected():
+    v = _vlbm()
+    announce("one-cell periodic axis")
+    w = W.affine_mesh("D2Q9", (1, 3), np.eye(2))
+    with pytest.raises(v.VlbmError) as e:
+        gpu_mesh(w)
+    assert e.value.code == v.ERR_ARG and "periodic" in str(e.value)
+
+
 def test_error_paths():
     v = _vlbm()
     w = W.wavy_periodic("D2Q9", (12, 10), 0.1)
