@@ -275,6 +275,39 @@ def surrogate_flops_per_sample(H, W):
     return total
 
 
+def run_train(args, torch, vlbm):
+    """Throughput of the surrogate's training step alone (forward, MSE,
+    backward, Adam; BF16 MFMA) on one minibatch of bump-channel inputs with
+    seeded targets, 128 x 64 cells."""
+    from paper_2401_17183_amd import surrogate as S
+    from paper_2401_17183_amd import workloads as W
+    ws = W.surrogate_meshes(args.batch)
+    H, Wd = ws[0]["n"][1], ws[0]["n"][0]
+    x = torch.tensor(np.stack([S.features(w) for w in ws])).cuda()
+    rng = np.random.default_rng(2401)
+    t = torch.tensor(rng.standard_normal((args.batch, H, Wd, 3)).astype(np.float32)).cuda()
+    net = vlbm.Surrogate(H, Wd, args.batch, S.he_init(2401))
+    for _ in range(args.warmup):
+        net.train_step(x, t, 1e-4, want_loss=False)
+    stream = torch.cuda.current_stream()
+    ms = _timed(torch, stream, lambda n: [net.train_step(x, t, 1e-4, want_loss=False) for _ in range(n)],
+                args.steps)
+    ms_step = ms / args.steps
+    flops = 3 * surrogate_flops_per_sample(H, Wd) * args.batch
+    tf = flops / (ms_step / 1e3) / 1e12
+    net.close()
+    return {
+        "metric": METRIC, "value": round(args.batch / (ms_step / 1e3), 1), "unit": "samples/s (training)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"surrogate training step, minibatch {args.batch}, {Wd}x{H} bump channels",
+                   "flop_per_step": flops},
+        "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tf / 2500.0, 5), "traffic": None,
+                     "kernel": "k_conv_gemm / k_wgrad (forward, input and weight gradients)"},
+    }
+
+
 def run_surrogate(args, torch, vlbm):
     """Steady states of bump channels from the batched solver, training of the
     BF16-MFMA surrogate, then the test meshes solved to r <= 1e-6 from rest
@@ -374,7 +407,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch", "surrogate"])
+    ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch", "surrogate", "train"])
     ap.add_argument("--precision", default="fp32", choices=sorted(STORAGE_BYTES))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file for --workload batch")
     ap.add_argument("--persistent-only", action="store_true",
@@ -404,11 +437,13 @@ def main():
         out = run_batch(args, torch, vlbm)
     elif args.workload == "surrogate":
         out = run_surrogate(args, torch, vlbm)
+    elif args.workload == "train":
+        out = run_train(args, torch, vlbm)
     else:
         out = run_single(args, torch, vlbm)
     if args.copy_ref:
         _copy_ref(torch, out)
-    if not args.no_cpu and args.workload != "surrogate":
+    if not args.no_cpu and args.workload not in ("surrogate", "train"):
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
