@@ -4,7 +4,8 @@ One time step at a cell takes the arrived populations N_a (eq. (adv)) to the
 post-collision ones
 
     N'_a = N_a + Omega_a + dN_a                                   eq. (lbe)
-    Omega_a = -(N_a - J f^eq_a) / tau                             eq. (collide), BGK
+    Omega_a = sum_b M_ab (N_b - J f^eq_b)                         eq. (collide)
+            = -(N_a - J f^eq_a) / tau                             BGK, M = -I / tau
     dN_a = w_a J [ c_a.F / T0 + H2_a : dPi / T0 ]                 eq. (deltaN)
     J F^i = -1/2 sum_a [ A^i_a N'_a + A^i_opp(a) N_a ]            eq. (compo-constr)
     dPi^{ij} = -1/2 (1 - 1/2tau) sum_a c^i_a (A^j_a + A^j_opp(a)) f^eq_a
@@ -28,9 +29,26 @@ Readings:
   1/2 (1 - 1/2tau) (Ut^i rho a_ext^j + rho a_ext^i Ut^j) to dPi; on a uniform
   Cartesian mesh this is second-order (Guo-type) forcing.
 
+General collision matrix (eq. (collide) with eq. (matrix)).  The paper only
+asks of M that it relax the second moment at 1/tau (eq. (matrix)).  The
+library's M is the two-rate family
+    M = -(1/tau_g) I + (1/tau_g - 1/tau) H,
+    H_ab = w_a [1 + c_a.c_b / T0 + H2_a : H2_b / 2],
+H the projector onto the Hermite content up to second order (the span of w,
+w c^i and w H2^{ij}; a projector because the lattice is fourth-order
+isotropic).  The hydrodynamic part of f - f^eq relaxes at 1/tau and all the
+rest (third and higher Hermite content) at 1/tau_g.  tau_g = tau is BGK,
+tau_g = 1 is the regularised collision (the non-hydrodynamic content is
+removed in one step).  Eq. (matrix) and its inverse eq. (matrix2) hold for any
+tau_g as matrix identities, and sum Omega = sum c Omega = 0 because f - f^eq
+carries no mass or momentum.
+
 Pinned by: sum Omega = 0 and sum c Omega = 0 (eq. (conserv)/(omcons)), the three
 moment constraints on dN (eqs. (constraints), (constraint2), (constraint3)),
-F = 0 on a uniform lattice, and the per-cell mid-link momentum identity
+F = 0 on a uniform lattice, eqs. (matrix) and (matrix2) and the spectrum of
+the general M, its reduction to BGK at tau_g = tau and to the textbook
+regularised collision on a uniform lattice at tau_g = 1, and the per-cell
+mid-link momentum identity
     sum_a (c_a + A_a / 2) N'_a = sum_a (c_a - A_opp(a) / 2) N_a + J rho a_ext
 which follows from eq. (constraint2) and eq. (compo-constr) once the fixed
 point has converged (tests/test_oracle_collide.py).
@@ -75,14 +93,28 @@ def inertial_force(lat, J, A, N, Np):
             - 0.5 * np.einsum("ai...,a...->i...", A[lat.opp], N)) / J[None]
 
 
-def collide(geom, tau, N, tol=1e-14, max_iter=50):
+def hydrodynamic_projector(lat):
+    """H (Q, Q): H_ab = w_a [1 + c_a.c_b / T0 + H2_a : H2_b / 2]."""
+    H2 = hermite2(lat)
+    w = lat.w[:, None]
+    return w * (1.0 + lat.cf @ lat.cf.T / lat.T0 + 0.5 * np.einsum("aij,bij->ab", H2, H2))
+
+
+def collision_matrix(lat, tau, tau_g):
+    """M (Q, Q) of eq. (collide): -(1/tau_g) I + (1/tau_g - 1/tau) H."""
+    return -np.eye(lat.Q) / tau_g + (1.0 / tau_g - 1.0 / tau) * hydrodynamic_projector(lat)
+
+
+def collide(geom, tau, N, tol=1e-14, max_iter=50, tau_g=None):
     """Post-collision populations and the converged inertial force.
 
     N (Q, *n) -> (N', info) with info = {F, Ut, U, rho, iters (*n), converged}.
     iters is the per-cell number of fixed-point iterations needed to meet the
-    stopping rule (max_iter + 1 where it never did).
+    stopping rule (max_iter + 1 where it never did).  tau_g None: BGK;
+    otherwise the general collision matrix collision_matrix(lat, tau, tau_g).
     """
     lat = geom.lat
+    M = None if tau_g is None else collision_matrix(lat, tau, tau_g)
     J, A, gup, aext = geom.J, geom.A, geom.gup, geom.aext
     rho, U = moments(lat, J, N)
     F = np.zeros_like(U)
@@ -94,7 +126,11 @@ def collide(geom, tau, N, tol=1e-14, max_iter=50):
         Ut = U + Ft / (2.0 * rho[None])
         fe = feq(lat, rho, U, Ut, gup)
         dPi = delta_pi(lat, tau, A, fe, Ut, rho, aext)
-        Np = N - (N - J[None] * fe) / tau + delta_n(lat, J, Ft, dPi)
+        if M is None:
+            Om = -(N - J[None] * fe) / tau
+        else:
+            Om = np.einsum("ab,b...->a...", M, N - J[None] * fe)
+        Np = N + Om + delta_n(lat, J, Ft, dPi)
         Fn = inertial_force(lat, J, A, N, Np)
         change = np.max(np.abs(Fn - F), axis=0)
         newly = (change <= tol * rho) & (iters > max_iter)

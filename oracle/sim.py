@@ -30,8 +30,9 @@ from .stream import FARFIELD, WALL, sources, stream
 
 class Params:
     def __init__(self, tau, body_force=None, rho_inf=1.0, u_inf=None, tol=1e-14,
-                 max_iter=50, stream_only=False):
+                 max_iter=50, stream_only=False, tau_g=None):
         self.tau = float(tau)
+        self.tau_g = None if tau_g is None else float(tau_g)   # None: BGK
         self.body_force = body_force
         self.rho_inf = float(rho_inf)
         self.u_inf = u_inf
@@ -89,7 +90,7 @@ class Sim:
             if self.p.stream_only:
                 Np = self.N
             else:
-                Np, info = _c.collide(self.geom, self.p.tau, self.N, self.p.tol, self.p.max_iter)
+                Np, info = _c.collide(self.geom, self.p.tau, self.N, self.p.tol, self.p.max_iter, self.p.tau_g)
                 if not info["converged"]:
                     raise RuntimeError("collision fixed point did not converge")
             self.N = stream(self.mesh, Np, self.N_inf, self.src)
@@ -98,7 +99,7 @@ class Sim:
 
     def moments(self):
         """rho, Euclidean u = Ut^i g_i, contravariant U and Ut, fixed-point iters."""
-        _, info = _c.collide(self.geom, self.p.tau, self.N, self.p.tol, self.p.max_iter)
+        _, info = _c.collide(self.geom, self.p.tau, self.N, self.p.tol, self.p.max_iter, self.p.tau_g)
         u = np.einsum("i...,ik...->k...", info["Ut"], self.geom.g)
         return {"rho": info["rho"], "u": u, "U": info["U"], "Ut": info["Ut"],
                 "F": info["F"], "iters": info["iters"]}

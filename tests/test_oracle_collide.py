@@ -113,3 +113,133 @@ def test_delta_pi_continuum_limit():
         errs.append(np.max(np.abs(dPi - cont)) / np.max(np.abs(cont)))
     assert errs[1] < errs[0] / 3.0, errs
     assert errs[1] < 0.05, errs
+
+
+# ---- general collision matrix (eq. (collide) with eq. (matrix)) ----
+
+LATS = [lattice.D2Q9, lattice.D3Q19]
+RATES = [(0.8, 1.0), (0.6, 0.7), (1.7, 0.55), (0.9, 1.9)]
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+@pytest.mark.parametrize("tau,tau_g", RATES)
+def test_collision_matrix_second_moment(lat, tau, tau_g):
+    """sum_a c_a c_a M_ab = -(1/tau) c_b c_b (eq. (matrix)) for every column b
+    and every rate of the non-hydrodynamic part."""
+    M = C.collision_matrix(lat, tau, tau_g)
+    c = lat.cf
+    lhs = np.einsum("ai,aj,ab->ijb", c, c, M)
+    rhs = -np.einsum("bi,bj->ijb", c, c) / tau
+    assert np.max(np.abs(lhs - rhs)) < 1e-14
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+@pytest.mark.parametrize("tau,tau_g", RATES)
+def test_collision_matrix_inverse_second_moment(lat, tau, tau_g):
+    """sum_a c_a c_a (M^-1)_ab = -tau c_b c_b (eq. (matrix2)), M^-1 from a
+    general-purpose inverse."""
+    Minv = np.linalg.inv(C.collision_matrix(lat, tau, tau_g))
+    c = lat.cf
+    lhs = np.einsum("ai,aj,ab->ijb", c, c, Minv)
+    rhs = -tau * np.einsum("bi,bj->ijb", c, c)
+    assert np.max(np.abs(lhs - rhs)) < 1e-12 * max(tau, tau_g)
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+def test_collision_matrix_spectrum(lat):
+    """-1/tau on the 1 + d + d(d+1)/2 Hermite modes up to second order, -1/tau_g
+    on the remaining Q - that many; H is a projector of that rank."""
+    tau, tau_g = 0.7, 1.3
+    d = lat.d
+    nh = 1 + d + d * (d + 1) // 2
+    H = C.hydrodynamic_projector(lat)
+    assert np.max(np.abs(H @ H - H)) < 1e-14
+    assert np.linalg.matrix_rank(H) == nh
+    ev = np.sort(np.linalg.eigvals(C.collision_matrix(lat, tau, tau_g)).real)
+    want = np.sort(np.r_[np.full(nh, -1.0 / tau), np.full(lat.Q - nh, -1.0 / tau_g)])
+    assert np.max(np.abs(ev - want)) < 1e-12
+
+
+@pytest.mark.parametrize("wl", CASES, ids=lambda w: w["name"])
+def test_general_collision_at_tau_g_equal_tau_is_bgk(wl):
+    s = sim_of(wl)
+    N = near_equilibrium_state(s)
+    Np0, i0 = C.collide(s.geom, s.p.tau, N)
+    Np1, i1 = C.collide(s.geom, s.p.tau, N, tau_g=s.p.tau)
+    assert i0["converged"] and i1["converged"]
+    assert np.max(np.abs(Np1 - Np0)) < 1e-15 * np.abs(N).max() * s.lat.Q
+    assert np.max(np.abs(i1["F"] - i0["F"])) < 1e-15
+
+
+def general_pieces(s, N, tau_g):
+    Np, info = C.collide(s.geom, s.p.tau, N, tau_g=tau_g)
+    assert info["converged"]
+    g = s.geom
+    fe = feq(s.lat, info["rho"], info["U"], info["Ut"], g.gup)
+    Ft = info["F"] + info["rho"][None] * g.aext
+    dPi = C.delta_pi(s.lat, s.p.tau, g.A, fe, info["Ut"], info["rho"], g.aext)
+    dN = C.delta_n(s.lat, g.J, Ft, dPi)
+    return Np, info, Np - N - dN, fe
+
+
+@pytest.mark.parametrize("wl", CASES, ids=lambda w: w["name"])
+@pytest.mark.parametrize("tau_g", [1.0, 0.62, 1.6])
+def test_general_collision_conserves_and_keeps_mid_link_identity(wl, tau_g):
+    """sum Omega = sum c Omega = 0 (eqs. (conserv), (omcons)) and the mid-link
+    momentum identity with a non-BGK M; the non-hydrodynamic part changes the
+    result."""
+    s = sim_of(wl)
+    N = near_equilibrium_state(s)
+    Np, info, Om, _ = general_pieces(s, N, tau_g)
+    c = s.lat.cf
+    g = s.geom
+    scale = np.abs(N).max() * s.lat.Q
+    assert np.max(np.abs(Om.sum(0))) < 1e-14 * scale
+    assert np.max(np.abs(np.einsum("ai,a...->i...", c, Om))) < 1e-14 * scale
+    lhs = np.einsum("ai,a...->i...", c, Np) + 0.5 * np.einsum("ai...,a...->i...", g.A, Np)
+    rhs = (np.einsum("ai,a...->i...", c, N) - 0.5 * np.einsum("ai...,a...->i...", g.A[s.lat.opp], N)
+           + g.J[None] * info["rho"][None] * g.aext)
+    assert np.max(np.abs(lhs - rhs)) < 1e-13 * g.J.max()
+    Np0, _ = C.collide(s.geom, s.p.tau, N)
+    assert np.max(np.abs(Np - Np0)) > 1e-6 * np.abs(N).max()
+
+
+@pytest.mark.parametrize("wl", CASES, ids=lambda w: w["name"])
+def test_general_collision_stress_relaxes_at_tau(wl):
+    """The second moment of Omega is -(1/tau) times that of N - J f^eq whatever
+    tau_g is (eq. (matrix) acting on the non-equilibrium part)."""
+    s = sim_of(wl)
+    N = near_equilibrium_state(s)
+    c = s.lat.cf
+    for tau_g in (1.0, 1.7):
+        _, _, Om, fe = general_pieces(s, N, tau_g)
+        neq = N - s.geom.J[None] * fe
+        lhs = np.einsum("ai,aj,a...->ij...", c, c, Om)
+        rhs = -np.einsum("ai,aj,a...->ij...", c, c, neq) / s.p.tau
+        assert np.max(np.abs(lhs - rhs)) < 1e-14 * np.abs(N).max() * s.lat.Q
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+def test_regularised_collision_on_uniform_lattice(name):
+    """tau_g = 1 on a uniform Cartesian lattice is the textbook regularised BGK:
+    N' = J f^eq + (1 - 1/tau) w_a (c_a c_a - T0 I) : Pi_neq / (2 T0^2) with
+    Pi_neq = sum_b c_b c_b (N_b - J f^eq_b) (F = 0 and dN = 0 there)."""
+    d = 2 if name == "D2Q9" else 3
+    n = (6, 5) if d == 2 else (4, 5, 3)
+    wl = W.affine_mesh(name, n, 1.3 * np.eye(d))
+    s = sim_of(wl, tau=0.73)
+    N = near_equilibrium_state(s, amp=3e-2)
+    Np, info = C.collide(s.geom, s.p.tau, N, tau_g=1.0)
+    assert np.max(np.abs(info["F"])) < 1e-15   # zero up to the rounding of A on the scaled mesh
+    lat = s.lat
+    J = s.geom.J
+    fe = feq(lat, info["rho"], info["U"], info["Ut"], s.geom.gup)
+    neq = N - J[None] * fe
+    Pi = np.einsum("ai,aj,a...->ij...", lat.cf, lat.cf, neq)
+    Hs = np.einsum("ai,aj->aij", lat.cf, lat.cf) - lat.T0 * np.eye(d)[None]
+    reg = lat.w.reshape((-1,) + (1,) * d) * np.einsum("aij,ij...->a...", Hs, Pi) / (2 * lat.T0 ** 2)
+    want = J[None] * fe + (1 - 1 / s.p.tau) * reg
+    assert np.max(np.abs(Np - want)) < 1e-15 * np.abs(N).max() * lat.Q
+    # and it differs from BGK by the non-hydrodynamic content of N - J f^eq
+    Np0, _ = C.collide(s.geom, s.p.tau, N)
+    assert np.max(np.abs(Np0 - want)) > 1e-4 * np.abs(N).max()

@@ -8,11 +8,13 @@ from paper_2401_17183_amd import workloads as W
 from tests.oracle_helpers import near_equilibrium_state, sim_of
 
 
+@pytest.mark.parametrize("tau_g", [None, 1.0], ids=["bgk", "regularised"])
 @pytest.mark.parametrize("wl", [W.tanh_channel_2d(8, 16), W.wavy_channel_3d(8, 8, 6)], ids=lambda w: w["name"])
-def test_mass_and_mid_link_momentum_balance(wl):
+def test_mass_and_mid_link_momentum_balance(wl, tau_g):
     """Mass is exact; I(t+1) = I(t) + G * mass + W(t) (derived from
-    eq. (constraints) and eq. (adv)), to roundoff, every step."""
-    s = sim_of(wl)
+    eq. (constraints) and eq. (adv)), to roundoff, every step; with BGK and with
+    the general collision matrix."""
+    s = sim_of(wl, tau_g=tau_g)
     near_equilibrium_state(s, amp=1e-3)
     M0 = s.N.sum()
     I0 = s.momentum_I()
@@ -98,13 +100,13 @@ def test_poiseuille_needs_the_inertial_force(monkeypatch):
     assert bad > 30 * good, (good, bad)
 
 
-def shear_wave_rate(wl, steps=200, u0=1e-3):
+def shear_wave_rate(wl, steps=200, u0=1e-3, tau_g=None):
     """Decay rate of a shear wave u_x = u0 sin(k y), measured on the difference
     from a run started at rest on the same mesh (which removes the small
     stationary truncation-error currents of a curvilinear mesh)."""
     runs = []
     for amp in (u0, 0.0):
-        s = sim_of(wl)
+        s = sim_of(wl, tau_g=tau_g)
         m = s.mesh
         L = m.n[1] * m.dx
         y = m.coords[..., 1]
@@ -123,11 +125,13 @@ def shear_wave_rate(wl, steps=200, u0=1e-3):
     return -np.log(amps[1] / amps[0]) / steps / (k / m.dx) ** 2
 
 
-@pytest.mark.parametrize("n,amp,tol", [(48, 0.0, 3e-3), (32, 0.2, 2e-2)])
-def test_shear_wave_viscosity(n, amp, tol):
+@pytest.mark.parametrize("n,amp,tol,tau_g", [(48, 0.0, 3e-3, None), (32, 0.2, 2e-2, None),
+                                             (48, 0.0, 3e-3, 1.0), (32, 0.2, 2e-2, 1.0)])
+def test_shear_wave_viscosity(n, amp, tol, tau_g):
     """A decaying shear wave has nu = (tau - 1/2) T0 (Sec. 3, mu = (tau - 1/2) rho T0),
-    on a Cartesian and on a wavy curvilinear periodic mesh."""
+    on a Cartesian and on a wavy curvilinear periodic mesh; with the general
+    collision matrix too, whose stress relaxes at 1/tau by eq. (matrix)."""
     wl = W.wavy_periodic("D2Q9", (n, n), amp)
-    nu_meas = shear_wave_rate(wl)
+    nu_meas = shear_wave_rate(wl, tau_g=tau_g)
     nu = (wl["tau"] - 0.5) / 3.0
     assert abs(nu_meas / nu - 1) < tol, nu_meas / nu
