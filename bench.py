@@ -52,7 +52,7 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(workload="channel", seconds_target=12.0):
+def cpu_baseline(workload="channel", seconds_target=12.0, tau_g=None, tau=None):
     """The FP64 NumPy oracle, one BLAS thread, on a bounded replica of the
     workload (same lattice, stretching, tau and boundaries, fewer cells), stepped
     until ~seconds_target; MLUPS = cell updates / wall time."""
@@ -76,8 +76,9 @@ def cpu_baseline(workload="channel", seconds_target=12.0):
         for w in ws:
             lat = lattice.by_name(w["lattice"])
             m = geometry.Mesh(lat, w["n"], w["coords"], w["faces"], w["wrap"], w["dx"])
-            s = sim.Sim(m, sim.Params(w["tau"], body_force=w.get("body_force", (0, 0, 0)),
-                                      rho_inf=w.get("rho_inf", 1.0), u_inf=w.get("u_inf", (0, 0, 0))))
+            s = sim.Sim(m, sim.Params(w["tau"] if tau is None or workload == "batch" else tau, body_force=w.get("body_force", (0, 0, 0)),
+                                      rho_inf=w.get("rho_inf", 1.0), u_inf=w.get("u_inf", (0, 0, 0)),
+                                      tau_g=tau_g))
             s.init(w.get("rho"), w.get("u"))
             s.step(1)
             sims.append(s)
@@ -151,12 +152,20 @@ def _copy_ref(torch, out):
     out["config"]["copy_ref_GBps"] = round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)
 
 
+def collision_name(tau_g):
+    if tau_g is None:
+        return "BGK"
+    return "regularised (tau_g = 1)" if tau_g == 1.0 else f"general (tau_g = {tau_g})"
+
+
 def run_single(args, torch, vlbm):
     w = make_workload(args.workload)
+    if args.tau is not None:
+        w["tau"] = args.tau
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
     mesh = vlbm.Mesh.from_workload(w)
     p = vlbm.make_params(w["tau"], body_force=w.get("body_force", (0, 0, 0)), rho_inf=w.get("rho_inf", 1.0),
-                         u_inf=w.get("u_inf", (0, 0, 0)), precision=args.precision)
+                         u_inf=w.get("u_inf", (0, 0, 0)), precision=args.precision, tau_g=args.tau_g)
     rho = w.get("rho")
     u = w.get("u")
     sim = vlbm.Sim(mesh, p, rho=None if rho is None else rho.ravel(),
@@ -185,7 +194,8 @@ def run_single(args, torch, vlbm):
         state = str(e)
     traffic = None
     if args.workload == "channel" and args.precision in ("fp32", "fp32c"):
-        traffic = profiled_traffic(f"k_step_d3q19_channel_256x128x128_{args.precision}.md", STEP_SOURCES)
+        tag = ("" if args.tau is None else f"_tau{args.tau:g}") + ("" if args.tau_g is None else f"_taug{args.tau_g:g}")
+        traffic = profiled_traffic(f"k_step_d3q19_channel_256x128x128_{args.precision}{tag}.md", STEP_SOURCES)
     return {
         "metric": METRIC,
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -193,7 +203,7 @@ def run_single(args, torch, vlbm):
         "vs_baseline": None, "dtype": ARITH[args.precision],
         "data": "synthetic",
         "config": {"workload": w["name"] + f" {args.precision.upper()}", "cells": cells, "lattice": w["lattice"],
-                   "tau": w["tau"], "storage": STORAGE[args.precision],
+                   "tau": w["tau"], "collision": collision_name(args.tau_g), "storage": STORAGE[args.precision],
                    "wall_s": round(wall, 3), "finite": finite, "state": state},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -209,7 +219,8 @@ def run_batch(args, torch, vlbm):
     ws = W.batch_meshes(256)
     print("[bench] building 256 bump-channel meshes", file=sys.stderr, flush=True)
     meshes = [vlbm.Mesh.from_workload(w) for w in ws]
-    params = [vlbm.make_params(w["tau"], body_force=w["body_force"], precision=args.precision) for w in ws]
+    params = [vlbm.make_params(w["tau"], body_force=w["body_force"], precision=args.precision, tau_g=args.tau_g)
+              for w in ws]
     b = vlbm.Batch(meshes, params)
     for w, m in zip(ws, b.members):
         rho, u = W.channel_vortex_fields(w)
@@ -413,6 +424,11 @@ def main():
     ap.add_argument("--persistent-only", action="store_true",
                     help="--workload batch: time only the persistent graph-replayed mode (for counter runs)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tau", type=float, default=None,
+                    help="channel / O-grid: override the workload's relaxation time")
+    ap.add_argument("--tau-g", type=float, default=None,
+                    help="general collision matrix: relaxation time of the non-hydrodynamic part "
+                         "(default: BGK; 1 = regularised)")
     ap.add_argument("--train", type=int, default=1024, help="surrogate: training meshes")
     ap.add_argument("--val", type=int, default=128, help="surrogate: validation meshes")
     ap.add_argument("--test", type=int, default=64, help="surrogate: test meshes")
@@ -445,7 +461,7 @@ def main():
         _copy_ref(torch, out)
     if not args.no_cpu and args.workload not in ("surrogate", "train"):
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"] = cpu_baseline(args.workload, tau_g=args.tau_g, tau=args.tau)
     print(json.dumps(out), flush=True)
 
 

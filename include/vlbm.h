@@ -125,6 +125,11 @@ typedef struct {
                             1e-14 FP64, 1e-10 FP32, 1e-7 FP32C)                         */
   int32_t audit_every;   /* enqueue an audit every k steps (0 = never)                 */
   int32_t stream_only;   /* 1: advection only, no collision (a permutation test mode)  */
+  double tau_g;          /* collision matrix of eq. (collide): 0 (or tau) selects BGK,
+                            M = -I / tau; otherwise M = -I / tau_g + (1/tau_g - 1/tau) H,
+                            H the projector onto the Hermite content of order <= 2, so the
+                            stress relaxes at 1/tau (eq. (matrix)) and the rest at 1/tau_g
+                            (1: regularised collision); must exceed 1/2                 */
 } vlbm_params;
 
 /* Create a simulation on a precomputed mesh and set the initial state
@@ -133,13 +138,13 @@ typedef struct {
  * state: this is the library's reading).
  *  rho  device double [cells] or NULL (rho = 1);
  *  u    device double [d][cells] Euclidean velocity or NULL (u = 0).
- * Errors: VLBM_ERR_ARG (tau <= 1/2, bad precision), VLBM_ERR_STATE (geometry
- * not precomputed), VLBM_ERR_NOCONVERGE, VLBM_ERR_NOMEM, VLBM_ERR_DEVICE. */
+ * Errors: VLBM_ERR_ARG (tau <= 1/2, tau_g neither 0 nor above 1/2, bad
+ * precision), VLBM_ERR_STATE (geometry not precomputed), VLBM_ERR_NOCONVERGE, VLBM_ERR_NOMEM, VLBM_ERR_DEVICE. */
 int vlbm_init(vlbm_mesh m, const vlbm_params* p, const double* rho, const double* u,
               void* stream, vlbm_sim* out);
 
-/* Advance nsteps time steps: the fused pull-advection (eq. (adv)) + BGK
- * collision (eq. (collide)) + inertial force (eqs. (compo-constr),
+/* Advance nsteps time steps: the fused pull-advection (eq. (adv)) + collision
+ * (eq. (collide), BGK or the general matrix of tau_g) + inertial force (eqs. (compo-constr),
  * (delta-flux), (deltaN)) + curvilinear equilibrium (eq. (equilibrium)) update
  * of eq. (lbe), with the implicit force solved per cell as a converged fixed
  * point.  Asynchronous: returns after enqueueing on the sim's stream. */

@@ -20,14 +20,16 @@ namespace vlbm {
 namespace {
 
 // FF = 0 when no member has far-field links, else 2 (per-member run-time test).
-template <class L, class P, class S, class T, int BLOCK, int FF>
+// GEN: some member uses a general collision matrix; members stepped with
+// the BGK matrix then take the same arithmetic with tau_g = tau (c1 = 0).
+template <class L, class P, class S, class T, int BLOCK, int FF, bool GEN>
 __global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_batch(const StepArgs<P, S, T>* __restrict__ args,
                                                                 const Tile* __restrict__ tiles, int ntiles,
                                                                 int parity) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile tl = tiles[t];
     const StepArgs<P, S, T> a = args[2 * tl.mesh + parity];
-    step_cell<L, P, S, T, BLOCK, FF>(a, tl.first + threadIdx.x);
+    step_cell<L, P, S, T, BLOCK, FF, GEN>(a, tl.first + threadIdx.x);
   }
 }
 
@@ -81,8 +83,12 @@ template <class L, class P, class S, class T, int BLOCK>
 hipError_t launch_batch_typed(BatchObj* b, int parity) {
   const int grid = b->grid_per_cu > 0 ? std::min(b->ntiles, b->grid_per_cu * b->cus) : b->ntiles;
   const StepArgs<P, S, T>* args = static_cast<const StepArgs<P, S, T>*>(b->d_args);
-  if (b->any_ff) k_batch<L, P, S, T, BLOCK, 2><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
-  else k_batch<L, P, S, T, BLOCK, 0><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
+  if (b->any_general)
+    k_batch<L, P, S, T, BLOCK, 2, true><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
+  else if (b->any_ff)
+    k_batch<L, P, S, T, BLOCK, 2, false><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
+  else
+    k_batch<L, P, S, T, BLOCK, 0, false><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct BatchObj {
   int64_t t = 0;
   int64_t total_cells = 0;
   bool any_ff = false;               // some member has far-field links
+  bool any_general = false;          // some member uses a general collision matrix
   const double** d_rsrc = nullptr;   // per member: address of its latest audit's residual
   double* d_resid = nullptr;         // gathered residuals [count]
 };

@@ -285,6 +285,8 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   *out = nullptr;
   if (!m->have_geometry) return fail(VLBM_ERR_STATE, "vlbm_init before vlbm_geometry_precompute");
   if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(VLBM_ERR_ARG, "tau must exceed 1/2 (got %g)", p->tau);
+  if (p->tau_g != 0.0 && (!(p->tau_g > 0.5) || !isfinite(p->tau_g)))
+    return fail(VLBM_ERR_ARG, "tau_g must be 0 (BGK) or exceed 1/2 (got %g)", p->tau_g);
   if (p->precision < VLBM_FP64 || p->precision > VLBM_FP32C)
     return fail(VLBM_ERR_UNSUPPORTED, "precision %d is not built", p->precision);
   if (p->audit_every < 0) return fail(VLBM_ERR_ARG, "audit_every must be >= 0");
@@ -547,6 +549,7 @@ int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int co
     b->members.push_back(s);
     b->total_cells += m->box.ncells;
     b->any_ff = b->any_ff || s->has_farfield;
+    b->any_general = b->any_general || general_collision(s->p);
   }
   if (batch_upload(b) != hipSuccess) {
     fail(VLBM_ERR_DEVICE, "batch upload failed");

@@ -237,6 +237,10 @@ struct SimObj {
   int* flags = nullptr;         // device int[4]: 0 = unconverged count, 1 = max iters
 };
 
+// The general collision matrix is used when tau_g is set and differs from tau
+// (tau_g = tau is BGK exactly).
+inline int general_collision(const vlbm_params& p) { return p.tau_g != 0.0 && p.tau_g != p.tau ? 1 : 0; }
+
 inline bool storage_is_fp64(int precision) { return precision == VLBM_FP64; }
 inline bool storage_is_16(int precision) { return precision == VLBM_FP16S || precision == VLBM_BF16S; }
 inline size_t pop_elem(int precision) {

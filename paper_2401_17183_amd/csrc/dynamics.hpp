@@ -79,6 +79,62 @@ __device__ __forceinline__ void a_pair(const CellGeo<L, T, AT, ST>& g, int p, in
   }
 }
 
+// Collision matrix of eq. (collide): M = -s I + (s - 1/tau) H, with H the
+// projector onto the Hermite content of order <= 2 (the span of w, w c and
+// w H2).  Every such M satisfies eq. (matrix); s = 1/tau is BGK and s = 1 the
+// regularised collision.  Applied to f - f^eq, which carries no mass and no
+// momentum,
+//   Omega_a = -s (N_a - J f^eq_a) + (s - 1/tau) w_a H2_a : Pi_neq / (2 T0),
+//   Pi_neq  = sum_a c_a c_a (N_a - J f^eq_a) = S2 - J rho (T0 g + Ut Ut),
+// S2 = sum_a c_a c_a N_a (the second moment of f^eq is exact on the lattice).
+// The second term has the w H2 : . / T0 form of dN, so the collision is BGK at
+// rate s with c1 Pi_neq / J (c1 = (s - 1/tau) / 2) added to dPi inside dN.
+template <class T> struct Relax {
+  T tau;
+  T s;          // rate of the non-hydrodynamic part (1/tau for BGK)
+  T c1;         // (s - 1/tau) / 2
+  int general;  // 0: BGK (c1 = 0, the stress terms are skipped)
+};
+
+template <class T>
+__device__ __forceinline__ Relax<T> make_relax(T tau, T tau_g, int general) {
+  Relax<T> r;
+  const T inv_tau = T(1) / tau;
+  r.tau = tau;
+  r.general = general;
+  r.s = general ? T(1) / tau_g : inv_tau;
+  r.c1 = general ? T(0.5) * (r.s - inv_tau) : T(0);
+  return r;
+}
+
+// S2 = sum_a c_a c_a N_a (upper triangle) scaled by f; returns its trace.
+template <class L, class T, class NS>
+__device__ __forceinline__ T second_moment(const NS* N, T f, T* S2) {
+  constexpr int D = L::D;
+#pragma unroll
+  for (int k = 0; k < nup<D>(); ++k) S2[k] = 0;
+#pragma unroll
+  for (int a = 1; a < L::Q; ++a) {
+    const T n = T(N[a]);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i; j < D; ++j) {
+        const int cc = L::c(a, i) * L::c(a, j);
+        if (cc != 0) S2[up<D>(i, j)] += T(cc) * n;
+      }
+  }
+  T tr = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      S2[up<D>(i, j)] *= f;
+      if (i == j) tr += S2[up<D>(i, j)];
+    }
+  return tr;
+}
+
 // Per-cell scalars of the equilibrium that do not depend on the direction.
 template <class L, class T> struct EqCoef {
   T rho, trG, U[L::D], Ut[L::D], r[L::D];
@@ -204,28 +260,35 @@ __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const E
   }
 }
 
-// Pass 2: Y^i = sum_a A^i_a dN_a.
+// Pass 2: Y^i = sum_a A^i_a dN_a, dN with the volume J.
 template <class L, class T, class AT, int ST, int a = 1>
-__device__ __forceinline__ void pass_dn(const CellGeo<L, T, AT, ST>& g, const T* Ft, const T* dpi, T trdpi, T* Y) {
+__device__ __forceinline__ void pass_dn_j(const CellGeo<L, T, AT, ST>& g, T J, const T* Ft, const T* dpi, T trdpi,
+                                          T* Y) {
   if constexpr (a < L::Q) {
     T ap[L::D], am[L::D];
     a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
-    const T dp = delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
-    const T dm = delta_n_dir<L, T, a + 1>(g.j(), Ft, dpi, trdpi);
+    const T dp = delta_n_dir<L, T, a>(J, Ft, dpi, trdpi);
+    const T dm = delta_n_dir<L, T, a + 1>(J, Ft, dpi, trdpi);
 #pragma unroll
     for (int i = 0; i < L::D; ++i) Y[i] += ap[i] * dp + am[i] * dm;
-    pass_dn<L, T, AT, ST, a + 2>(g, Ft, dpi, trdpi, Y);
+    pass_dn_j<L, T, AT, ST, a + 2>(g, J, Ft, dpi, trdpi, Y);
   }
 }
 
-// Output pass: N'_a = N_a - (N_a - J f^eq_a)/tau + dN_a  (eqs. (lbe), (collide)).
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void pass_dn(const CellGeo<L, T, AT, ST>& g, const T* Ft, const T* dpi, T trdpi, T* Y) {
+  pass_dn_j<L, T, AT, ST>(g, g.j(), Ft, dpi, trdpi, Y);
+}
+
+// Output pass: N'_a = N_a - s (N_a - J f^eq_a) + dN_a  (eqs. (lbe), (collide));
+// s = 1/tau for BGK, and dPi carries the stress term of a general M.
 template <class L, class T, class AT, int ST, class NS, int a = 0>
 __device__ __forceinline__ void pass_out(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, const NS* N, const T* Ft,
-                                         const T* dpi, T trdpi, T inv_tau, T* Np) {
+                                         const T* dpi, T trdpi, T s, T* Np) {
   if constexpr (a < L::Q) {
     const T n = T(N[a]);
-    Np[a] = n - (n - g.j() * feq_dir<L, T, AT, ST, a>(g, e)) * inv_tau + delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
-    pass_out<L, T, AT, ST, NS, a + 1>(g, e, N, Ft, dpi, trdpi, inv_tau, Np);
+    Np[a] = n - (n - g.j() * feq_dir<L, T, AT, ST, a>(g, e)) * s + delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
+    pass_out<L, T, AT, ST, NS, a + 1>(g, e, N, Ft, dpi, trdpi, s, Np);
   }
 }
 
@@ -249,7 +312,7 @@ __device__ __forceinline__ T finish_dpi(const CellGeo<L, T, AT, ST>& g, T (*M)[L
 // State of one cell's collision between its phases.
 template <class L, class T> struct CollState {
   T rho, invJ, half_inv_rho, cJ;
-  T U[L::D], BC[L::D];          // BC = B - (1 - 1/tau) C / 2 (constant part of J F)
+  T U[L::D], BC[L::D];          // BC = B - (1 - s) C / 2 - Z / 2 (constant part of J F)
   T Ut[L::D], Ft[L::D];
   T dpi[nup<L::D>()], trdpi;
   EqCoef<L, T> e;
@@ -258,9 +321,12 @@ template <class L, class T> struct CollState {
 
 // Phase 1: moments (eqs. (dist), (moments), (vcurvi)) and the parts of
 // eq. (compo-constr) that do not change during the fixed point:
-//   B^i = -1/2 sum_a A^i_opp(a) N_a  and  C^i = sum_a A^i_a N_a.
+//   B^i = -1/2 sum_a A^i_opp(a) N_a,  C^i = sum_a A^i_a N_a  and, for a general
+//   M, Z^i = sum_a A^i_a dN_a(F = 0, dPi = c1 S2 / J) (the population part of
+//   the stress term, linear in dPi).
 template <class L, class T, class AT, int ST, class NS>
-__device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, const NS* N, T tau, CollState<L, T>& st) {
+__device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r,
+                                                CollState<L, T>& st) {
   constexpr int D = L::D;
   constexpr int Q = L::Q;
   T rhoJ = 0;
@@ -280,15 +346,25 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
       }
     }
   }
-  const T inv_tau = T(1) / tau;
   st.rho = rhoJ / g.j();
   st.invJ = T(1) / g.j();
   st.half_inv_rho = T(0.5) / st.rho;
-  st.cJ = g.j() * inv_tau;
+  st.cJ = g.j() * r.s;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     st.U[i] = mom[i] / rhoJ;
-    st.BC[i] = B[i] - T(0.5) * (T(1) - inv_tau) * C[i];
+    st.BC[i] = B[i] - T(0.5) * (T(1) - r.s) * C[i];
+  }
+  if (r.general) {   // wave-uniform
+    // dN is J times a function of dPi: with J = 1 and dPi = c1 S2 the product
+    // J dPi = c1 S2 is the same
+    T S2[nup<D>()], Z[D], zero[D];
+    const T tr = second_moment<L, T, NS>(N, r.c1, S2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) Z[i] = zero[i] = 0;
+    pass_dn_j<L, T, AT, ST>(g, T(1), zero, S2, tr, Z);
+#pragma unroll
+    for (int i = 0; i < D; ++i) st.BC[i] -= T(0.5) * Z[i];
   }
 }
 
@@ -298,13 +374,15 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
 // (0, or the previous step's converged F: the converged fixed point does not
 // depend on it) and the converged F on exit; st keeps the equilibrium, dPi and
 // F_tot of the last iteration for the output phase.  Each iteration uses
-//   sum_a A_a N'_a = (1 - 1/tau) C + (J/tau) sum_a A_a f^eq_a + sum_a A_a dN_a
-// so that no per-direction array is live inside the loop.
+//   sum_a A_a N'_a = (1 - s) C + J s sum_a A_a f^eq_a + sum_a A_a dN_a
+// so that no per-direction array is live inside the loop (s = 1/tau for BGK;
+// for a general M, dN includes the stress term, whose population part Z is
+// constant and sits in BC).
 template <class L, class T, class AT, int ST>
-__device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, T tau, T tol, int max_iter, T* F,
-                                                CollState<L, T>& st, int min_iter = 1) {
+__device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, const Relax<T>& r, T tol, int max_iter,
+                                                T* F, CollState<L, T>& st, int min_iter = 1) {
   constexpr int D = L::D;
-  const T k = T(1) - T(0.5) / tau;
+  const T k = T(1) - T(0.5) / r.tau;
   int it = 1;
   int done = 0;
   CellGeo<L, T, AT, ST> gl = g;
@@ -330,6 +408,16 @@ __device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, 
     }
     pass_feq<L, T, AT, ST, false>(gl, st.e, X, nullptr, M);
     st.trdpi = finish_dpi<L, T, AT, ST>(gl, M, st.Ut, rho_l, k, st.dpi);
+    if (r.general) {   // wave-uniform: the f^eq part of the stress term, -c1 rho (T0 g + Ut Ut)
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+          const T v = r.c1 * rho_l * (T(T0) * gval(gl, i, j) + st.Ut[i] * st.Ut[j]);
+          st.dpi[up<D>(i, j)] -= v;
+          if (i == j) st.trdpi -= v;
+        }
+    }
     T Y[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) Y[i] = 0;
@@ -350,11 +438,21 @@ __device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, 
   st.iters = done ? it : max_iter + 1;
 }
 
-// Phase 3: N' of the last iteration (eqs. (lbe), (collide), (deltaN)).
+// Phase 3: N' of the last iteration (eqs. (lbe), (collide), (deltaN)); for a
+// general M the population part c1 S2 / J of the stress term joins dPi here.
 template <class L, class T, class AT, int ST, class NS>
-__device__ __forceinline__ void collide_output(const CellGeo<L, T, AT, ST>& g, const NS* N, T tau, const CollState<L, T>& st,
-                                               T* Np) {
-  pass_out<L, T, AT, ST, NS>(g, st.e, N, st.Ft, st.dpi, st.trdpi, T(1) / tau, Np);
+__device__ __forceinline__ void collide_output(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r,
+                                               const CollState<L, T>& st, T* Np) {
+  if (r.general) {
+    T dpi[nup<L::D>()];
+    T tr = second_moment<L, T, NS>(N, r.c1 * st.invJ, dpi);
+#pragma unroll
+    for (int k = 0; k < nup<L::D>(); ++k) dpi[k] += st.dpi[k];
+    tr += st.trdpi;
+    pass_out<L, T, AT, ST, NS>(g, st.e, N, st.Ft, dpi, tr, r.s, Np);
+  } else {
+    pass_out<L, T, AT, ST, NS>(g, st.e, N, st.Ft, st.dpi, st.trdpi, r.s, Np);
+  }
 }
 
 struct CollideOut {
@@ -363,12 +461,12 @@ struct CollideOut {
 
 // The whole collision of one cell with N held in registers throughout.
 template <class L, class T, class AT, int ST, class NS>
-__device__ __forceinline__ CollideOut collide(const CellGeo<L, T, AT, ST>& g, const NS* N, T tau, T tol, int max_iter,
-                                              T* Np, T* F, T* Ut_out, T* U_out, T& rho_out) {
+__device__ __forceinline__ CollideOut collide(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r, T tol,
+                                              int max_iter, T* Np, T* F, T* Ut_out, T* U_out, T& rho_out) {
   CollState<L, T> st;
-  collide_prepare<L, T, AT, ST, NS>(g, N, tau, st);
-  collide_iterate<L, T, AT, ST>(g, tau, tol, max_iter, F, st);
-  collide_output<L, T, AT, ST, NS>(g, N, tau, st, Np);
+  collide_prepare<L, T, AT, ST, NS>(g, N, r, st);
+  collide_iterate<L, T, AT, ST>(g, r, tol, max_iter, F, st);
+  collide_output<L, T, AT, ST, NS>(g, N, r, st, Np);
 #pragma unroll
   for (int i = 0; i < L::D; ++i) {
     Ut_out[i] = st.Ut[i];

@@ -18,8 +18,8 @@ template <class S> struct StateArgs {
   const double* g;     // [d][d][cells]
   const double* A;     // [Q][d][cells]
   double G[3], uinf[3];
-  double rho_inf, tau, tol;
-  int max_iter;
+  double rho_inf, tau, tau_g, tol;
+  int general, max_iter;
   const S* in;         // populations to gather from (N'(t-1))
   S* out;              // populations to scatter into
   const S* rsrc;       // 16-bit modes: reference of each arriving link
@@ -187,7 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_refs_own(StateArgs<S> a) {
   if (!consistent_equilibrium<L, double>(g, 1.0, Ut, a.tau, a.tol, a.max_iter, N, F)) atomicAdd(a.flag, 1);
   double Np[L::Q], U[D], rho;
   for (int i = 0; i < D; ++i) F[i] = 0;
-  const CollideOut o = collide<L, double, double, 0, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
+  const CollideOut o = collide<L, double, double, 0, double>(g, N, make_relax<double>(a.tau, a.tau_g, a.general), a.tol,
+                                                         a.max_iter, Np, F, Ut, U, rho);
   if (o.iters > a.max_iter) atomicAdd(a.flag, 1);
   for (int al = 0; al < L::Q; ++al) a.rown[al * nc + cell] = S(Np[al]);
 }
@@ -226,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(StateArgs<S> a) {
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
   double Np[L::Q], F[D], Ut[D], U[D], rho;
   for (int i = 0; i < D; ++i) F[i] = 0;
-  const CollideOut o = collide<L, double, double, 0, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
+  const CollideOut o = collide<L, double, double, 0, double>(g, N, make_relax<double>(a.tau, a.tau_g, a.general), a.tol,
+                                                         a.max_iter, Np, F, Ut, U, rho);
   if (o.iters > a.max_iter) atomicAdd(a.flag, 1);
   a.rho_out[cell] = rho;
   for (int k = 0; k < D; ++k) {
@@ -292,7 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
     if (!nonfinite) {
       double Np[Q], F[D], Ut[D], U[D], rho;
       for (int i = 0; i < D; ++i) F[i] = 0;
-      const CollideOut o = collide<L, double, double, 0, double>(g, N, a.tau, a.tol, a.max_iter, Np, F, Ut, U, rho);
+      const CollideOut o = collide<L, double, double, 0, double>(g, N, make_relax<double>(a.tau, a.tau_g, a.general), a.tol,
+                                                         a.max_iter, Np, F, Ut, U, rho);
       v[11] = o.iters > a.max_iter ? 1.0 : 0.0;
       v[12] = o.iters;
       double du2 = 0, uu = 0;
@@ -378,6 +381,8 @@ StateArgs<S> make_args(SimObj* s) {
   }
   a.rho_inf = s->p.rho_inf;
   a.tau = s->p.tau;
+  a.general = general_collision(s->p);
+  a.tau_g = a.general ? s->p.tau_g : s->p.tau;
   // the FP64 dry run converges to FP64 roundoff whatever the storage precision
   a.tol = fmin(s->p.fp_tol, 1e-13);
   a.max_iter = s->p.fp_max_iter;

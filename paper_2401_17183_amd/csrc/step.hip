@@ -1,5 +1,5 @@
-// The fused time step: pull advection (eq. (adv)) + BGK collision with the
-// implicit inertial force (eqs. (lbe), (collide), (compo-constr), (delta-flux),
+// The fused time step: pull advection (eq. (adv)) + collision (eq. (collide))
+// with the implicit inertial force (eqs. (lbe), (collide), (compo-constr), (delta-flux),
 // (deltaN), (equilibrium)), one thread per cell, SoA populations, A/B buffers.
 #include "stepcore.hpp"
 
@@ -11,15 +11,16 @@ constexpr int kBlock = 256;
 // FP32 geometry: two waves per SIMD (see VLBM_STEP_ATTR).
 // FF = 0 when the mesh has no far-field links, else 2 (wave-uniform run-time
 // test, which keeps the far-field variant free of spills).
-template <class L, class P, class S, class T, int FF>
+// GEN: general collision matrix (its own instantiation, always with FF = 2).
+template <class L, class P, class S, class T, int FF, bool GEN>
 __global__ __launch_bounds__(kBlock) VLBM_STEP_ATTR void k_step(StepArgs<P, S, T> a) {
-  step_cell<L, P, S, T, kBlock, FF>(a, blockIdx.x * kBlock + threadIdx.x);
+  step_cell<L, P, S, T, kBlock, FF, GEN>(a, blockIdx.x * kBlock + threadIdx.x);
 }
 
 // FP64 storage keeps A in registers and runs at the occupancy the compiler picks.
-template <class L, class P, class S, class T, int FF>
+template <class L, class P, class S, class T, int FF, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_step64(StepArgs<P, S, T> a) {
-  step_cell<L, P, S, T, kBlock, FF>(a, blockIdx.x * kBlock + threadIdx.x);
+  step_cell<L, P, S, T, kBlock, FF, GEN>(a, blockIdx.x * kBlock + threadIdx.x);
 }
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
@@ -55,11 +56,13 @@ hipError_t step_typed(SimObj* s) {
   const StepArgs<P, S, T> a = make_step_args<P, S, T>(s);
   const int nb = (a.box.ncells + kBlock - 1) / kBlock;
   if constexpr (sizeof(S) == 8) {
-    if (a.has_ff) k_step64<L, P, S, T, 2><<<nb, kBlock, 0, s->stream>>>(a);
-    else k_step64<L, P, S, T, 0><<<nb, kBlock, 0, s->stream>>>(a);
+    if (a.general) k_step64<L, P, S, T, 2, true><<<nb, kBlock, 0, s->stream>>>(a);
+    else if (a.has_ff) k_step64<L, P, S, T, 2, false><<<nb, kBlock, 0, s->stream>>>(a);
+    else k_step64<L, P, S, T, 0, false><<<nb, kBlock, 0, s->stream>>>(a);
   } else {
-    if (a.has_ff) k_step<L, P, S, T, 2><<<nb, kBlock, 0, s->stream>>>(a);
-    else k_step<L, P, S, T, 0><<<nb, kBlock, 0, s->stream>>>(a);
+    if (a.general) k_step<L, P, S, T, 2, true><<<nb, kBlock, 0, s->stream>>>(a);
+    else if (a.has_ff) k_step<L, P, S, T, 2, false><<<nb, kBlock, 0, s->stream>>>(a);
+    else k_step<L, P, S, T, 0, false><<<nb, kBlock, 0, s->stream>>>(a);
   }
   return hipGetLastError();
 }

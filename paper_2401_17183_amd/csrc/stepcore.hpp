@@ -1,7 +1,8 @@
 // Core of the fused time step shared by the single-mesh and the batched
-// kernels: pull advection (eq. (adv)) + BGK collision with the implicit
-// inertial force (eqs. (lbe), (collide), (compo-constr), (delta-flux),
-// (deltaN), (equilibrium)), one thread per cell, SoA populations.
+// kernels: pull advection (eq. (adv)) + collision (BGK, or a general matrix
+// that satisfies eq. (matrix)) with the implicit inertial force (eqs. (lbe),
+// (collide), (compo-constr), (delta-flux), (deltaN), (equilibrium)), one
+// thread per cell, SoA populations.
 #pragma once
 
 #include <type_traits>
@@ -26,7 +27,8 @@ template <class P, class S, class T> struct StepArgs {
   const P* __restrict__ rown;   // 16-bit modes: reference of each written slot
   float scale, inv_scale;
   const S* __restrict__ geo;
-  T tau, tol, rho_inf;
+  T tau, tau_g, tol, rho_inf;
+  int general;                  // collision matrix other than BGK (tau_g != tau)
   int max_iter, min_iter;
   int stream_only;
   int has_force, has_ff;
@@ -125,7 +127,9 @@ __device__ __forceinline__ void store_slot(const StepArgs<P, S, T>& a, int al, i
 }
 
 // One cell of one mesh; BLOCK threads per workgroup share the LDS staging.
-template <class L, class P, class S, class T, int BLOCK, int FF = 2>
+// GEN: general collision matrix (compiled separately, so that the BGK kernels
+// carry none of its registers).
+template <class L, class P, class S, class T, int BLOCK, int FF = 2, bool GEN = false>
 __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
@@ -152,8 +156,9 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
 #pragma unroll
   for (int i = 0; i < D; ++i) F[i] = word(a.fcache, i, nc)[cell];
   CollState<L, T> st;
-  collide_prepare<L, T, S, ST, NR>(g, N, a.tau, st);
-  collide_iterate<L, T, S, ST>(g, a.tau, a.tol, a.max_iter, F, st, a.min_iter);
+  const Relax<T> rx = make_relax<T>(a.tau, a.tau_g, GEN ? 1 : 0);
+  collide_prepare<L, T, S, ST, NR>(g, N, rx, st);
+  collide_iterate<L, T, S, ST>(g, rx, a.tol, a.max_iter, F, st, a.min_iter);
   if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
 #pragma unroll
   for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
@@ -177,12 +182,12 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
     P ref[Q];
 #pragma unroll
     for (int al = 0; al < Q; ++al) ref[al] = word(a.rown, al, nc)[cell];
-    collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
+    collide_output<L, T, S, ST, NR>(g, N, rx, st, Np);
 #pragma unroll
     for (int al = 0; al < Q; ++al)
       word(a.out, al, nc)[cell] = PopCodec<P>::template encode<T>(T(Np[al]), ref[al], a.scale);
   } else {
-    collide_output<L, T, S, ST, NR>(g, N, a.tau, st, Np);
+    collide_output<L, T, S, ST, NR>(g, N, rx, st, Np);
 #pragma unroll
     for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, Np[al]);
   }
@@ -201,6 +206,8 @@ inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   a.inv_scale = 1.0f / a.scale;
   a.geo = static_cast<const S*>(s->geo);
   a.tau = T(s->p.tau);
+  a.general = general_collision(s->p);
+  a.tau_g = T(a.general ? s->p.tau_g : s->p.tau);
   a.tol = T(s->p.fp_tol);
   a.rho_inf = T(s->p.rho_inf);
   a.max_iter = s->p.fp_max_iter;

@@ -53,7 +53,8 @@ class vlbm_geom_report(C.Structure):
 class vlbm_params(C.Structure):
     _fields_ = [("tau", C.c_double), ("body_force", C.c_double * 3), ("rho_inf", C.c_double),
                 ("u_inf", C.c_double * 3), ("precision", C.c_int32), ("fp_max_iter", C.c_int32),
-                ("fp_tol", C.c_double), ("audit_every", C.c_int32), ("stream_only", C.c_int32)]
+                ("fp_tol", C.c_double), ("audit_every", C.c_int32), ("stream_only", C.c_int32),
+                ("tau_g", C.c_double)]
 
 
 class vlbm_audit(C.Structure):
@@ -254,9 +255,12 @@ class Mesh:
 
 
 def make_params(tau, body_force=(0, 0, 0), rho_inf=1.0, u_inf=(0, 0, 0), precision=FP64, fp_max_iter=0,
-                fp_tol=-1.0, audit_every=0, stream_only=False):
+                fp_tol=-1.0, audit_every=0, stream_only=False, tau_g=None):
+    """Simulation parameters; tau_g None (or tau) is BGK, otherwise the general
+    collision matrix whose non-hydrodynamic part relaxes at 1/tau_g."""
     p = vlbm_params()
     p.tau = float(tau)
+    p.tau_g = 0.0 if tau_g is None else float(tau_g)
     bf = list(body_force) + [0.0] * (3 - len(body_force))
     ui = list(u_inf) + [0.0] * (3 - len(u_inf))
     for k in range(3):
