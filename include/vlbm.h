@@ -41,8 +41,9 @@ enum { VLBM_D2Q9 = 0, VLBM_D3Q19 = 1 };
  *  FP32   populations and geometry stored in FP32, FP64 arithmetic in registers
  *         (FP32 arithmetic loses the small velocity signal to cancellation);
  *  FP32C  FP32 storage and FP32 arithmetic (faster, less accurate);
- *  FP16S / BF16S  scaled deviations from the per-cell rest equilibrium stored
- *         in 16 bits. */
+ *  FP16S / BF16S  deviations from the per-cell rest equilibrium stored in 16
+ *         bits (FP16: multiplied by the largest power of two up to 4096 that
+ *         keeps deviations up to 4 max J inside FP16's range). */
 enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP16S = 2, VLBM_BF16S = 3, VLBM_FP32C = 4 };
 
 enum { VLBM_PERIODIC = 0, VLBM_WALL = 1, VLBM_FARFIELD = 2 };
@@ -130,6 +131,9 @@ typedef struct {
                             H the projector onto the Hermite content of order <= 2, so the
                             stress relaxes at 1/tau (eq. (matrix)) and the rest at 1/tau_g
                             (1: regularised collision); must exceed 1/2                 */
+  int32_t rebase_every;  /* FP16S / BF16S: every k steps the 16-bit references are re-based
+                            on the current state, so that the stored deviations restart
+                            near zero (0: every 10 steps; < 0: never); ignored otherwise */
 } vlbm_params;
 
 /* Create a simulation on a precomputed mesh and set the initial state
@@ -144,7 +148,8 @@ int vlbm_init(vlbm_mesh m, const vlbm_params* p, const double* rho, const double
               void* stream, vlbm_sim* out);
 
 /* Advance nsteps time steps: the fused pull-advection (eq. (adv)) + collision
- * (eq. (collide), BGK or the general matrix of tau_g) + inertial force (eqs. (compo-constr),
+ * (eq. (collide), BGK or the general matrix of tau_g) (16-bit modes: plus the
+ * re-basing of the references every rebase_every steps) + inertial force (eqs. (compo-constr),
  * (delta-flux), (deltaN)) + curvilinear equilibrium (eq. (equilibrium)) update
  * of eq. (lbe), with the implicit force solved per cell as a converged fixed
  * point.  Asynchronous: returns after enqueueing on the sim's stream. */
@@ -189,8 +194,9 @@ int vlbm_audit_now(vlbm_sim s);
  * non-finite populations (the records are still copied). */
 int vlbm_audits(vlbm_sim s, vlbm_audit* out, int cap, int* n_out);
 
-/* Checkpoint: raw storage-precision populations, step counter and params into
- * host memory.  With buf == NULL only *used (the size needed) is set. */
+/* Checkpoint: raw storage-precision populations, the force cache, the step
+ * counter and (16-bit modes) the references into host memory.  With
+ * buf == NULL only *used (the size needed) is set. */
 int vlbm_save(vlbm_sim s, void* buf, size_t cap, size_t* used);
 /* Restore a checkpoint written by vlbm_save for a sim on the same mesh with the
  * same precision.  Errors: VLBM_ERR_ARG on a size or header mismatch. */

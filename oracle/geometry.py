@@ -9,6 +9,10 @@ Boundary readings (the paper leaves boundaries out of its scope):
 * every non-periodic face carries two ghost node layers in the coordinate
   input, so that g_i exists on the first ghost layer and the contracted
   coefficient A (below) exists on every link of every real cell;
+* lattices with links longer than one cell (D2Q21, D3Q39) take periodic axes
+  only: the wall and far-field readings are for one-cell links.  g_i is then
+  needed s cells beyond every real cell (s the longest link), which the
+  periodic wrap supplies;
 * a periodic axis i wraps the index and translates positions by a constant
   vector L_i: x(q + n_i e_i) = x(q) + L_i.
 
@@ -66,6 +70,8 @@ class Mesh:
         for i in range(self.d):
             self.wrap[i] = np.asarray(wrap[i], dtype=np.float64)[: self.d]
         self.dx = float(dx)
+        if self.lat.speed > 1 and not all(f[0] == PERIODIC for f in self.faces):
+            raise MeshError(f"{self.lat.name} needs periodic axes (its links span {self.lat.speed} cells)")
         self.coords = np.asarray(coords, dtype=np.float64)
         want = tuple(reversed([self.m(i) for i in range(self.d)])) + (self.d,)
         if self.coords.shape != want:
@@ -139,10 +145,17 @@ def _cross3(a, b):
                      a[0] * b[1] - a[1] * b[0]])
 
 
-def basis(mesh):
-    """g_i, J, g^i, g^{ij} on real cells plus one ghost layer.
+def box_layers(mesh):
+    """Layers around the real cells on which basis() gives g_i: the longest
+    link of the lattice (1 for D2Q9 / D3Q19)."""
+    return mesh.lat.speed
 
-    Returns dict with arrays on the box q in [-1, n + 1):
+
+def basis(mesh):
+    """g_i, J, g^i, g^{ij} on real cells plus box_layers(mesh) layers around
+    them (one for D2Q9 / D3Q19).
+
+    Returns dict with arrays on the box q in [-s, n + s), s = box_layers(mesh):
       g    (d, d, *box): g[i] is the tangent vector g_i (eq. (tangent))
       J    (*box)                                   (eq. (jacobian))
       gco  (d, d, *box): gco[i] is the co-tangent g^i (eq. (covectors))
@@ -151,7 +164,8 @@ def basis(mesh):
     Raises MeshError when beta is undefined or J <= 0 anywhere on the box.
     """
     d = mesh.d
-    P = np.moveaxis(padded_coords(mesh, NGHOST), -1, 0)  # (d, *box2)
+    L = box_layers(mesh)
+    P = np.moveaxis(padded_coords(mesh, L + 1), -1, 0)  # (d, *box of L + 1 layers)
     g = []
     beta = []
     for i in range(d):
@@ -159,9 +173,9 @@ def basis(mesh):
         e[i] = 1
         me = [0] * d
         me[i] = -1
-        x0 = _view(P, 1, [0] * d, NGHOST, 1)
-        Dp = _view(P, 1, e, NGHOST, 1) - x0        # D_{+i}
-        Dm = _view(P, 1, me, NGHOST, 1) - x0       # D_{-i}
+        x0 = _view(P, 1, [0] * d, L + 1, L)
+        Dp = _view(P, 1, e, L + 1, L) - x0        # D_{+i}
+        Dm = _view(P, 1, me, L + 1, L) - x0       # D_{-i}
         diff = Dp - Dm
         nd = np.sqrt(np.sum(diff * diff, axis=0))
         if np.any(nd == 0.0):
@@ -197,13 +211,14 @@ def link_coefficients(mesh, bas):
     """
     lat = mesh.lat
     d = mesh.d
+    L = box_layers(mesh)
     g = bas["g"]
-    g0 = _view(g, 2, [0] * d, 1, 0)
-    gco0 = _view(bas["gco"], 2, [0] * d, 1, 0)
+    g0 = _view(g, 2, [0] * d, L, 0)
+    gco0 = _view(bas["gco"], 2, [0] * d, L, 0)
     out = np.zeros((lat.Q, d) + mesh.shape)
     for a in range(lat.Q):
         c = lat.c[a]
-        gs = _view(g, 2, list(c), 1, 0)
+        gs = _view(g, 2, list(c), L, 0)
         e_here = np.einsum("j,jk...->k...", lat.cf[a], g0)
         e_there = np.einsum("j,jk...->k...", lat.cf[a], gs)
         out[a] = np.einsum("k...,ik...->i...", e_there - e_here, gco0)
@@ -214,16 +229,17 @@ def theta(mesh, bas, offset):
     """Theta^i_j(q + offset, q) = [g_j(q + offset) - g_j(q)] . g^i(q) on real
     cells (eq. (gamma)); shape (i, j, *n).  Used by the geometry pins."""
     d = mesh.d
+    L = box_layers(mesh)
     g = bas["g"]
-    g0 = _view(g, 2, [0] * d, 1, 0)
-    gs = _view(g, 2, list(offset), 1, 0)
-    gco0 = _view(bas["gco"], 2, [0] * d, 1, 0)
+    g0 = _view(g, 2, [0] * d, L, 0)
+    gs = _view(g, 2, list(offset), L, 0)
+    gco0 = _view(bas["gco"], 2, [0] * d, L, 0)
     return np.einsum("jk...,ik...->ij...", gs - g0, gco0)
 
 
-def real(field, lead, d):
-    """The real-cell part of a field given on the box q in [-1, n + 1)."""
-    return _view(field, lead, [0] * d, 1, 0)
+def real(field, lead, d, layers=1):
+    """The real-cell part of a field given on the box q in [-layers, n + layers)."""
+    return _view(field, lead, [0] * d, layers, 0)
 
 
 class Geometry:
@@ -239,11 +255,12 @@ class Geometry:
         self.lat = mesh.lat
         d = mesh.d
         bas = basis(mesh)
+        L = box_layers(mesh)
         self.box = bas
-        self.g = real(bas["g"], 2, d)
-        self.J = real(bas["J"], 0, d)
-        self.gco = real(bas["gco"], 2, d)
-        self.gup = real(bas["gup"], 2, d)
+        self.g = real(bas["g"], 2, d, L)
+        self.J = real(bas["J"], 0, d, L)
+        self.gco = real(bas["gco"], 2, d, L)
+        self.gup = real(bas["gup"], 2, d, L)
         self.A = link_coefficients(mesh, bas)
         G = np.zeros(d) if body_force is None else np.asarray(body_force, dtype=np.float64)[:d]
         self.G = G

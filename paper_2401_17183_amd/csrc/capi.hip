@@ -397,10 +397,12 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s) return fail(VLBM_ERR_ARG, "null sim");
   if (nsteps < 0) return fail(VLBM_ERR_ARG, "nsteps < 0");
+  const int rebase = s->p.rebase_every == 0 ? 10 : s->p.rebase_every;
   for (int64_t k = 0; k < nsteps; ++k) {
     HIP_TRY(launch_step(s));
     s->buf ^= 1;
     s->t++;
+    if (rebase > 0 && storage_is_16(s->p.precision) && s->t % rebase == 0) HIP_TRY(launch_rebase(s));
     if (s->p.audit_every > 0 && s->t % s->p.audit_every == 0) {
       int rc = vlbm_audit_now(sh);
       if (rc) return rc;
@@ -459,11 +461,18 @@ int vlbm_audits(vlbm_sim sh, vlbm_audit* out, int cap, int* n_out) {
   return ok();
 }
 
+// 16-bit modes: the checkpoint also holds the writers' references (re-based
+// during the run, so they are part of the state).
+static size_t ref_bytes(const SimObj* s) {
+  return storage_is_16(s->p.precision) ? (size_t)s->mesh->box.ncells * s->mesh->Q * 2 : 0;
+}
+
 int vlbm_save(vlbm_sim sh, void* buf, size_t cap, size_t* used) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s || !used) return fail(VLBM_ERR_ARG, "vlbm_save: null argument");
   const size_t fbytes = (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision);
-  const size_t need = sizeof(CkptHeader) + s->pop_bytes + fbytes;
+  const size_t rbytes = ref_bytes(s);
+  const size_t need = sizeof(CkptHeader) + s->pop_bytes + fbytes + rbytes;
   *used = need;
   if (!buf) return ok();
   if (cap < need) return fail(VLBM_ERR_ARG, "buffer too small: need %zu bytes", need);
@@ -473,6 +482,9 @@ int vlbm_save(vlbm_sim sh, void* buf, size_t cap, size_t* used) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemcpy(static_cast<char*>(buf) + sizeof(h), s->pop[s->buf], s->pop_bytes, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(static_cast<char*>(buf) + sizeof(h) + s->pop_bytes, s->fcache, fbytes, hipMemcpyDeviceToHost));
+  if (rbytes)
+    HIP_TRY(hipMemcpy(static_cast<char*>(buf) + sizeof(h) + s->pop_bytes + fbytes, s->rown, rbytes,
+                      hipMemcpyDeviceToHost));
   return ok();
 }
 
@@ -481,17 +493,23 @@ int vlbm_restore(vlbm_sim sh, const void* buf, size_t size) {
   if (!s || !buf) return fail(VLBM_ERR_ARG, "vlbm_restore: null argument");
   if (size < sizeof(CkptHeader)) return fail(VLBM_ERR_ARG, "checkpoint too small");
   const size_t fbytes = (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision);
+  const size_t rbytes = ref_bytes(s);
   CkptHeader h;
   memcpy(&h, buf, sizeof(h));
   if (h.magic != kMagic || h.lattice != s->mesh->lattice || h.precision != s->p.precision ||
       h.ncells != s->mesh->box.ncells || h.Q != s->mesh->Q || h.bytes != (int64_t)s->pop_bytes ||
-      size != sizeof(h) + s->pop_bytes + fbytes)
+      size != sizeof(h) + s->pop_bytes + fbytes + rbytes)
     return fail(VLBM_ERR_ARG, "checkpoint does not match this simulation");
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemcpy(s->pop[s->buf], static_cast<const char*>(buf) + sizeof(h), s->pop_bytes,
                     hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(s->fcache, static_cast<const char*>(buf) + sizeof(h) + s->pop_bytes, fbytes,
                     hipMemcpyHostToDevice));
+  if (rbytes) {   // the writers' references, then the readers' copies gathered from them
+    HIP_TRY(hipMemcpy(s->rown, static_cast<const char*>(buf) + sizeof(h) + s->pop_bytes + fbytes, rbytes,
+                      hipMemcpyHostToDevice));
+    HIP_TRY(launch_refs_src(s));
+  }
   s->t = h.t;
   s->have_u_prev = 0;
   return ok();

@@ -248,7 +248,18 @@ inline size_t pop_elem(int precision) {
 }
 // scale s of the 16-bit deviations: FP16 needs it to keep small deviations
 // out of its subnormal range, BF16 shares FP32's exponent range
-inline float pop_scale(int precision) { return precision == VLBM_FP16S ? 4096.0f : 1.0f; }
+// Scale of the stored FP16 deviations (N - reference) * scale.  FP16 keeps its
+// relative precision at any scale, but its range ends at 65504: deviations grow
+// with the cell volume J, so the scale is the largest power of two up to 4096
+// that keeps deviations up to 4 J_max representable.
+inline float pop_scale(int precision, double max_J) {
+  if (precision != VLBM_FP16S) return 1.0f;
+  const double jm = max_J > 1e-30 ? max_J : 1e-30;
+  const double cap = 65504.0 / (4.0 * jm);
+  float s = 4096.0f;
+  while (s > 1.0f / 1024.0f && s > cap) s *= 0.5f;
+  return s;
+}
 inline size_t fcache_elem(int precision) {
   return (precision == VLBM_FP32C || storage_is_16(precision)) ? 4 : 8;
 }
@@ -263,6 +274,8 @@ hipError_t launch_get_pop(SimObj* s, double* N);
 hipError_t launch_set_pop(SimObj* s, const double* N);
 hipError_t launch_audit(SimObj* s, int slot);
 hipError_t launch_refs(SimObj* s);
+hipError_t launch_rebase(SimObj* s);     // 16-bit modes: references re-based on the current state
+hipError_t launch_refs_src(SimObj* s);   // 16-bit modes: rsrc gathered again from rown
 
 int geometry_partial_blocks(const MeshObj* m);
 

@@ -193,6 +193,25 @@ __global__ __launch_bounds__(kBlock) void k_refs_own(StateArgs<S> a) {
   for (int al = 0; al < L::Q; ++al) a.rown[al * nc + cell] = S(Np[al]);
 }
 
+// Re-basing of the 16-bit references on the current state: every slot the cell
+// wrote (its post-collision N'_a, encoded against rown[a]) takes its own
+// 16-bit rounding as the new reference and is re-encoded against it, so the
+// stored deviations restart near zero and FP16/BF16 keep their relative
+// precision on a small number.  k_refs_src then refreshes rsrc.
+template <class L, class S>
+__global__ __launch_bounds__(kBlock) void k_rebase(StateArgs<S> a) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= a.box.ncells) return;
+  const long nc = a.box.ncells;
+  for (int al = 0; al < L::Q; ++al) {
+    const long i = al * nc + cell;
+    const double n = PopCodec<S>::template decode<double>(a.in[i], a.rown[i], a.inv_scale);
+    const S r = S(n);
+    a.rown[i] = r;
+    a.out[i] = PopCodec<S>::template encode<double>(n, r, a.scale);
+  }
+}
+
 // ... and, gathered along the links, the reference of each arriving link (rsrc).
 template <class L, class S>
 __global__ __launch_bounds__(kBlock) void k_refs_src(StateArgs<S> a) {
@@ -390,7 +409,7 @@ StateArgs<S> make_args(SimObj* s) {
   a.out = static_cast<S*>(s->pop[s->buf]);
   a.rsrc = static_cast<const S*>(s->rsrc);
   a.rown = static_cast<S*>(s->rown);
-  a.scale = pop_scale(s->p.precision);
+  a.scale = pop_scale(s->p.precision, s->mesh->report.max_J);
   a.inv_scale = 1.0f / a.scale;
   a.flag = s->flags;
   a.fcache = s->fcache;
@@ -427,6 +446,14 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
     case 5:
       k_refs_own<L, S><<<nb, kBlock, 0, st>>>(a);
       if (hipGetLastError() != hipSuccess) break;
+      k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
+      break;
+    case 6:
+      k_rebase<L, S><<<nb, kBlock, 0, st>>>(a);
+      if (hipGetLastError() != hipSuccess) break;
+      k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
+      break;
+    case 7:
       k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
       break;
     case 4: {
@@ -484,6 +511,14 @@ hipError_t launch_set_pop(SimObj* s, const double* N) {
 }
 hipError_t launch_refs(SimObj* s) {
   return dispatch_any(s, 5, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+}
+hipError_t launch_refs_src(SimObj* s) {
+  if (!storage_is_16(s->p.precision)) return hipSuccess;
+  return dispatch_any(s, 7, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+}
+hipError_t launch_rebase(SimObj* s) {
+  if (!storage_is_16(s->p.precision)) return hipSuccess;
+  return dispatch_any(s, 6, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 hipError_t launch_audit(SimObj* s, int slot) {
   return dispatch_any(s, 4, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, slot);

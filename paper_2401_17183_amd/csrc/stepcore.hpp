@@ -202,7 +202,7 @@ inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   a.out = static_cast<P*>(s->pop[s->buf ^ 1]);
   a.rsrc = static_cast<const P*>(s->rsrc);
   a.rown = static_cast<const P*>(s->rown);
-  a.scale = pop_scale(s->p.precision);
+  a.scale = pop_scale(s->p.precision, s->mesh->report.max_J);
   a.inv_scale = 1.0f / a.scale;
   a.geo = static_cast<const S*>(s->geo);
   a.tau = T(s->p.tau);

@@ -54,7 +54,7 @@ class vlbm_params(C.Structure):
     _fields_ = [("tau", C.c_double), ("body_force", C.c_double * 3), ("rho_inf", C.c_double),
                 ("u_inf", C.c_double * 3), ("precision", C.c_int32), ("fp_max_iter", C.c_int32),
                 ("fp_tol", C.c_double), ("audit_every", C.c_int32), ("stream_only", C.c_int32),
-                ("tau_g", C.c_double)]
+                ("tau_g", C.c_double), ("rebase_every", C.c_int32)]
 
 
 class vlbm_audit(C.Structure):
@@ -255,12 +255,13 @@ class Mesh:
 
 
 def make_params(tau, body_force=(0, 0, 0), rho_inf=1.0, u_inf=(0, 0, 0), precision=FP64, fp_max_iter=0,
-                fp_tol=-1.0, audit_every=0, stream_only=False, tau_g=None):
+                fp_tol=-1.0, audit_every=0, stream_only=False, tau_g=None, rebase_every=0):
     """Simulation parameters; tau_g None (or tau) is BGK, otherwise the general
     collision matrix whose non-hydrodynamic part relaxes at 1/tau_g."""
     p = vlbm_params()
     p.tau = float(tau)
     p.tau_g = 0.0 if tau_g is None else float(tau_g)
+    p.rebase_every = int(rebase_every)
     bf = list(body_force) + [0.0] * (3 - len(body_force))
     ui = list(u_inf) + [0.0] * (3 - len(u_inf))
     for k in range(3):

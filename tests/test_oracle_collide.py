@@ -10,7 +10,8 @@ from paper_2401_17183_amd import workloads as W
 from tests.oracle_helpers import near_equilibrium_state, sim_of
 from tests.test_oracle_geometry import central_gamma, refine_wavy
 
-CASES = [W.wavy_channel_3d(8, 8, 6), W.tanh_channel_2d(12, 16), W.wavy_periodic("D2Q9", (10, 12), 0.2)]
+CASES = [W.wavy_channel_3d(8, 8, 6), W.tanh_channel_2d(12, 16), W.wavy_periodic("D2Q9", (10, 12), 0.2),
+         W.wavy_periodic("D2Q21", (10, 12), 0.1), W.wavy_periodic("D3Q39", (6, 5, 7), 0.08)]
 
 
 def converged_pieces(s, N):
@@ -117,7 +118,7 @@ def test_delta_pi_continuum_limit():
 
 # ---- general collision matrix (eq. (collide) with eq. (matrix)) ----
 
-LATS = [lattice.D2Q9, lattice.D3Q19]
+LATS = [lattice.D2Q9, lattice.D3Q19, lattice.D2Q21, lattice.D3Q39]
 RATES = [(0.8, 1.0), (0.6, 0.7), (1.7, 0.55), (0.9, 1.9)]
 
 

@@ -41,31 +41,31 @@ def test_naive_momentum_is_not_the_conserved_one():
     assert np.max(np.abs(P() - P0)) > 1e-6
 
 
-def textbook_bgk(N, c, w, tau, steps):
-    """An independent plain D2Q9/D3Q19 BGK with the third-order Hermite
-    equilibrium on a uniform periodic lattice (unit spacing)."""
+def textbook_bgk(N, c, w, tau, steps, t0=1.0 / 3.0):
+    """An independent plain BGK with the third-order Hermite equilibrium on a
+    uniform periodic lattice (unit spacing), lattice temperature t0."""
     d = c.shape[1]
     for _ in range(steps):
         rho = N.sum(0)
         u = np.einsum("ai,a...->i...", c, N) / rho
         cu = np.einsum("ai,i...->a...", c, u)
         u2 = np.sum(u * u, axis=0)[None]
-        fe = w.reshape((-1,) + (1,) * d) * rho[None] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * u2
-                                                        + 4.5 * cu ** 3 - 4.5 * cu * u2)
+        fe = w.reshape((-1,) + (1,) * d) * rho[None] * (1 + cu / t0 + cu ** 2 / (2 * t0 ** 2) - u2 / (2 * t0)
+                                                        + cu ** 3 / (6 * t0 ** 3) - cu * u2 / (2 * t0 ** 2))
         Np = N - (N - fe) / tau
         N = np.stack([np.roll(Np[a], shift=tuple(int(v) for v in c[a][::-1]), axis=tuple(range(d)))
                       for a in range(len(w))])
     return N
 
 
-@pytest.mark.parametrize("lat,n", [("D2Q9", (9, 7)), ("D3Q19", (6, 5, 4))])
+@pytest.mark.parametrize("lat,n", [("D2Q9", (9, 7)), ("D3Q19", (6, 5, 4)), ("D2Q21", (9, 7)), ("D3Q39", (6, 5, 4))])
 def test_cartesian_reduction_to_textbook_bgk(lat, n):
     """On a uniform Cartesian lattice (g^{ij} = delta, Theta = 0) the scheme is the
-    standard LBM (remark after eq. (equilibrium))."""
+    standard LBM (remark after eq. (equilibrium)), with the lattice's T0."""
     wl = W.affine_mesh(lat, n, np.eye(len(n)))
     s = sim_of(wl, tau=0.7)
     N0 = near_equilibrium_state(s, amp=1e-2)
-    ref = textbook_bgk(N0.copy(), s.lat.cf, s.lat.w, 0.7, 10)
+    ref = textbook_bgk(N0.copy(), s.lat.cf, s.lat.w, 0.7, 10, s.lat.T0)
     s.step(10)
     assert np.max(np.abs(s.N - ref)) < 1e-15
 

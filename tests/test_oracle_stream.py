@@ -8,7 +8,8 @@ from tests.oracle_helpers import mesh_of, sim_of
 
 
 @pytest.mark.parametrize("wl", [W.tanh_channel_2d(6, 5), W.wavy_channel_3d(5, 4, 3),
-                                W.wavy_periodic("D3Q19", (4, 5, 3), 0.1)], ids=lambda w: w["name"])
+                                W.wavy_periodic("D3Q19", (4, 5, 3), 0.1), W.wavy_periodic("D2Q21", (5, 4), 0.1),
+                                W.wavy_periodic("D3Q39", (4, 5, 3), 0.1)], ids=lambda w: w["name"])
 def test_stream_is_a_permutation(wl):
     m = mesh_of(wl)
     ids = np.arange(m.lat.Q * m.ncells, dtype=np.float64).reshape((m.lat.Q,) + m.shape)
@@ -16,7 +17,7 @@ def test_stream_is_a_permutation(wl):
     assert np.array_equal(np.sort(out.ravel()), ids.ravel())
 
 
-@pytest.mark.parametrize("lat,n", [("D2Q9", (7, 7)), ("D3Q19", (5, 5, 5))])
+@pytest.mark.parametrize("lat,n", [("D2Q9", (7, 7)), ("D3Q19", (5, 5, 5)), ("D2Q21", (7, 7)), ("D3Q39", (5, 5, 5))])
 def test_period_of_pure_streaming_is_identity(lat, n):
     wl = W.wavy_periodic(lat, n, 0.1)
     s = sim_of(wl, stream_only=True)
