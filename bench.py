@@ -49,6 +49,11 @@ def make_workload(name):
         return W.tanh_channel_3d(256, 128, 128)
     if name == "ogrid":
         return W.ogrid_3d()
+    if name == "d3q39":
+        # sixth-order isotropic lattice: periodic wavy box, 128^3 cells
+        return W.wavy_periodic("D3Q39", (128, 128, 128), 2.0)
+    if name == "d2q21":
+        return W.wavy_periodic("D2Q21", (2048, 1024), 8.0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -68,6 +73,12 @@ def cpu_baseline(workload="channel", seconds_target=12.0, tau_g=None, tau=None):
     elif workload == "ogrid":
         ws = [W.ogrid_3d(32, 64, 8)]
         label = "D3Q19 O-grid 32x64x8"
+    elif workload == "d3q39":
+        ws = [W.wavy_periodic("D3Q39", (16, 16, 16), 0.25)]
+        label = "D3Q39 wavy periodic 16^3"
+    elif workload == "d2q21":
+        ws = [W.wavy_periodic("D2Q21", (64, 64), 0.25)]
+        label = "D2Q21 wavy periodic 64^2"
     else:
         ws = [W.tanh_channel_3d(32, 32, 16)]
         label = "D3Q19 tanh(2.5) channel 32x32x16"
@@ -418,7 +429,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="channel", choices=["channel", "ogrid", "batch", "surrogate", "train"])
+    ap.add_argument("--workload", default="channel",
+                    choices=["channel", "ogrid", "d3q39", "d2q21", "batch", "surrogate", "train"])
     ap.add_argument("--precision", default="fp32", choices=sorted(STORAGE_BYTES))
     ap.add_argument("--tune-cache", default=None, help="autotune cache file for --workload batch")
     ap.add_argument("--persistent-only", action="store_true",

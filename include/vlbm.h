@@ -23,6 +23,16 @@
  *           (1,0,1)(-1,0,-1) (1,0,-1)(-1,0,1) (0,1,1)(0,-1,-1) (0,1,-1)(0,-1,1)
  *    with weights 4/9,1/9,1/36 (D2Q9) and 1/3,1/18,1/36 (D3Q19), T0 = 1/3
  *    (velocity set and T0: Sec. 2.1 around eq. (iso)).
+ *    Sixth-order isotropic sets (eq. (iso) in full), T0 = 2/3, links up to three
+ *    cells long, periodic axes only:
+ *    D3Q39: (0,0,0); (+-1,0,0) (0,+-1,0) (0,0,+-1); (1,1,1)(-1,-1,-1)
+ *           (1,1,-1)(-1,-1,1) (1,-1,1)(-1,1,-1) (1,-1,-1)(-1,1,1); (+-2,0,0)
+ *           (0,+-2,0) (0,0,+-2); (2,2,0)(-2,-2,0) (2,-2,0)(-2,2,0) (2,0,2)(-2,0,-2)
+ *           (2,0,-2)(-2,0,2) (0,2,2)(0,-2,-2) (0,2,-2)(0,-2,2); (+-3,0,0) (0,+-3,0)
+ *           (0,0,+-3); weights per shell 1/12, 1/12, 1/27, 2/135, 1/432, 1/1620;
+ *    D2Q21: (0,0); (+-1,0) (0,+-1); (1,1)(-1,-1) (1,-1)(-1,1); (+-2,0) (0,+-2);
+ *           (2,2)(-2,-2) (2,-2)(-2,2); (+-3,0) (0,+-3); weights per shell 91/324,
+ *           1/12, 2/27, 7/360, 1/432, 1/1620 (the planar projection of D3Q39).
  */
 #ifndef VLBM_H
 #define VLBM_H
@@ -34,7 +44,7 @@
 extern "C" {
 #endif
 
-enum { VLBM_D2Q9 = 0, VLBM_D3Q19 = 1 };
+enum { VLBM_D2Q9 = 0, VLBM_D3Q19 = 1, VLBM_D2Q21 = 2, VLBM_D3Q39 = 3 };
 
 /* Storage / arithmetic precision of a simulation:
  *  FP64   populations and geometry stored in FP64, FP64 arithmetic;

@@ -91,26 +91,27 @@ extern "C" {
 
 const char* vlbm_last_error(void) { return g_err; }
 
+extern "C++" {
+template <class L>
+static void lattice_table(int32_t* Q, int32_t* d, int32_t* c, double* w) {
+  *Q = L::Q;
+  *d = L::D;
+  for (int a = 0; a < L::Q; ++a) {
+    for (int i = 0; i < L::D; ++i)
+      if (c) c[a * L::D + i] = L::c(a, i);
+    if (w) w[a] = L::w(a);
+  }
+}
+}
+
 int vlbm_lattice_info(int lattice, int32_t* Q, int32_t* d, int32_t* c, double* w) {
   if (!Q || !d) return fail(VLBM_ERR_ARG, "vlbm_lattice_info: null output");
-  if (lattice == VLBM_D2Q9) {
-    *Q = D2Q9::Q;
-    *d = D2Q9::D;
-    for (int a = 0; a < D2Q9::Q; ++a) {
-      for (int i = 0; i < 2; ++i)
-        if (c) c[a * 2 + i] = D2Q9::c(a, i);
-      if (w) w[a] = D2Q9::w(a);
-    }
-  } else if (lattice == VLBM_D3Q19) {
-    *Q = D3Q19::Q;
-    *d = D3Q19::D;
-    for (int a = 0; a < D3Q19::Q; ++a) {
-      for (int i = 0; i < 3; ++i)
-        if (c) c[a * 3 + i] = D3Q19::c(a, i);
-      if (w) w[a] = D3Q19::w(a);
-    }
-  } else {
-    return fail(VLBM_ERR_ARG, "unknown lattice %d", lattice);
+  switch (lattice) {
+    case VLBM_D2Q9: lattice_table<D2Q9>(Q, d, c, w); break;
+    case VLBM_D3Q19: lattice_table<D3Q19>(Q, d, c, w); break;
+    case VLBM_D2Q21: lattice_table<D2Q21>(Q, d, c, w); break;
+    case VLBM_D3Q39: lattice_table<D3Q39>(Q, d, c, w); break;
+    default: return fail(VLBM_ERR_ARG, "unknown lattice %d", lattice);
   }
   return ok();
 }
@@ -119,10 +120,11 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
                      vlbm_mesh* out) {
   if (!n || !coords || !topo || !out) return fail(VLBM_ERR_ARG, "vlbm_mesh_create: null argument");
   *out = nullptr;
-  if (lattice != VLBM_D2Q9 && lattice != VLBM_D3Q19) return fail(VLBM_ERR_ARG, "unknown lattice %d", lattice);
+  if (lattice < VLBM_D2Q9 || lattice > VLBM_D3Q39) return fail(VLBM_ERR_ARG, "unknown lattice %d", lattice);
   if (!(dx > 0.0) || !isfinite(dx)) return fail(VLBM_ERR_ARG, "dx must be positive and finite");
-  const int d = lattice == VLBM_D2Q9 ? 2 : 3;
-  if (d == 2 && n[2] != 1) return fail(VLBM_ERR_ARG, "D2Q9 needs n[2] == 1");
+  const int d = (lattice == VLBM_D2Q9 || lattice == VLBM_D2Q21) ? 2 : 3;
+  const int speed = lattice_speed(lattice);
+  if (d == 2 && n[2] != 1) return fail(VLBM_ERR_ARG, "a 2-D lattice needs n[2] == 1");
   int64_t nc = 1;
   for (int i = 0; i < d; ++i) {
     if (n[i] < 1 || n[i] > (1 << 20)) return fail(VLBM_ERR_ARG, "n[%d] = %lld out of range", i, (long long)n[i]);
@@ -133,7 +135,7 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
   if (!m) return fail(VLBM_ERR_NOMEM, "host allocation failed");
   m->lattice = lattice;
   m->d = d;
-  m->Q = d == 2 ? 9 : 19;
+  m->Q = lattice == VLBM_D2Q9 ? 9 : lattice == VLBM_D3Q19 ? 19 : lattice == VLBM_D2Q21 ? 21 : 39;
   m->dx = dx;
   size_t ncoord = (size_t)d;
   for (int i = 0; i < 3; ++i) {
@@ -153,6 +155,16 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
       if (lo == VLBM_PERIODIC && n[i] < 2) {
         delete m;
         return fail(VLBM_ERR_ARG, "periodic axis %d needs at least 2 cells", i);
+      }
+      // links longer than one cell have only the periodic reading
+      if (speed > 1 && lo != VLBM_PERIODIC) {
+        delete m;
+        return fail(VLBM_ERR_UNSUPPORTED, "axis %d: this lattice's links span %d cells; it needs periodic axes",
+                    i, speed);
+      }
+      if (lo == VLBM_PERIODIC && n[i] < speed) {
+        delete m;
+        return fail(VLBM_ERR_ARG, "periodic axis %d needs at least %d cells for this lattice", i, speed);
       }
     }
     m->m[i] = !active ? 1 : (m->box.face[i][0] == VLBM_PERIODIC ? (int)n[i] : (int)n[i] + 4);
@@ -290,6 +302,8 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   if (p->precision < VLBM_FP64 || p->precision > VLBM_FP32C)
     return fail(VLBM_ERR_UNSUPPORTED, "precision %d is not built", p->precision);
   if (p->audit_every < 0) return fail(VLBM_ERR_ARG, "audit_every must be >= 0");
+  if (lattice_speed(m->lattice) > 1 && storage_is_16(p->precision))
+    return fail(VLBM_ERR_UNSUPPORTED, "16-bit storage is built for D2Q9 and D3Q19");
   SimObj* s = new (std::nothrow) SimObj();
   if (!s) return fail(VLBM_ERR_NOMEM, "host allocation failed");
   s->mesh = m;
@@ -315,7 +329,7 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   };
   if ((rc = dev_alloc(&s->pop[0], s->pop_bytes))) return bail(rc);
   if ((rc = dev_alloc(&s->pop[1], s->pop_bytes))) return bail(rc);
-  const int words = m->lattice == VLBM_D2Q9 ? Pack<D2Q9>::WORDS : Pack<D3Q19>::WORDS;
+  const int words = pack_words(m->lattice);
   if ((rc = dev_alloc(&s->geo, nc * words * geometry_bytes(s->p.precision)))) return bail(rc);
   if (storage_is_16(s->p.precision)) {
     if ((rc = dev_alloc(&s->rown, nc * m->Q * sb))) return bail(rc);
@@ -534,10 +548,12 @@ static int batch_cus() {
 int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int count, void* stream, vlbm_batch* out) {
   if (!meshes || !params || !out || count <= 0) return fail(VLBM_ERR_ARG, "vlbm_batch_create: bad argument");
   *out = nullptr;
+  if (!meshes[0]) return fail(VLBM_ERR_ARG, "vlbm_batch_create: null mesh");
   const int lat = reinterpret_cast<MeshObj*>(meshes[0])->lattice;
   const int prec = params[0].precision;
   if (prec != VLBM_FP64 && prec != VLBM_FP32 && prec != VLBM_FP32C)
     return fail(VLBM_ERR_UNSUPPORTED, "batches are built for FP64, FP32 and FP32C");
+  if (lat != VLBM_D2Q9 && lat != VLBM_D3Q19) return fail(VLBM_ERR_UNSUPPORTED, "batches are built for D2Q9 and D3Q19");
   BatchObj* b = new (std::nothrow) BatchObj();
   if (!b) return fail(VLBM_ERR_NOMEM, "host allocation failed");
   b->lattice = lat;

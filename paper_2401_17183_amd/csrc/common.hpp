@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/vlbm.h"
 
 namespace vlbm {
@@ -14,12 +16,23 @@ namespace vlbm {
 // ---------------------------------------------------------------------------
 // Lattices (Sec. 2.1, eq. (iso) and the D3Q19 set printed there; D2Q9 is its
 // planar analogue).  Rest first, then opposite pairs (2k-1, 2k).  All lookups
-// are constexpr so fully unrolled loops fold them into immediates.
+// are constexpr so fully unrolled loops fold them into immediates.  Each
+// lattice carries its T0 and the factors 1/T0, 1/(2 T0), 1/(6 T0^3) of the
+// equilibrium and of dN, and SPEED, its longest link in cells per axis.
+//
+// D3Q39 and D2Q21 are sixth-order isotropic (eq. (iso) in full), T0 = 2/3:
+// D3Q39 has the shells 0, (1,0,0), (1,1,1), (2,0,0), (2,2,0), (3,0,0) with
+// weights 1/12, 1/12, 1/27, 2/135, 1/432, 1/1620; D2Q21 is its projection on
+// the (x, y) plane (shells 0, (1,0), (1,1), (2,0), (2,2), (3,0) with weights
+// 91/324, 1/12, 2/27, 7/360, 1/432, 1/1620).  Their links span up to three
+// cells, so they run on periodic axes only.
 // ---------------------------------------------------------------------------
 struct D2Q9 {
   static constexpr int Q = 9;
   static constexpr int D = 2;
   static constexpr int ID = VLBM_D2Q9;
+  static constexpr int SPEED = 1;
+  static constexpr double T0 = 1.0 / 3.0, INV_T0 = 3.0, INV_2T0 = 1.5, INV_6T03 = 4.5;
   __host__ __device__ static constexpr int c(int a, int i) {
     constexpr int t[9][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
                              {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
@@ -34,6 +47,8 @@ struct D3Q19 {
   static constexpr int Q = 19;
   static constexpr int D = 3;
   static constexpr int ID = VLBM_D3Q19;
+  static constexpr int SPEED = 1;
+  static constexpr double T0 = 1.0 / 3.0, INV_T0 = 3.0, INV_2T0 = 1.5, INV_6T03 = 4.5;
   __host__ __device__ static constexpr int c(int a, int i) {
     constexpr int t[19][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},
                               {0, 0, 1},   {0, 0, -1},  {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},
@@ -46,9 +61,62 @@ struct D3Q19 {
   }
 };
 
+struct D2Q21 {
+  static constexpr int Q = 21;
+  static constexpr int D = 2;
+  static constexpr int ID = VLBM_D2Q21;
+  static constexpr int SPEED = 3;
+  static constexpr double T0 = 2.0 / 3.0, INV_T0 = 1.5, INV_2T0 = 0.75, INV_6T03 = 0.5625;
+  __host__ __device__ static constexpr int c(int a, int i) {
+    constexpr int t[21][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},   {0, -1, 0}, {1, 1, 0},
+                              {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},  {2, 0, 0},   {-2, 0, 0}, {0, 2, 0},
+                              {0, -2, 0}, {2, 2, 0},  {-2, -2, 0}, {2, -2, 0},  {-2, 2, 0}, {3, 0, 0},
+                              {-3, 0, 0}, {0, 3, 0},  {0, -3, 0}};
+    return t[a][i];
+  }
+  __host__ __device__ static constexpr double w(int a) {
+    return a == 0 ? 91.0 / 324.0
+                  : a < 5 ? 1.0 / 12.0
+                  : a < 9 ? 2.0 / 27.0
+                  : a < 13 ? 7.0 / 360.0
+                  : a < 17 ? 1.0 / 432.0
+                  : 1.0 / 1620.0;
+  }
+};
+
+struct D3Q39 {
+  static constexpr int Q = 39;
+  static constexpr int D = 3;
+  static constexpr int ID = VLBM_D3Q39;
+  static constexpr int SPEED = 3;
+  static constexpr double T0 = 2.0 / 3.0, INV_T0 = 1.5, INV_2T0 = 0.75, INV_6T03 = 0.5625;
+  __host__ __device__ static constexpr int c(int a, int i) {
+    constexpr int t[39][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},
+                              {0, 0, -1},  {1, 1, 1},   {-1, -1, -1}, {1, 1, -1},  {-1, -1, 1}, {1, -1, 1},
+                              {-1, 1, -1}, {1, -1, -1}, {-1, 1, 1},  {2, 0, 0},   {-2, 0, 0},  {0, 2, 0},
+                              {0, -2, 0},  {0, 0, 2},   {0, 0, -2},  {2, 2, 0},   {-2, -2, 0}, {2, -2, 0},
+                              {-2, 2, 0},  {2, 0, 2},   {-2, 0, -2}, {2, 0, -2},  {-2, 0, 2},  {0, 2, 2},
+                              {0, -2, -2}, {0, 2, -2},  {0, -2, 2},  {3, 0, 0},   {-3, 0, 0},  {0, 3, 0},
+                              {0, -3, 0},  {0, 0, 3},   {0, 0, -3}};
+    return t[a][i];
+  }
+  __host__ __device__ static constexpr double w(int a) {
+    return a == 0 ? 1.0 / 12.0
+                  : a < 7 ? 1.0 / 12.0
+                  : a < 15 ? 1.0 / 27.0
+                  : a < 21 ? 2.0 / 135.0
+                  : a < 33 ? 1.0 / 432.0
+                  : 1.0 / 1620.0;
+  }
+};
+
 __host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
 
-constexpr double T0 = 1.0 / 3.0;
+// One bit per direction (64 bits once Q exceeds 32).
+template <class L> using DirMask = typename std::conditional<(L::Q > 32), unsigned long long, unsigned>::type;
+
+// Longest link of a lattice id (cells per axis).
+inline int lattice_speed(int lattice) { return lattice == VLBM_D2Q21 || lattice == VLBM_D3Q39 ? 3 : 1; }
 
 // ---------------------------------------------------------------------------
 // Population storage codecs.  FP64/FP32 store N itself.  The 16-bit modes
@@ -211,6 +279,15 @@ template <class L> struct Pack {
   static constexpr int UINF = AEXT + L::D;                    // present if far field
   static constexpr int WORDS = UINF + L::D;
 };
+
+inline int pack_words(int lattice) {
+  switch (lattice) {
+    case VLBM_D2Q9: return Pack<D2Q9>::WORDS;
+    case VLBM_D3Q19: return Pack<D3Q19>::WORDS;
+    case VLBM_D2Q21: return Pack<D2Q21>::WORDS;
+    default: return Pack<D3Q39>::WORDS;
+  }
+}
 
 struct SimObj {
   MeshObj* mesh;

@@ -147,7 +147,7 @@ template <class L, class T> struct EqCoef {
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ EqCoef<L, T> eq_coef(const CellGeo<L, T, AT, ST>& g, T rho, const T* U, const T* Ut) {
   constexpr int D = L::D;
-  const T t0 = T(T0);
+  const T t0 = T(L::T0);
   EqCoef<L, T> e;
   e.rho = rho;
   T uu = 0, trg = 0;
@@ -177,7 +177,7 @@ __device__ __forceinline__ EqCoef<L, T> eq_coef(const CellGeo<L, T, AT, ST>& g, 
 template <class L, class T, class AT, int ST, int a>
 __device__ __forceinline__ T feq_dir(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e) {
   constexpr int D = L::D;
-  const T t0 = T(T0);
+  const T t0 = T(L::T0);
   T cU = 0, cUt = 0, cr = 0, cgc = 0;
   int cc = 0;
 #pragma unroll
@@ -196,10 +196,10 @@ __device__ __forceinline__ T feq_dir(const CellGeo<L, T, AT, ST>& g, const EqCoe
     }
   }
   const T cGc = t0 * (cgc - T(cc)) + cUt * cUt;
-  const T H2G = cGc * T(3) - e.trG;
+  const T H2G = cGc * T(L::INV_T0) - e.trG;
   const T H3R = T(3) * t0 * (cgc * cUt - T(cc) * cU) + cUt * cUt * cUt - T(3) * t0 * cr;
-  // 1/T0 = 3, 1/(2 T0) = 3/2, 1/(6 T0^3) = 9/2
-  return e.rho * T(L::w(a)) * (T(1) + T(3) * cU + T(1.5) * H2G + T(4.5) * H3R);
+  // factors 1/T0, 1/(2 T0), 1/(6 T0^3) of the lattice (3, 3/2, 9/2 for T0 = 1/3)
+  return e.rho * T(L::w(a)) * (T(1) + T(L::INV_T0) * cU + T(L::INV_2T0) * H2G + T(L::INV_6T03) * H3R);
 }
 
 template <class L, class T, class AT, int ST, int a = 0>
@@ -227,7 +227,7 @@ __device__ __forceinline__ T delta_n_dir(T J, const T* Ft, const T* dpi, T trdpi
       cpc += T(ci * cj) * dpi[up<D>(i, j)];
     }
   }
-  return T(L::w(a)) * J * (T(3) * cF + T(3) * (T(3) * cpc - trdpi));
+  return T(L::w(a)) * J * (T(L::INV_T0) * cF + T(L::INV_T0) * (T(L::INV_T0) * cpc - trdpi));
 }
 
 // Pass 1 of one fixed-point iteration, with the equilibrium at the current Ut:
@@ -413,7 +413,7 @@ __device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, 
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = i; j < D; ++j) {
-          const T v = r.c1 * rho_l * (T(T0) * gval(gl, i, j) + st.Ut[i] * st.Ut[j]);
+          const T v = r.c1 * rho_l * (T(L::T0) * gval(gl, i, j) + st.Ut[i] * st.Ut[j]);
           st.dpi[up<D>(i, j)] -= v;
           if (i == j) st.trdpi -= v;
         }

@@ -14,7 +14,8 @@ struct GeoArgs {
   Box box;
   int d;
   int m[3];           // coordinate extents
-  int nb[3];          // box extents (n_i + 2 on axes < d, 1 otherwise)
+  int layers;         // box layers around the real cells: the lattice's longest link
+  int nb[3];          // box extents (n_i + 2 layers on axes < d, 1 otherwise)
   int nbox;
   double wrap[3][3];
   double inv2dx;
@@ -29,8 +30,9 @@ struct GeoArgs {
   double* partial;    // [blocks][6]
 };
 
-// x(q) for q with one or two layers outside the real box: periodic axes wrap
-// the index and add the translation, non-periodic axes read ghost nodes.
+// x(q) for q outside the real box: periodic axes wrap the index (any number of
+// periods) and add the translation, non-periodic axes read the two ghost node
+// layers (the only layers a one-cell lattice needs there).
 __device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
   int idx[3] = {0, 0, 0};
   double shift[3] = {0, 0, 0};
@@ -55,7 +57,7 @@ __device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
   }
 }
 
-// Pass 1: one thread per box cell (real cells and the first ghost layer):
+// Pass 1: one thread per box cell (real cells and `layers` layers around them):
 // D_{+-i} (eq. (distance)), beta_i and g_i (eq. (tangent)), J (eq. (jacobian)),
 // g^i (eq. (covectors)), g^{ij} (eq. (inverse)).
 __global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
   const int d = a.d;
   int bq[3] = {b % a.nb[0], (b / a.nb[0]) % a.nb[1], b / (a.nb[0] * a.nb[1])};
   int q[3] = {0, 0, 0};
-  for (int i = 0; i < d; ++i) q[i] = bq[i] - 1;
+  for (int i = 0; i < d; ++i) q[i] = bq[i] - a.layers;
   double x0[3];
   coord_at(a, q, x0);
   double gv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -180,7 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_links(GeoArgs a) {
     const int x = cell % a.box.n[0];
     const int y = (cell / a.box.n[0]) % a.box.n[1];
     const int z = cell / (a.box.n[0] * a.box.n[1]);
-    int bq[3] = {x + 1, y + (D > 1 ? 1 : 0), z + (D > 2 ? 1 : 0)};
+    const int ly = a.layers;
+    int bq[3] = {x + ly, y + (D > 1 ? ly : 0), z + (D > 2 ? ly : 0)};
     const int b0 = bq[0] + a.nb[0] * (bq[1] + a.nb[1] * bq[2]);
     double gco[D][D], g0[D][D];
     for (int i = 0; i < D; ++i)
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_links(GeoArgs a) {
       for (int i = 0; i < D; ++i)
         for (int j = 0; j < D; ++j) cgc += L::c(al, i) * L::c(al, j) * G[i * D + j];
       for (int i = 0; i < D; ++i) cc += L::c(al, i) * L::c(al, i);
-      const double ratio = 1.0 + 0.5 * (3.0 * (cgc - cc) - (trg - D));
+      const double ratio = 1.0 + 0.5 * (L::INV_T0 * (cgc - cc) - (trg - D));
       vrest = fmin(vrest, ratio);
     }
   }
@@ -255,9 +258,10 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
   a.box = m->box;
   a.d = m->d;
   a.nbox = 1;
+  a.layers = lattice_speed(m->lattice);
   for (int i = 0; i < 3; ++i) {
     a.m[i] = m->m[i];
-    a.nb[i] = i < m->d ? m->box.n[i] + 2 : 1;
+    a.nb[i] = i < m->d ? m->box.n[i] + 2 * a.layers : 1;
     a.nbox *= a.nb[i];
     for (int k = 0; k < 3; ++k) a.wrap[i][k] = m->wrap[i][k];
   }
@@ -277,10 +281,12 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
     (void)hipFree(a.gbox);
     return e;
   }
-  if (m->lattice == VLBM_D2Q9)
-    k_links<D2Q9><<<nblocks_partial, kBlock, 0, s>>>(a);
-  else
-    k_links<D3Q19><<<nblocks_partial, kBlock, 0, s>>>(a);
+  switch (m->lattice) {
+    case VLBM_D2Q9: k_links<D2Q9><<<nblocks_partial, kBlock, 0, s>>>(a); break;
+    case VLBM_D3Q19: k_links<D3Q19><<<nblocks_partial, kBlock, 0, s>>>(a); break;
+    case VLBM_D2Q21: k_links<D2Q21><<<nblocks_partial, kBlock, 0, s>>>(a); break;
+    default: k_links<D3Q39><<<nblocks_partial, kBlock, 0, s>>>(a); break;
+  }
   if ((e = hipGetLastError()) != hipSuccess) {
     (void)hipFree(a.gbox);
     return e;

@@ -76,9 +76,9 @@ __device__ inline void cell_xyz(const Box& b, int cell, int& x, int& y, int& z) 
 // wallmask receives the directions that bounced.
 template <class L, class S>
 __device__ inline void gather64(const StateArgs<S>& a, const CellGeo<L, double>& g, const double* Uinf, int cell,
-                                int x, int y, int z, double* N, unsigned& wallmask) {
+                                int x, int y, int z, double* N, DirMask<L>& wallmask) {
   const long nc = a.box.ncells;
-  unsigned ff = 0;
+  DirMask<L> ff = 0;
   wallmask = 0;
 #pragma unroll
   for (int al = 0; al < L::Q; ++al) {
@@ -87,15 +87,15 @@ __device__ inline void gather64(const StateArgs<S>& a, const CellGeo<L, double>&
     const int dir = kind == LINK_INTERIOR ? al : opp(al);
     N[al] = PopCodec<S>::template decode<double>(a.in[dir * nc + src], a.rsrc ? a.rsrc[al * nc + cell] : S(0),
                                                  a.inv_scale);
-    if (kind == LINK_WALL) wallmask |= 1u << al;
-    if (kind == LINK_FARFIELD) ff |= 1u << al;
+    if (kind == LINK_WALL) wallmask |= DirMask<L>(1) << al;
+    if (kind == LINK_FARFIELD) ff |= DirMask<L>(1) << al;
   }
   if (ff) {
     double fe[L::Q];
     feq_farfield<L, double>(g, a.rho_inf, Uinf, fe);
 #pragma unroll
     for (int al = 0; al < L::Q; ++al)
-      if (ff & (1u << al)) N[al] = g.j() * fe[al];
+      if ((ff >> al) & 1) N[al] = g.j() * fe[al];
   }
 }
 
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(StateArgs<S> a) {
   double Uinf[L::D];
   const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
   double N[L::Q];
-  unsigned wm;
+  DirMask<L> wm;
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
 #pragma unroll
   for (int al = 0; al < L::Q; ++al) a.N_out[al * nc + cell] = N[al];
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(StateArgs<S> a) {
   double Uinf[D];
   const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
   double N[L::Q];
-  unsigned wm;
+  DirMask<L> wm;
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
   double Np[L::Q], F[D], Ut[D], U[D], rho;
   for (int i = 0; i < D; ++i) F[i] = 0;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
     double Uinf[D];
     const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
     double N[Q];
-    unsigned wm;
+    DirMask<L> wm;
     gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
     double gi[D][D];
     for (int i = 0; i < D; ++i)
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
         const double ci = L::c(al, i);
         const double Ao = g.a(opp(al), i);
         inner[i] += (ci - 0.5 * Ao) * n;
-        if (wm & (1u << al)) wall[i] += (2.0 * ci - Ao) * n;
+        if ((wm >> al) & 1) wall[i] += (2.0 * ci - Ao) * n;
       }
     }
     v[0] = mass;
@@ -473,22 +473,32 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
   return hipGetLastError();
 }
 
+template <class L>
+hipError_t dispatch_lattice(SimObj* s, int what, const double* r_in, const double* u_in, double* r_out,
+                            double* u_out, double* U_out, double* N_out, const double* N_in, int slot) {
+  switch (s->p.precision) {
+    case VLBM_FP64: return dispatch<L, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    case VLBM_FP16S:
+      if constexpr (L::SPEED == 1)
+        return dispatch<L, __half>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+      else
+        return hipErrorInvalidValue;   // 16-bit storage is rejected for long-link lattices at init
+    case VLBM_BF16S:
+      if constexpr (L::SPEED == 1)
+        return dispatch<L, __hip_bfloat16>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+      else
+        return hipErrorInvalidValue;
+    default: return dispatch<L, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+  }
+}
+
 hipError_t dispatch_any(SimObj* s, int what, const double* r_in, const double* u_in, double* r_out, double* u_out,
                         double* U_out, double* N_out, const double* N_in, int slot) {
-  const bool d2 = s->mesh->lattice == VLBM_D2Q9;
-  switch (s->p.precision) {
-    case VLBM_FP64:
-      return d2 ? dispatch<D2Q9, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
-                : dispatch<D3Q19, double>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
-    case VLBM_FP16S:
-      return d2 ? dispatch<D2Q9, __half>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
-                : dispatch<D3Q19, __half>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
-    case VLBM_BF16S:
-      return d2 ? dispatch<D2Q9, __hip_bfloat16>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
-                : dispatch<D3Q19, __hip_bfloat16>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
-    default:
-      return d2 ? dispatch<D2Q9, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot)
-                : dispatch<D3Q19, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+  switch (s->mesh->lattice) {
+    case VLBM_D2Q9: return dispatch_lattice<D2Q9>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    case VLBM_D3Q19: return dispatch_lattice<D3Q19>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    case VLBM_D2Q21: return dispatch_lattice<D2Q21>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
+    default: return dispatch_lattice<D3Q39>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
   }
 }
 

@@ -12,15 +12,21 @@ constexpr int kBlock = 256;
 // FF = 0 when the mesh has no far-field links, else 2 (wave-uniform run-time
 // test, which keeps the far-field variant free of spills).
 // GEN: general collision matrix (its own instantiation, always with FF = 2).
-template <class L, class P, class S, class T, int FF, bool GEN>
-__global__ __launch_bounds__(kBlock) VLBM_STEP_ATTR void k_step(StepArgs<P, S, T> a) {
-  step_cell<L, P, S, T, kBlock, FF, GEN>(a, blockIdx.x * kBlock + threadIdx.x);
+template <class L, class P, class S, class T, int FF, bool GEN, int BLOCK = kBlock>
+__global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_step(StepArgs<P, S, T> a) {
+  step_cell<L, P, S, T, BLOCK, FF, GEN>(a, blockIdx.x * BLOCK + threadIdx.x);
 }
 
 // FP64 storage keeps A in registers and runs at the occupancy the compiler picks.
-template <class L, class P, class S, class T, int FF, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_step64(StepArgs<P, S, T> a) {
-  step_cell<L, P, S, T, kBlock, FF, GEN>(a, blockIdx.x * kBlock + threadIdx.x);
+template <class L, class P, class S, class T, int FF, bool GEN, int BLOCK = kBlock>
+__global__ __launch_bounds__(BLOCK) void k_step64(StepArgs<P, S, T> a) {
+  step_cell<L, P, S, T, BLOCK, FF, GEN>(a, blockIdx.x * BLOCK + threadIdx.x);
+}
+
+// Threads per block: D3Q39 stages its 114 A words per cell in LDS, so its
+// blocks are smaller (58 KB of LDS either way).
+template <class L, class S> constexpr int block_for() {
+  return L::Q > 21 ? (sizeof(S) == 4 ? 128 : 64) : kBlock;
 }
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
@@ -54,15 +60,27 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
 template <class L, class P, class S, class T>
 hipError_t step_typed(SimObj* s) {
   const StepArgs<P, S, T> a = make_step_args<P, S, T>(s);
-  const int nb = (a.box.ncells + kBlock - 1) / kBlock;
-  if constexpr (sizeof(S) == 8) {
-    if (a.general) k_step64<L, P, S, T, 2, true><<<nb, kBlock, 0, s->stream>>>(a);
-    else if (a.has_ff) k_step64<L, P, S, T, 2, false><<<nb, kBlock, 0, s->stream>>>(a);
-    else k_step64<L, P, S, T, 0, false><<<nb, kBlock, 0, s->stream>>>(a);
+  if constexpr (L::SPEED > 1) {   // periodic axes only: no far field
+    constexpr int B = block_for<L, S>();
+    const int nb = (a.box.ncells + B - 1) / B;
+    if constexpr (sizeof(S) == 8) {
+      if (a.general) k_step64<L, P, S, T, 0, true, B><<<nb, B, 0, s->stream>>>(a);
+      else k_step64<L, P, S, T, 0, false, B><<<nb, B, 0, s->stream>>>(a);
+    } else {
+      if (a.general) k_step<L, P, S, T, 0, true, B><<<nb, B, 0, s->stream>>>(a);
+      else k_step<L, P, S, T, 0, false, B><<<nb, B, 0, s->stream>>>(a);
+    }
   } else {
-    if (a.general) k_step<L, P, S, T, 2, true><<<nb, kBlock, 0, s->stream>>>(a);
-    else if (a.has_ff) k_step<L, P, S, T, 2, false><<<nb, kBlock, 0, s->stream>>>(a);
-    else k_step<L, P, S, T, 0, false><<<nb, kBlock, 0, s->stream>>>(a);
+    const int nb = (a.box.ncells + kBlock - 1) / kBlock;
+    if constexpr (sizeof(S) == 8) {
+      if (a.general) k_step64<L, P, S, T, 2, true><<<nb, kBlock, 0, s->stream>>>(a);
+      else if (a.has_ff) k_step64<L, P, S, T, 2, false><<<nb, kBlock, 0, s->stream>>>(a);
+      else k_step64<L, P, S, T, 0, false><<<nb, kBlock, 0, s->stream>>>(a);
+    } else {
+      if (a.general) k_step<L, P, S, T, 2, true><<<nb, kBlock, 0, s->stream>>>(a);
+      else if (a.has_ff) k_step<L, P, S, T, 2, false><<<nb, kBlock, 0, s->stream>>>(a);
+      else k_step<L, P, S, T, 0, false><<<nb, kBlock, 0, s->stream>>>(a);
+    }
   }
   return hipGetLastError();
 }
@@ -83,8 +101,12 @@ hipError_t step_lattice(SimObj* s) {
   switch (s->p.precision) {
     case VLBM_FP64: return step_typed<L, double, double, double>(s);
     case VLBM_FP32: return step_typed<L, float, float, double>(s);
-    case VLBM_FP16S: return step_typed<L, __half, float, float>(s);
-    case VLBM_BF16S: return step_typed<L, __hip_bfloat16, float, float>(s);
+    case VLBM_FP16S:
+      if constexpr (L::SPEED == 1) return step_typed<L, __half, float, float>(s);
+      else return hipErrorInvalidValue;   // rejected at init
+    case VLBM_BF16S:
+      if constexpr (L::SPEED == 1) return step_typed<L, __hip_bfloat16, float, float>(s);
+      else return hipErrorInvalidValue;
     default: return step_typed<L, float, float, float>(s);
   }
 }
@@ -92,13 +114,26 @@ hipError_t step_lattice(SimObj* s) {
 }  // namespace
 
 hipError_t launch_step(SimObj* s) {
-  return s->mesh->lattice == VLBM_D2Q9 ? step_lattice<D2Q9>(s) : step_lattice<D3Q19>(s);
+  switch (s->mesh->lattice) {
+    case VLBM_D2Q9: return step_lattice<D2Q9>(s);
+    case VLBM_D3Q19: return step_lattice<D3Q19>(s);
+    case VLBM_D2Q21: return step_lattice<D2Q21>(s);
+    default: return step_lattice<D3Q39>(s);
+  }
+}
+
+template <class S>
+hipError_t pack_storage(SimObj* s) {
+  switch (s->mesh->lattice) {
+    case VLBM_D2Q9: return pack_typed<D2Q9, S>(s);
+    case VLBM_D3Q19: return pack_typed<D3Q19, S>(s);
+    case VLBM_D2Q21: return pack_typed<D2Q21, S>(s);
+    default: return pack_typed<D3Q39, S>(s);
+  }
 }
 
 hipError_t launch_pack(SimObj* s) {
-  const bool d2 = s->mesh->lattice == VLBM_D2Q9;
-  if (storage_is_fp64(s->p.precision)) return d2 ? pack_typed<D2Q9, double>(s) : pack_typed<D3Q19, double>(s);
-  return d2 ? pack_typed<D2Q9, float>(s) : pack_typed<D3Q19, float>(s);
+  return storage_is_fp64(s->p.precision) ? pack_storage<double>(s) : pack_storage<float>(s);
 }
 
 }  // namespace vlbm

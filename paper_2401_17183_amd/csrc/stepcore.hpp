@@ -76,19 +76,23 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
 }
 
 template <class L, class P, class S, class T, class NR, int al = 0>
-__device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const LinkPlan& plan, int cell, NR* N,
-                                            unsigned& ff) {
+__device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const LinkPlan& plan, int x, int y, int z,
+                                            int cell, NR* N, DirMask<L>& ff) {
   if constexpr (al < L::Q) {
     using C = PopCodec<P>;
     const int nc = a.box.ncells;
     int src;
-    const int kind = link_at<L, al>(plan, cell, src);
+    // one-cell links resolve from the per-cell plan; longer ones (periodic
+    // axes only) wrap their own coordinates
+    int kind;
+    if constexpr (L::SPEED == 1) kind = link_at<L, al>(plan, cell, src);
+    else kind = link_source<L>(a.box, al, x, y, z, src);
     const int dir = kind == LINK_INTERIOR ? al : opp(al);
     const P h = word(a.in, 0, nc)[(size_t)dir * nc + src];
     if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rsrc, al, nc)[cell], a.inv_scale);
     else N[al] = h;
-    ff |= (kind == LINK_FARFIELD ? 1u : 0u) << al;
-    gather_dirs<L, P, S, T, NR, al + 1>(a, plan, cell, N, ff);
+    ff |= DirMask<L>(kind == LINK_FARFIELD ? 1 : 0) << al;
+    gather_dirs<L, P, S, T, NR, al + 1>(a, plan, x, y, z, cell, N, ff);
   }
 }
 
@@ -104,9 +108,10 @@ __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo
   constexpr int D = L::D;
   using C = PopCodec<P>;
   const int nc = a.box.ncells;
-  const LinkPlan plan = link_plan<L>(a.box, x, y, z);
-  unsigned ff = 0;
-  gather_dirs<L, P, S, T, NR>(a, plan, cell, N, ff);
+  LinkPlan plan{};
+  if constexpr (L::SPEED == 1) plan = link_plan<L>(a.box, x, y, z);
+  DirMask<L> ff = 0;
+  gather_dirs<L, P, S, T, NR>(a, plan, x, y, z, cell, N, ff);
   if (FF == 1 || (FF == 2 && a.has_ff)) {   // compile-time or wave-uniform
     T Uinf[D];
 #pragma unroll
@@ -114,7 +119,7 @@ __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo
     T fe[Q];
     feq_farfield<L, T>(g, a.rho_inf, Uinf, fe);
 #pragma unroll
-    for (int al = 0; al < Q; ++al) N[al] = (ff >> al) & 1u ? NR(g.j() * fe[al]) : N[al];
+    for (int al = 0; al < Q; ++al) N[al] = (ff >> al) & 1 ? NR(g.j() * fe[al]) : N[al];
   }
 }
 
@@ -141,8 +146,9 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   const int r = cell / a.box.n[0];
   const int y = r % a.box.n[1];
   const int z = r / a.box.n[1];
-  // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19)
-  constexpr int ST = sizeof(S) == 4 ? BLOCK : 0;
+  // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19); so
+  // does D3Q39 in FP64 (its 114 A words cannot live in registers)
+  constexpr int ST = (sizeof(S) == 4 || L::Q > 21) ? BLOCK : 0;
   __shared__ S sA[ST ? (Q - 1) * D * BLOCK : 1];
   NR N[Q];
   const CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));

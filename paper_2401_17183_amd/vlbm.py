@@ -22,13 +22,13 @@ if not os.path.exists(LIBPATH):
                       "or python -m paper_2401_17183_amd.build")
 _lib = C.CDLL(LIBPATH)
 
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D2Q21, D3Q39 = 0, 1, 2, 3
 FP64, FP32, FP16S, BF16S, FP32C = 0, 1, 2, 3, 4
 PERIODIC, WALL, FARFIELD = 0, 1, 2
 OK, ERR_ARG, ERR_MESH, ERR_NOMEM, ERR_DEVICE, ERR_NOCONVERGE, ERR_STATE, ERR_NONFINITE, ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 BATCH_PERSISTENT_GRAPH, BATCH_PERSISTENT, BATCH_EAGER, BATCH_EAGER_GRAPH = 0, 1, 2, 3
-LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
+LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D2Q21": D2Q21, "D3Q39": D3Q39}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S, "bf16s": BF16S, "fp32c": FP32C}
 
 
@@ -199,8 +199,8 @@ class Mesh:
 
     def __init__(self, lattice, n, coords, faces, wrap, dx, precompute=True):
         self.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
-        self.d = 2 if self.lattice == D2Q9 else 3
-        self.Q = 9 if self.lattice == D2Q9 else 19
+        self.d = 2 if self.lattice in (D2Q9, D2Q21) else 3
+        self.Q = {D2Q9: 9, D3Q19: 19, D2Q21: 21, D3Q39: 39}[self.lattice]
         n = tuple(int(v) for v in n)
         self.n = n
         self.ncells = int(np.prod(n))

@@ -45,10 +45,12 @@ def test_lattice_tables_match_the_oracle():
     import numpy as np
     from oracle import lattice
     from paper_2401_17183_amd import vlbm
-    for name, code in (("D2Q9", vlbm.D2Q9), ("D3Q19", vlbm.D3Q19)):
+    for name, code in (("D2Q9", vlbm.D2Q9), ("D3Q19", vlbm.D3Q19), ("D2Q21", vlbm.D2Q21), ("D3Q39", vlbm.D3Q39)):
         c, w = vlbm.lattice_info(code)
         lat = lattice.by_name(name)
-        assert np.array_equal(c, lat.c) and np.array_equal(w, lat.w)
+        assert np.array_equal(c, lat.c), name
+        # each side writes its weights as its own fractions: equal to rounding
+        assert np.allclose(w, lat.w, rtol=2e-16, atol=0), name
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libvlbm.so not built")
@@ -98,6 +100,28 @@ def test_mesh_arguments_rejected_without_a_device(case):
     with pytest.raises(vlbm.VlbmError) as e:
         vlbm.vlbm_mesh_create(lattice, nn, ptr, ctypes.byref(topo), dx, ctypes.byref(h))
     assert e.value.code == vlbm.ERR_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvlbm.so not built")
+@pytest.mark.parametrize("lattice,n,faces,code", [
+    ("D3Q39", (4, 4, 4), "wall", "UNSUPPORTED"),      # three-cell links: periodic axes only
+    ("D2Q21", (4, 2, 1), "periodic", "ARG"),          # a periodic axis shorter than the longest link
+    ("D2Q21", (4, 4, 2), "periodic", "ARG")])          # a 2-D lattice with n[2] != 1
+def test_long_link_lattices_rejected_where_unsupported(lattice, n, faces, code):
+    """Lattices with links up to three cells long take periodic axes of at
+    least three cells; the checks run on the host."""
+    import numpy as np
+    from paper_2401_17183_amd import vlbm
+    topo = vlbm.vlbm_topology()
+    if faces == "wall":
+        topo.face[1][0] = topo.face[1][1] = vlbm.WALL
+    h = ctypes.c_void_p()
+    X = np.zeros(4096)
+    with pytest.raises(vlbm.VlbmError) as e:
+        vlbm.vlbm_mesh_create(vlbm.LATTICES[lattice], (ctypes.c_int64 * 3)(*n),
+                              X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(topo), 1.0,
+                              ctypes.byref(h))
+    assert e.value.code == getattr(vlbm, "ERR_" + code)
 
 
 def test_conv_descriptor_rejected_without_a_device():

@@ -125,13 +125,16 @@ def shear_wave_rate(wl, steps=200, u0=1e-3, tau_g=None):
     return -np.log(amps[1] / amps[0]) / steps / (k / m.dx) ** 2
 
 
-@pytest.mark.parametrize("n,amp,tol,tau_g", [(48, 0.0, 3e-3, None), (32, 0.2, 2e-2, None),
-                                             (48, 0.0, 3e-3, 1.0), (32, 0.2, 2e-2, 1.0)])
-def test_shear_wave_viscosity(n, amp, tol, tau_g):
+@pytest.mark.parametrize("lat,n,amp,tol,tau_g", [("D2Q9", 48, 0.0, 3e-3, None), ("D2Q9", 32, 0.2, 2e-2, None),
+                                                  ("D2Q9", 48, 0.0, 3e-3, 1.0), ("D2Q9", 32, 0.2, 2e-2, 1.0),
+                                                  ("D2Q21", 48, 0.0, 3e-3, None), ("D2Q21", 32, 0.2, 2e-2, None)])
+def test_shear_wave_viscosity(lat, n, amp, tol, tau_g):
     """A decaying shear wave has nu = (tau - 1/2) T0 (Sec. 3, mu = (tau - 1/2) rho T0),
     on a Cartesian and on a wavy curvilinear periodic mesh; with the general
-    collision matrix too, whose stress relaxes at 1/tau by eq. (matrix)."""
-    wl = W.wavy_periodic("D2Q9", (n, n), amp)
+    collision matrix too, whose stress relaxes at 1/tau by eq. (matrix); and on
+    the sixth-order lattice, whose T0 is 2/3."""
+    from oracle import lattice
+    wl = W.wavy_periodic(lat, (n, n), amp)
     nu_meas = shear_wave_rate(wl, tau_g=tau_g)
-    nu = (wl["tau"] - 0.5) / 3.0
+    nu = (wl["tau"] - 0.5) * lattice.by_name(lat).T0
     assert abs(nu_meas / nu - 1) < tol, nu_meas / nu
