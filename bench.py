@@ -105,6 +105,9 @@ def cpu_baseline(workload="channel", seconds_target=12.0, tau_g=None, tau=None):
             "sample": f"{label}, FP64, {steps} steps, {dt:.1f} s, 1 thread"}
 
 
+# committed counter summaries per single-mesh workload: <stem>_<precision>[_tau..][_taug..].md
+PROFILE_STEM = {"channel": "k_step_d3q19_channel_256x128x128", "d3q39": "k_step_d3q39_wavy_128x128x128"}
+
 STEP_SOURCES = ["paper_2401_17183_amd/csrc/common.hpp", "paper_2401_17183_amd/csrc/dynamics.hpp",
                 "paper_2401_17183_amd/csrc/stepcore.hpp", "paper_2401_17183_amd/csrc/step.hip"]
 BATCH_SOURCES = STEP_SOURCES[:3] + ["paper_2401_17183_amd/csrc/batch.hip"]
@@ -204,9 +207,9 @@ def run_single(args, torch, vlbm):
         finite = False
         state = str(e)
     traffic = None
-    if args.workload == "channel" and args.precision in ("fp32", "fp32c"):
+    if args.workload in PROFILE_STEM:
         tag = ("" if args.tau is None else f"_tau{args.tau:g}") + ("" if args.tau_g is None else f"_taug{args.tau_g:g}")
-        traffic = profiled_traffic(f"k_step_d3q19_channel_256x128x128_{args.precision}{tag}.md", STEP_SOURCES)
+        traffic = profiled_traffic(f"{PROFILE_STEM[args.workload]}_{args.precision}{tag}.md", STEP_SOURCES)
     return {
         "metric": METRIC,
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
