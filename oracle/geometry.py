@@ -9,10 +9,10 @@ Boundary readings (the paper leaves boundaries out of its scope):
 * every non-periodic face carries two ghost node layers in the coordinate
   input, so that g_i exists on the first ghost layer and the contracted
   coefficient A (below) exists on every link of every real cell;
-* lattices with links longer than one cell (D2Q21, D3Q39) take periodic axes
-  only: the wall and far-field readings are for one-cell links.  g_i is then
-  needed s cells beyond every real cell (s the longest link), which the
-  periodic wrap supplies;
+* lattices with links longer than one cell (D2Q21, D3Q39, longest link s = 3
+  cells) need g_i s cells beyond every real cell: a non-periodic face then
+  carries s + 1 ghost node layers (ghost_layers()).  Such a lattice takes walls
+  on at most one axis (no corners) and no far-field faces;
 * a periodic axis i wraps the index and translates positions by a constant
   vector L_i: x(q + n_i e_i) = x(q) + L_i.
 
@@ -42,6 +42,12 @@ PERIODIC, WALL, FARFIELD = 0, 1, 2
 NGHOST = 2
 
 
+def ghost_layers(lat):
+    """Ghost node layers a non-periodic face carries: one more than the
+    longest link (2 for D2Q9 / D3Q19, 4 for D2Q21 / D3Q39)."""
+    return lat.speed + 1
+
+
 class MeshError(ValueError):
     """Degenerate mesh: beta undefined (D_i = D_-i) or J <= 0."""
 
@@ -50,8 +56,8 @@ class Mesh:
     """A body-fitted mesh.
 
     n      : tuple (n_1, .., n_d) of real cells per index axis
-    coords : float64 array (m_d, .., m_1, d); m_i = n_i + 4 on non-periodic axes
-             (two ghost layers per face), m_i = n_i on periodic axes
+    coords : float64 array (m_d, .., m_1, d); m_i = n_i + 2 ghost_layers on
+             non-periodic axes, m_i = n_i on periodic axes
     faces  : per axis (low, high) kinds, PERIODIC on both faces or on neither
     wrap   : per axis translation L_i (length-d vector; ignored unless periodic)
     dx     : the representative spacing of eq. (tangent)
@@ -70,8 +76,12 @@ class Mesh:
         for i in range(self.d):
             self.wrap[i] = np.asarray(wrap[i], dtype=np.float64)[: self.d]
         self.dx = float(dx)
-        if self.lat.speed > 1 and not all(f[0] == PERIODIC for f in self.faces):
-            raise MeshError(f"{self.lat.name} needs periodic axes (its links span {self.lat.speed} cells)")
+        if self.lat.speed > 1:
+            walls = [i for i, f in enumerate(self.faces) if f[0] != PERIODIC]
+            if any(FARFIELD in f for f in self.faces) or len(walls) > 1:
+                raise MeshError(f"{self.lat.name} takes walls on at most one axis and no far field")
+            if any(n < self.lat.speed for n in self.n):
+                raise MeshError(f"{self.lat.name} needs at least {self.lat.speed} cells per axis")
         self.coords = np.asarray(coords, dtype=np.float64)
         want = tuple(reversed([self.m(i) for i in range(self.d)])) + (self.d,)
         if self.coords.shape != want:
@@ -81,7 +91,7 @@ class Mesh:
         return self.faces[i][0] == PERIODIC
 
     def m(self, i):
-        return self.n[i] if self.periodic(i) else self.n[i] + 2 * NGHOST
+        return self.n[i] if self.periodic(i) else self.n[i] + 2 * ghost_layers(self.lat)
 
     @property
     def shape(self):
@@ -93,13 +103,17 @@ class Mesh:
         return int(np.prod(self.n))
 
 
-def padded_coords(mesh, layers=NGHOST):
+def padded_coords(mesh, layers=None):
     """x(q) for q^i in [-layers, n_i + layers) on every axis.
 
     Non-periodic axes read the supplied ghost layers; periodic axes wrap the
-    index and add the translation L_i per wrap.
+    index and add the translation L_i per wrap.  layers defaults to the ghost
+    layers of the lattice.
     """
+    if layers is None:
+        layers = ghost_layers(mesh.lat)
     d = mesh.d
+    ng = ghost_layers(mesh.lat)
     idx = []
     shifts = []
     for i in range(d):
@@ -108,9 +122,9 @@ def padded_coords(mesh, layers=NGHOST):
             idx.append(np.mod(q, mesh.n[i]))
             shifts.append(np.floor_divide(q, mesh.n[i]).astype(np.float64))
         else:
-            if layers > NGHOST:
+            if layers > ng:
                 raise MeshError("not enough ghost layers")
-            idx.append(q + NGHOST)
+            idx.append(q + ng)
             shifts.append(np.zeros(q.shape))
     # numpy axis order is (q^d, .., q^1)
     P = mesh.coords[np.ix_(*reversed(idx))].copy()

@@ -111,18 +111,28 @@ class Sim:
         return np.einsum("i...,ik...->k...", inner, g).reshape(d, -1).sum(axis=1)
 
     def wall_impulse(self):
-        """W of the step that produced the current state."""
+        """W of the step that produced the current state: per bounced link
+        (q, a) with source cell q_s, the arriving mid-link momentum minus the
+        departing one, g_i(q) (c^i_a - A^i_opp(a)(q)/2) N_a(q) + g_i(q_s)
+        (c^i_a - A^i_opp(a)(q_s)/2) N_a(q); for one-cell links q_s = q and
+        this is g_i(q) (2 c^i_a - A^i_opp(a)(q)) N_a(q)."""
         g, A, c, opp = self.geom.g, self.geom.A, self.lat.cf, self.lat.opp
         d = self.mesh.d
+        gf = g.reshape(d, d, -1)
+        Af = A.reshape(A.shape[0], d, -1)
         tot = np.zeros(d)
         for a in range(self.lat.Q):
-            _, kind = self.src[a]
-            m = kind == WALL
+            src, kind = self.src[a]
+            m = (kind == WALL).ravel()
             if not np.any(m):
                 continue
-            coef = 2.0 * c[a].reshape((d,) + (1,) * d) - A[opp[a]]     # (i, *n)
-            vec = np.einsum("i...,ik...->k...", coef, g)                 # (k, *n)
-            tot += np.sum(vec * (self.N[a] * m)[None], axis=tuple(range(1, d + 1)))
+            qs = src.ravel()[m]
+            qq = np.arange(self.mesh.ncells)[m]
+            n = self.N[a].ravel()[m]
+            here = c[a][:, None] - 0.5 * Af[opp[a]][:, qq]      # (i, links)
+            there = c[a][:, None] - 0.5 * Af[opp[a]][:, qs]
+            vec = np.einsum("il,ikl->kl", here, gf[:, :, qq]) + np.einsum("il,ikl->kl", there, gf[:, :, qs])
+            tot += np.sum(vec * n[None], axis=1)
         return tot
 
     def audit(self):

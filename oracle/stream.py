@@ -5,6 +5,15 @@ Readings for links whose source q - c_a lies outside the index box (the paper
 puts boundary treatment out of its scope):
 * periodic axis: the index wraps;
 * wall face: halfway bounce-back, N_a(q, t + 1) = N'_opp(a)(q, t);
+* wall face, links longer than one cell (D2Q21, D3Q39; walls on one axis
+  i only): the particle that arrives at q along c_a left a cell q_s along
+  -c_a, met the wall (half a cell beyond the last real cell), reversed and
+  finished the time step: N_a(q, t + 1) = N'_opp(a)(q_s, t).  With d the
+  distance of q_s from the wall in cells, its path gives
+  q_s^i = |c^i| - 1 - q^i at the low face (2 n_i - 1 - |c^i| - q^i at the
+  high face) and q_s^j = q^j - c^j (1 - (2 d + 1) / |c^i|) on the other axes
+  (integer on these lattices, whose diagonal links have |c^j| = |c^i|).  For a
+  one-cell link q_s = q, the rule above;
 * far-field face: N_a(q, t + 1) = N_inf_a(q), an imposed population;
 * a link leaving through both a far-field and a wall face counts as far-field.
 
@@ -21,10 +30,35 @@ from .geometry import PERIODIC, WALL, FARFIELD
 INTERIOR = 0
 
 
+def wall_source(mesh, a, q, i, mask):
+    """The cell q_s whose opposite population reaches q along direction a
+    after reflection at the wall of axis i (the multi-cell rule above);
+    q (list of index arrays), returns the list of q_s index arrays (valid
+    where mask, the links that do meet the wall, is set)."""
+    c = mesh.lat.c[a]
+    ci = int(c[i])
+    k = abs(ci)
+    n = mesh.n[i]
+    qs_i = (k - 1 - q[i]) if ci > 0 else (2 * n - 1 - k - q[i])
+    dist = qs_i if ci > 0 else n - 1 - qs_i
+    out = []
+    for j in range(mesh.d):
+        if j == i:
+            out.append(qs_i)
+            continue
+        cj = int(c[j])
+        num = cj * (k - 2 * dist - 1)            # c^j (1 - (2 d + 1) / |c^i|) |c^i|
+        assert np.all((num % k)[mask] == 0)
+        sj = q[j] - num // k
+        out.append(np.mod(sj, mesh.n[j]) if mesh.periodic(j) else sj)
+    return out
+
+
 def sources(mesh):
     """Per direction a: (flat source index (*n), kind (*n)) where kind is
-    INTERIOR, WALL or FARFIELD; for WALL/FARFIELD links the index is the cell
-    itself (the bounce-back slot)."""
+    INTERIOR, WALL or FARFIELD; for FARFIELD links the index is the cell
+    itself, for WALL links the cell whose opposite population bounces into q
+    (the cell itself for one-cell links)."""
     lat = mesh.lat
     d = mesh.d
     out = []
@@ -52,7 +86,14 @@ def sources(mesh):
         for i in reversed(range(d)):
             flat = flat * mesh.n[i] + s[i]
         own = np.arange(mesh.ncells).reshape(mesh.shape)
-        flat = np.where(kind == INTERIOR, flat, own)
+        bounce = own
+        if lat.speed > 1 and np.any(kind == WALL):
+            wi = [i for i in range(d) if not mesh.periodic(i)][0]
+            qs = wall_source(mesh, a, q, wi, kind == WALL)
+            bounce = np.zeros(mesh.shape, dtype=np.int64)
+            for i in reversed(range(d)):
+                bounce = bounce * mesh.n[i] + np.where(kind == WALL, qs[i], 0)
+        flat = np.where(kind == INTERIOR, flat, np.where(kind == WALL, bounce, own))
         out.append((flat, kind))
     return out
 

@@ -21,33 +21,44 @@ NGHOST = 2
 SEED = 2401
 
 
-def _cell_eta(n, lo=-1.0, hi=1.0):
-    """Cell-centred parameter values, two ghost layers each side."""
-    j = np.arange(-NGHOST, n + NGHOST)
+# lattices whose links span three cells: four ghost node layers per wall face,
+# and their lattice temperature (the others: two layers, T0 = 1/3)
+LONG_LINK = {"D2Q21": 2.0 / 3.0, "D3Q39": 2.0 / 3.0}
+
+
+def ghost_layers(lattice):
+    return 4 if lattice in LONG_LINK else NGHOST
+
+
+def _cell_eta(n, lo=-1.0, hi=1.0, ghost=NGHOST):
+    """Cell-centred parameter values, `ghost` layers each side."""
+    j = np.arange(-ghost, n + ghost)
     return lo + (j + 0.5) * (hi - lo) / n
 
 
-def _central_min(y):
+def _central_min(y, ghost=NGHOST):
     """Smallest central spacing (y_{j+1} - y_{j-1}) / 2 over real nodes."""
-    yr = y[NGHOST - 1: len(y) - NGHOST + 1]
+    yr = y[ghost - 1: len(y) - ghost + 1]
     return float(np.min((yr[2:] - yr[:-2]) / 2.0))
 
 
-def tanh_channel_2d(n1=64, n2=32, strength=2.0, tau=0.8, G=1e-6):
+def tanh_channel_2d(n1=64, n2=32, strength=2.0, tau=0.8, G=1e-6, lattice="D2Q9", dx_ratio=np.sqrt(3.0)):
     """Plane channel, periodic x, walls at y = +-1, y = tanh(s eta)/tanh(s).
 
-    dx = sqrt(3) * (smallest central wall-normal spacing), streamwise spacing dx.
+    dx = dx_ratio * (smallest central wall-normal spacing), streamwise spacing
+    dx.  lattice D2Q21 carries four ghost node layers per wall face.
     """
-    eta = _cell_eta(n2)
+    ng = ghost_layers(lattice)
+    eta = _cell_eta(n2, ghost=ng)
     y = np.tanh(strength * eta) / np.tanh(strength)
-    dx = np.sqrt(3.0) * _central_min(y)
+    dx = dx_ratio * _central_min(y, ng)
     x = np.arange(n1) * dx
     X = np.empty((len(y), n1, 2))
     X[..., 0] = x[None, :]
     X[..., 1] = y[:, None]
     return {
-        "name": f"D2Q9 tanh({strength}) channel {n1}x{n2}",
-        "lattice": "D2Q9", "n": (n1, n2), "coords": X,
+        "name": f"{lattice} tanh({strength}) channel {n1}x{n2}",
+        "lattice": lattice, "ghost": ng, "n": (n1, n2), "coords": X,
         "faces": [(PERIODIC, PERIODIC), (WALL, WALL)],
         "wrap": [(n1 * dx, 0.0), (0.0, 0.0)], "dx": dx,
         "tau": tau, "body_force": (G, 0.0), "half_height": 1.0 / dx,
@@ -58,8 +69,9 @@ def poiseuille_fields(w):
     """Analytic plane Poiseuille profile u = G (H^2 - Y^2) / (2 nu) in lattice
     units (Y, H in units of dx), rho = 1; used as the initial state."""
     n1, n2 = w["n"]
-    nu = (w["tau"] - 0.5) / 3.0
-    y = w["coords"][NGHOST:NGHOST + n2, 0, 1] / w["dx"]
+    nu = (w["tau"] - 0.5) * LONG_LINK.get(w["lattice"], 1.0 / 3.0)
+    ng = w.get("ghost", NGHOST)
+    y = w["coords"][ng:ng + n2, 0, 1] / w["dx"]
     H = w["half_height"]
     G = w["body_force"][0]
     ux = G * (H * H - y * y) / (2.0 * nu)
@@ -69,12 +81,14 @@ def poiseuille_fields(w):
 
 
 def tanh_channel_3d(n1=256, n2=128, n3=128, strength=2.5, tau=0.52, G=1e-6,
-                    noise=1e-3, seed=SEED):
+                    noise=1e-3, seed=SEED, lattice="D3Q19", dx_ratio=np.sqrt(3.0)):
     """Channel: x, z periodic, walls at y = +-1, y = tanh(s eta)/tanh(s);
-    initial rho = 1, u ~ U(-noise, noise) per component (seeded)."""
-    eta = _cell_eta(n2)
+    initial rho = 1, u ~ U(-noise, noise) per component (seeded);
+    dx = dx_ratio * (smallest central wall-normal spacing)."""
+    ng = ghost_layers(lattice)
+    eta = _cell_eta(n2, ghost=ng)
     y = np.tanh(strength * eta) / np.tanh(strength)
-    dx = np.sqrt(3.0) * _central_min(y)
+    dx = dx_ratio * _central_min(y, ng)
     X = np.empty((n3, len(y), n1, 3))
     X[..., 0] = (np.arange(n1) * dx)[None, None, :]
     X[..., 1] = y[None, :, None]
@@ -82,8 +96,8 @@ def tanh_channel_3d(n1=256, n2=128, n3=128, strength=2.5, tau=0.52, G=1e-6,
     rng = np.random.default_rng(seed)
     u = rng.uniform(-noise, noise, size=(3, n3, n2, n1))
     return {
-        "name": f"D3Q19 tanh({strength}) channel {n1}x{n2}x{n3}",
-        "lattice": "D3Q19", "n": (n1, n2, n3), "coords": X,
+        "name": f"{lattice} tanh({strength}) channel {n1}x{n2}x{n3}",
+        "lattice": lattice, "ghost": ng, "n": (n1, n2, n3), "coords": X,
         "faces": [(PERIODIC, PERIODIC), (WALL, WALL), (PERIODIC, PERIODIC)],
         "wrap": [(n1 * dx, 0, 0), (0, 0, 0), (0, 0, n3 * dx)], "dx": dx,
         "tau": tau, "body_force": (G, 0.0, 0.0),

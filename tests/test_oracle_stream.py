@@ -9,8 +9,14 @@ from tests.oracle_helpers import mesh_of, sim_of
 
 @pytest.mark.parametrize("wl", [W.tanh_channel_2d(6, 5), W.wavy_channel_3d(5, 4, 3),
                                 W.wavy_periodic("D3Q19", (4, 5, 3), 0.1), W.wavy_periodic("D2Q21", (5, 4), 0.1),
-                                W.wavy_periodic("D3Q39", (4, 5, 3), 0.1)], ids=lambda w: w["name"])
+                                W.wavy_periodic("D3Q39", (4, 5, 3), 0.1),
+                                W.tanh_channel_2d(6, 7, strength=0.3, lattice="D2Q21", dx_ratio=1.0),
+                                W.tanh_channel_3d(5, 7, 4, strength=0.3, lattice="D3Q39", dx_ratio=1.0)],
+                         ids=lambda w: w["name"])
 def test_stream_is_a_permutation(wl):
+    """Every post-collision population lands in exactly one slot, also with the
+    multi-cell bounce-back of the long-link lattices (a wrong mirror source
+    would send two links to one slot)."""
     m = mesh_of(wl)
     ids = np.arange(m.lat.Q * m.ncells, dtype=np.float64).reshape((m.lat.Q,) + m.shape)
     out = S.stream(m, ids)
