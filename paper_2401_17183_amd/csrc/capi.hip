@@ -136,6 +136,8 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
   m->lattice = lattice;
   m->d = d;
   m->Q = lattice == VLBM_D2Q9 ? 9 : lattice == VLBM_D3Q19 ? 19 : lattice == VLBM_D2Q21 ? 21 : 39;
+  const int ghost = speed + 1;   // ghost node layers per non-periodic face
+  int wall_axes = 0;
   m->dx = dx;
   size_t ncoord = (size_t)d;
   for (int i = 0; i < 3; ++i) {
@@ -156,18 +158,21 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
         delete m;
         return fail(VLBM_ERR_ARG, "periodic axis %d needs at least 2 cells", i);
       }
-      // links longer than one cell have only the periodic reading
-      if (speed > 1 && lo != VLBM_PERIODIC) {
+      // links longer than one cell: walls on one axis at most, no far field
+      if (speed > 1 && (lo == VLBM_FARFIELD || hi == VLBM_FARFIELD)) {
         delete m;
-        return fail(VLBM_ERR_UNSUPPORTED, "axis %d: this lattice's links span %d cells; it needs periodic axes",
-                    i, speed);
+        return fail(VLBM_ERR_UNSUPPORTED, "axis %d: far-field faces are built for one-cell links only", i);
       }
-      if (lo == VLBM_PERIODIC && n[i] < speed) {
+      if (speed > 1 && lo == VLBM_WALL && ++wall_axes > 1) {
         delete m;
-        return fail(VLBM_ERR_ARG, "periodic axis %d needs at least %d cells for this lattice", i, speed);
+        return fail(VLBM_ERR_UNSUPPORTED, "this lattice takes walls on one axis at most");
+      }
+      if (n[i] < speed) {
+        delete m;
+        return fail(VLBM_ERR_ARG, "axis %d needs at least %d cells for this lattice", i, speed);
       }
     }
-    m->m[i] = !active ? 1 : (m->box.face[i][0] == VLBM_PERIODIC ? (int)n[i] : (int)n[i] + 4);
+    m->m[i] = !active ? 1 : (m->box.face[i][0] == VLBM_PERIODIC ? (int)n[i] : (int)n[i] + 2 * ghost);
     ncoord *= m->m[i];
     for (int k = 0; k < 3; ++k) m->wrap[i][k] = (active && k < d) ? topo->wrap[i][k] : 0.0;
   }

@@ -171,10 +171,18 @@ enum LinkKind { LINK_INTERIOR = 0, LINK_WALL = 1, LINK_FARFIELD = 2 };
 // (eq. (adv)).  Periodic axes wrap; a link that leaves through a far-field
 // face is FARFIELD, otherwise through a wall face is WALL.  Written with
 // selects only, so that a wavefront never diverges on it.
+//
+// A WALL link reads the opposite population of its bounce-back source: the
+// cell itself for one-cell links.  A longer link (D2Q21, D3Q39: walls on one
+// axis i only) follows its straight path reflected at the wall, half a cell
+// beyond the last real cell: the source lies d cells from the wall with
+// q_s^i = |c^i| - 1 - q^i (low face) or 2 n_i - 1 - |c^i| - q^i (high face),
+// and q_s^j = q^j - c^j (|c^i| - 2 d - 1) / |c^i| on the other (periodic) axes.
 template <class L>
 __device__ __forceinline__ int link_source(const Box& b, int a, int x, int y, int z, int& src) {
+  const int q0[3] = {x, y, z};
   int q[3] = {x, y, z};
-  int wall = 0, far = 0;
+  int wall = 0, far = 0, wax = 0;
 #pragma unroll
   for (int i = 0; i < L::D; ++i) {
     const int ci = L::c(a, i);
@@ -186,12 +194,42 @@ __device__ __forceinline__ int link_source(const Box& b, int a, int x, int y, in
     const int f = b.face[i][side];
     const int per = f == VLBM_PERIODIC;
     q[i] = out ? (per ? (ci > 0 ? s + n : s - n) : q[i]) : s;
-    wall |= out & (f == VLBM_WALL);
+    const int w = out & (f == VLBM_WALL);
+    wall |= w;
+    wax = w ? i : wax;
     far |= out & (f == VLBM_FARFIELD);
   }
   src = q[0] + b.n[0] * (q[1] + b.n[1] * q[2]);
   // non-periodic exits keep the own cell as source (the bounce-back slot)
   src = (wall | far) ? x + b.n[0] * (y + b.n[1] * z) : src;
+  if constexpr (L::SPEED > 1) {
+    // every non-zero component of a link of these lattices has the same
+    // magnitude k, so the shift c^j (k - 2 d - 1) / k is sgn(c^j) (k - 2 d - 1)
+    int qs[3] = {x, y, z};
+    int dist = 0;
+#pragma unroll
+    for (int i = 0; i < L::D; ++i) {
+      const int ci = L::c(a, i);
+      if (ci == 0) continue;
+      const int n = b.n[i];
+      const int kk = ci > 0 ? ci : -ci;
+      const int si = ci > 0 ? kk - 1 - q0[i] : 2 * n - 1 - kk - q0[i];
+      const int here = i == wax;
+      qs[i] = here ? si : qs[i];
+      dist = here ? (ci > 0 ? si : n - 1 - si) : dist;
+    }
+#pragma unroll
+    for (int j = 0; j < L::D; ++j) {
+      const int cj = L::c(a, j);
+      if (cj == 0) continue;
+      const int k = cj > 0 ? cj : -cj;
+      const int n = b.n[j];
+      int s = q0[j] - (cj > 0 ? 1 : -1) * (k - 2 * dist - 1);
+      s = s < 0 ? s + n : (s >= n ? s - n : s);
+      qs[j] = j == wax ? qs[j] : s;
+    }
+    src = (wall & !far) ? qs[0] + b.n[0] * (qs[1] + b.n[1] * qs[2]) : src;
+  }
   return far ? LINK_FARFIELD : (wall ? LINK_WALL : LINK_INTERIOR);
 }
 

@@ -15,6 +15,7 @@ struct GeoArgs {
   int d;
   int m[3];           // coordinate extents
   int layers;         // box layers around the real cells: the lattice's longest link
+  int ghost;          // ghost node layers per non-periodic face (layers + 1)
   int nb[3];          // box extents (n_i + 2 layers on axes < d, 1 otherwise)
   int nbox;
   double wrap[3][3];
@@ -31,8 +32,8 @@ struct GeoArgs {
 };
 
 // x(q) for q outside the real box: periodic axes wrap the index (any number of
-// periods) and add the translation, non-periodic axes read the two ghost node
-// layers (the only layers a one-cell lattice needs there).
+// periods) and add the translation, non-periodic axes read the ghost node
+// layers of the coordinate input.
 __device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
   int idx[3] = {0, 0, 0};
   double shift[3] = {0, 0, 0};
@@ -46,7 +47,7 @@ __device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
       idx[i] = qi;
       shift[i] = (double)s;
     } else {
-      idx[i] = qi + 2;
+      idx[i] = qi + a.ghost;
     }
   }
   const long off = ((long)idx[2] * a.m[1] + idx[1]) * a.m[0] + idx[0];
@@ -259,6 +260,7 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
   a.d = m->d;
   a.nbox = 1;
   a.layers = lattice_speed(m->lattice);
+  a.ghost = a.layers + 1;
   for (int i = 0; i < 3; ++i) {
     a.m[i] = m->m[i];
     a.nb[i] = i < m->d ? m->box.n[i] + 2 * a.layers : 1;

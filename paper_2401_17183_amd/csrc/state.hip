@@ -281,9 +281,9 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
     double gi[D][D];
     for (int i = 0; i < D; ++i)
       for (int k = 0; k < D; ++k) gi[i][k] = a.g[(i * D + k) * nc + cell];
-    double mass = 0, inner[D], wall[D];
+    double mass = 0, inner[D], wall[D], wallE[D];
     int nonfinite = 0, negative = 0;
-    for (int i = 0; i < D; ++i) inner[i] = wall[i] = 0;
+    for (int i = 0; i < D; ++i) inner[i] = wall[i] = wallE[i] = 0;
 #pragma unroll
     for (int al = 0; al < Q; ++al) {
       const double n = N[al];
@@ -297,10 +297,28 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
         inner[i] += (ci - 0.5 * Ao) * n;
         if ((wm >> al) & 1) wall[i] += (2.0 * ci - Ao) * n;
       }
+      if constexpr (L::SPEED > 1) {
+        // a bounced long link arrives from another cell q_s: its departing
+        // mid-link momentum g_i(q_s) (c^i - A^i_opp(q_s)/2) N replaces the
+        // second copy of this cell's in the one-cell form 2 c - A_opp
+        if ((wm >> al) & 1) {
+          int src;
+          (void)link_source<L>(a.box, al, x, y, z, src);
+#pragma unroll
+          for (int i = 0; i < D; ++i) {
+            const double ci = L::c(al, i);
+            const double ah = g.a(opp(al), i);
+            const double as = a.A[(opp(al) * D + i) * nc + src];
+            wall[i] -= (ci - 0.5 * ah) * n;   // keep this cell's half only
+#pragma unroll
+            for (int k = 0; k < D; ++k) wallE[k] += a.g[(i * D + k) * nc + src] * (ci - 0.5 * as) * n;
+          }
+        }
+      }
     }
     v[0] = mass;
     for (int k = 0; k < D; ++k) {
-      double sI = 0, sW = 0;
+      double sI = 0, sW = wallE[k];
       for (int i = 0; i < D; ++i) {
         sI += gi[i][k] * inner[i];
         sW += gi[i][k] * wall[i];

@@ -104,17 +104,23 @@ def test_mesh_arguments_rejected_without_a_device(case):
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libvlbm.so not built")
 @pytest.mark.parametrize("lattice,n,faces,code", [
-    ("D3Q39", (4, 4, 4), "wall", "UNSUPPORTED"),      # three-cell links: periodic axes only
-    ("D2Q21", (4, 2, 1), "periodic", "ARG"),          # a periodic axis shorter than the longest link
-    ("D2Q21", (4, 4, 2), "periodic", "ARG")])          # a 2-D lattice with n[2] != 1
+    ("D3Q39", (4, 4, 4), "two walls", "UNSUPPORTED"),  # three-cell links: walls on one axis at most
+    ("D3Q39", (4, 4, 4), "far field", "UNSUPPORTED"),  # and no far field
+    ("D2Q21", (4, 2, 1), "periodic", "ARG"),           # an axis shorter than the longest link
+    ("D2Q21", (4, 4, 2), "periodic", "ARG")])           # a 2-D lattice with n[2] != 1
 def test_long_link_lattices_rejected_where_unsupported(lattice, n, faces, code):
-    """Lattices with links up to three cells long take periodic axes of at
-    least three cells; the checks run on the host."""
+    """Lattices with links up to three cells long take axes of at least three
+    cells, walls on one axis at most and no far field; the checks run on the
+    host."""
     import numpy as np
     from paper_2401_17183_amd import vlbm
     topo = vlbm.vlbm_topology()
-    if faces == "wall":
+    if faces == "two walls":
         topo.face[1][0] = topo.face[1][1] = vlbm.WALL
+        topo.face[2][0] = topo.face[2][1] = vlbm.WALL
+    elif faces == "far field":
+        topo.face[1][0] = vlbm.WALL
+        topo.face[1][1] = vlbm.FARFIELD
     h = ctypes.c_void_p()
     X = np.zeros(4096)
     with pytest.raises(vlbm.VlbmError) as e:

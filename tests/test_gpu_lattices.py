@@ -1,6 +1,7 @@
 """Sixth-order isotropic lattices (D2Q21, D3Q39: eq. (iso) in full, T0 = 2/3,
-links up to three cells long, periodic meshes) on the GPU versus the FP64
-oracle: geometry, streaming, initial state, steps, audits."""
+links up to three cells long, on periodic boxes and on channels whose walls
+reflect the long links) on the GPU versus the FP64 oracle: geometry,
+streaming, initial state, steps, audits."""
 import numpy as np
 import pytest
 
@@ -32,9 +33,12 @@ def gpu_sim(w, precision="fp64", rho=None, u=None, mesh=None, **kw):
     return v.Sim(mesh, p, rho=rho, u=u), mesh
 
 
-# ragged sizes, several periods of the longest link on every axis
-MESHES = [W.wavy_periodic("D2Q21", (22, 17), 0.12), W.wavy_periodic("D3Q39", (9, 7, 6), 0.08)]
-IDS = [w["lattice"] for w in MESHES]
+# ragged sizes, several periods of the longest link on every axis; the
+# channels have walls (multi-cell bounce-back) on their second axis
+MESHES = [W.wavy_periodic("D2Q21", (22, 17), 0.12), W.wavy_periodic("D3Q39", (9, 7, 6), 0.08),
+          W.tanh_channel_2d(12, 14, strength=0.3, lattice="D2Q21", dx_ratio=1.0),
+          W.tanh_channel_3d(7, 9, 5, strength=0.3, tau=0.8, lattice="D3Q39", dx_ratio=1.0)]
+IDS = [w["lattice"] + (" channel" if "channel" in w["name"] else " wavy") for w in MESHES]
 
 
 def seeded_flow(o, seed=11, amp=0.02):
@@ -134,10 +138,11 @@ def test_reduced_precision_velocity(w, precision, bound):
 
 
 @pytest.mark.parametrize("w", MESHES, ids=IDS)
-def test_audits_conserve(w):
-    """Periodic mesh, no force: mass and the mid-link momentum I are conserved
-    to roundoff every step (eqs. (conserv), (omcons), (constraint2)) and equal
-    the oracle's audits."""
+def test_audits_balance(w):
+    """Mass is conserved to roundoff and the mid-link momentum obeys
+    I(t+1) = I(t) + G * mass + W(t) every step, W the wall impulse of the
+    bounced links (multi-cell bounce-back included); the audits equal the
+    oracle's."""
     announce(f"audits {w['name']}")
     o = sim_of(w)
     rho, u = seeded_flow(o)
@@ -148,14 +153,20 @@ def test_audits_conserve(w):
     s.step(4)
     aud = s.audits()
     assert len(aud) == 5
+    prev = None
     for k, a in enumerate(aud):
         if k > 0:
             o.step()
         oa = o.audit()
-        assert abs(a["mass"] - oa["mass"]) <= 1e-13 * oa["mass"]
-        assert np.allclose(a["mom_I"][:d], oa["mom_I"], rtol=0, atol=1e-12 * oa["mass"])
-        assert np.allclose(a["mom_I"], aud[0]["mom_I"], rtol=0, atol=1e-12 * oa["mass"])
+        scale = oa["mass"]
+        assert abs(a["mass"] - oa["mass"]) <= 1e-13 * scale
+        assert np.allclose(a["mom_I"][:d], oa["mom_I"], rtol=0, atol=1e-12 * scale)
+        assert np.allclose(a["wall_impulse"][:d], oa["wall_impulse"], rtol=0, atol=1e-12 * scale)
+        if prev is not None:
+            bal = a["mom_I"] - prev["mom_I"] - prev["force_impulse"] - a["wall_impulse"]
+            assert np.max(np.abs(bal)) <= 1e-12 * scale, bal
         assert a["nonfinite"] == 0 and a["unconverged"] == 0
+        prev = a
 
 
 def test_sixteen_bit_storage_and_batches_are_rejected():
