@@ -269,11 +269,19 @@ int vlbm_batch_sync(vlbm_batch b);
  * cache_path (nullable; a cached entry for the same key is reused). */
 int vlbm_batch_autotune(vlbm_batch b, int trial_steps, const char* cache_path, int* block, int* grid_per_cu);
 int vlbm_batch_destroy(vlbm_batch b);
-/* Audit every member now (as vlbm_audit_now) and write each member's
+/* Audit every active member now (as vlbm_audit_now) and write each member's
  * steady-state residual r = ||u - u_prev||_2 / ||u||_2 (u = output velocity,
  * u_prev = that of the member's previous audit; NaN at a member's first audit)
- * to residual[count] (host).  Synchronises the batch stream. */
+ * to residual[count] (host); a retired member reports its last audit.
+ * Synchronises the batch stream. */
 int vlbm_batch_residuals(vlbm_batch b, double* residual);
+/* Choose the members vlbm_batch_step advances: active host int32[count],
+ * non-zero = stepped (NULL = all).  A retired member keeps its state and step
+ * count; the launch covers only the active members' cells, so a batch whose
+ * members converge at different times costs what its active cells cost.  The
+ * active members must share one step count (VLBM_ERR_STATE otherwise).
+ * Synchronises the batch stream. */
+int vlbm_batch_set_active(vlbm_batch b, const int32_t* active);
 
 /* ---- Learned warm start: a convolutional surrogate on BF16 MFMA ----------
  *

@@ -62,8 +62,9 @@ hipError_t upload_args(BatchObj* b) {
 }
 
 hipError_t build_tiles(BatchObj* b) {
-  std::vector<int> order(b->members.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::vector<int> order;
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->active.empty() || b->active[i]) order.push_back((int)i);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return b->members[x]->mesh->box.ncells > b->members[y]->mesh->box.ncells;
   });
@@ -74,6 +75,8 @@ hipError_t build_tiles(BatchObj* b) {
   }
   b->ntiles = (int)tiles.size();
   if (b->d_tiles) (void)hipFree(b->d_tiles);
+  b->d_tiles = nullptr;
+  if (tiles.empty()) return hipSuccess;
   hipError_t e = hipMalloc((void**)&b->d_tiles, sizeof(Tile) * tiles.size());
   if (e != hipSuccess) return e;
   return hipMemcpy(b->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
@@ -122,6 +125,7 @@ hipError_t upload_lattice(BatchObj* b) {
 }  // namespace
 
 hipError_t batch_launch(BatchObj* b, int parity) {
+  if (b->ntiles == 0) return hipSuccess;   // no active member
   return b->lattice == VLBM_D2Q9 ? launch_batch_lattice<D2Q9>(b, parity) : launch_batch_lattice<D3Q19>(b, parity);
 }
 
@@ -156,7 +160,9 @@ hipError_t batch_capture(BatchObj* b, int p, bool per_member) {
     if (!per_member) {
       le = batch_launch(b, par);
     } else {
-      for (SimObj* s : b->members) {
+      for (size_t m = 0; m < b->members.size(); ++m) {
+        if (!b->active[m]) continue;
+        SimObj* s = b->members[m];
         const int keep = s->buf;
         s->buf = par;
         le = launch_step(s);

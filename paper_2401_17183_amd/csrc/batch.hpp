@@ -14,6 +14,7 @@ struct Tile {
 
 struct BatchObj {
   std::vector<SimObj*> members;
+  std::vector<char> active;          // per member: stepped by vlbm_batch_step (all by default)
   int lattice = 0, precision = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;

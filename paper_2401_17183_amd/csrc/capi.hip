@@ -590,6 +590,7 @@ int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int co
     b->any_ff = b->any_ff || s->has_farfield;
     b->any_general = b->any_general || general_collision(s->p);
   }
+  b->active.assign(b->members.size(), 1);
   if (batch_upload(b) != hipSuccess) {
     fail(VLBM_ERR_DEVICE, "batch upload failed");
     return bail(VLBM_ERR_DEVICE);
@@ -624,6 +625,11 @@ int vlbm_batch_residuals(vlbm_batch bh, double* residual) {
   std::vector<const double*> src(n);
   for (int i = 0; i < n; ++i) {
     SimObj* s = b->members[i];
+    if (!b->active[i] && s->audit_head > 0) {   // retired: its last residual
+      const int last = (int)((s->audit_head - 1) % s->audit_cap);
+      src[i] = &static_cast<const vlbm_audit*>(s->audit_ring)[last].residual;
+      continue;
+    }
     const int slot = (int)(s->audit_head % s->audit_cap);
     HIP_TRY(launch_audit(s, slot));
     s->audit_head++;
@@ -681,31 +687,44 @@ static int batch_one_step_eager(BatchObj* b, int parity, bool per_member) {
   if (!per_member) {
     HIP_TRY(batch_launch(b, parity));
   } else {
-    for (SimObj* s : b->members) HIP_TRY(launch_step(s));
+    for (size_t m = 0; m < b->members.size(); ++m)
+      if (b->active[m]) HIP_TRY(launch_step(b->members[m]));
   }
   return VLBM_OK;
 }
 
 static void batch_advance(BatchObj* b, int64_t k) {
-  for (SimObj* s : b->members) {
+  for (size_t m = 0; m < b->members.size(); ++m) {
+    if (!b->active[m]) continue;
+    SimObj* s = b->members[m];
     s->t += k;
     if (k & 1) s->buf ^= 1;
   }
   b->t += k;
 }
 
+// The first active member (its step count and buffer parity are the batch's),
+// or nullptr when every member is retired.
+static SimObj* batch_lead(const BatchObj* b) {
+  for (size_t m = 0; m < b->members.size(); ++m)
+    if (b->active[m]) return b->members[m];
+  return nullptr;
+}
+
 int vlbm_batch_step(vlbm_batch bh, int64_t nsteps) {
   BatchObj* b = reinterpret_cast<BatchObj*>(bh);
   if (!b || nsteps < 0) return fail(VLBM_ERR_ARG, "vlbm_batch_step: bad argument");
-  for (SimObj* s : b->members)
-    if (s->buf != b->members[0]->buf || s->t != b->members[0]->t)
+  SimObj* lead = batch_lead(b);
+  if (!lead) return ok();   // every member retired: nothing to step
+  for (size_t m = 0; m < b->members.size(); ++m)
+    if (b->active[m] && (b->members[m]->buf != lead->buf || b->members[m]->t != lead->t))
       return fail(VLBM_ERR_STATE, "batch members were stepped individually; they must share one step count");
   const bool per_member = b->mode >= VLBM_BATCH_EAGER;
   const bool graphs = b->mode == VLBM_BATCH_PERSISTENT_GRAPH || b->mode == VLBM_BATCH_EAGER_GRAPH;
   int64_t done = 0;
   if (graphs) {
     while (nsteps - done >= b->graph_steps) {
-      const int par = b->members[0]->buf;
+      const int par = lead->buf;
       if (!b->exec[par]) {
         hipError_t e = batch_capture(b, par, per_member);
         if (e != hipSuccess) return fail(VLBM_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
@@ -716,10 +735,35 @@ int vlbm_batch_step(vlbm_batch bh, int64_t nsteps) {
     }
   }
   for (; done < nsteps; ++done) {
-    const int rc = batch_one_step_eager(b, b->members[0]->buf, per_member);
+    const int rc = batch_one_step_eager(b, lead->buf, per_member);
     if (rc) return rc;
     batch_advance(b, 1);
   }
+  return ok();
+}
+
+int vlbm_batch_set_active(vlbm_batch bh, const int32_t* active) {
+  BatchObj* b = reinterpret_cast<BatchObj*>(bh);
+  if (!b) return fail(VLBM_ERR_ARG, "null batch");
+  const size_t n = b->members.size();
+  std::vector<char> next(n, 1);
+  if (active)
+    for (size_t m = 0; m < n; ++m) next[m] = active[m] != 0;
+  // the members stepped together must share their step count and parity
+  const SimObj* lead = nullptr;
+  for (size_t m = 0; m < n; ++m) {
+    if (!next[m]) continue;
+    const SimObj* s = b->members[m];
+    if (!lead) lead = s;
+    else if (s->t != lead->t || s->buf != lead->buf)
+      return fail(VLBM_ERR_STATE, "member %zu is at step %lld, the others at %lld: they cannot step together", m,
+                  (long long)s->t, (long long)lead->t);
+  }
+  if (next == b->active) return ok();
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  batch_drop_graphs(b);
+  b->active = next;
+  if (batch_upload(b) != hipSuccess) return fail(VLBM_ERR_DEVICE, "batch upload failed");
   return ok();
 }
 

@@ -24,9 +24,11 @@ __global__ __launch_bounds__(BLOCK) void k_step64(StepArgs<P, S, T> a) {
 }
 
 // Threads per block: D3Q39 stages its 114 A words per cell in LDS, so its
-// blocks are smaller (58 KB of LDS either way).
-template <class L, class S> constexpr int block_for() {
-  return L::Q > 21 ? (sizeof(S) == 4 ? 128 : 64) : kBlock;
+// blocks are smaller: 128 threads with FP64 arithmetic on FP32 geometry (one
+// wave per SIMD, no spills), 64 otherwise (measured faster for FP32
+// arithmetic; FP64 geometry needs 58 KB of LDS per 64 threads).
+template <class L, class S, class T> constexpr int block_for() {
+  return L::Q > 21 ? ((sizeof(S) == 4 && sizeof(T) == 8) ? 128 : 64) : kBlock;
 }
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
@@ -61,7 +63,7 @@ template <class L, class P, class S, class T>
 hipError_t step_typed(SimObj* s) {
   const StepArgs<P, S, T> a = make_step_args<P, S, T>(s);
   if constexpr (L::SPEED > 1) {   // periodic axes only: no far field
-    constexpr int B = block_for<L, S>();
+    constexpr int B = block_for<L, S, T>();
     const int nb = (a.box.ncells + B - 1) / B;
     if constexpr (sizeof(S) == 8) {
       if (a.general) k_step64<L, P, S, T, 0, true, B><<<nb, B, 0, s->stream>>>(a);

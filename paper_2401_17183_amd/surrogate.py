@@ -67,13 +67,18 @@ def make_batch(ws, precision="fp32"):
     return vlbm.Batch(meshes, params), meshes
 
 
-def solve_steady(batch, tol=1e-6, check_every=100, max_steps=400000, log=None):
+def solve_steady(batch, tol=1e-6, check_every=100, max_steps=400000, log=None, retire=True):
     """Step the whole batch until every member's residual is <= tol (or
-    max_steps).  Returns per-member steps to convergence (-1 if not reached),
-    the total steps taken and the wall time (s)."""
+    max_steps).  With retire, a member stops being stepped once it has
+    converged, so the launches cover only the members still running (they are
+    left retired: a member is stepped again after vlbm_reinit and set_active).
+    The members start at one step count.  Returns per-member steps to
+    convergence (-1 if not reached), the total steps taken and the wall time (s)."""
     import torch
     n = len(batch.members)
     steps = np.full(n, -1, dtype=np.int64)
+    if retire:
+        batch.set_active(None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.residuals()              # baseline velocity for the first residual
@@ -90,6 +95,8 @@ def solve_steady(batch, tol=1e-6, check_every=100, max_steps=400000, log=None):
             log(f"step {t}: {int((steps >= 0).sum())}/{n} converged, max r {np.max(r):.2e}")
         if np.all(steps >= 0):
             break
+        if retire and np.any(newly):
+            batch.set_active(steps < 0)
     batch.sync()
     return steps, t, time.perf_counter() - t0
 

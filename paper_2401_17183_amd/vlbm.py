@@ -114,6 +114,7 @@ _SIGS = {
     "vlbm_batch_autotune": (C.c_int, [_P, C.c_int, C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "vlbm_batch_destroy": (C.c_int, [_P]),
     "vlbm_batch_residuals": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "vlbm_batch_set_active": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "vlbm_conv2d_forward": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P, _P, _P, _P]),
     "vlbm_conv2d_backward_data": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P, _P]),
     "vlbm_conv2d_backward_weight": (C.c_int, [C.POINTER(vlbm_conv_desc), _P, _P, _P, _P, _P, _P]),
@@ -422,6 +423,14 @@ class Batch:
         out = (C.c_double * len(self.members))()
         vlbm_batch_residuals(self.h, out)
         return np.array(out[:])
+
+    def set_active(self, active=None):
+        """Members stepped by step(): a boolean sequence of length count (None = all)."""
+        if active is None:
+            vlbm_batch_set_active(self.h, None)
+            return
+        a = (C.c_int32 * len(self.members))(*[1 if x else 0 for x in active])
+        vlbm_batch_set_active(self.h, a)
 
     def autotune(self, trial_steps=20, cache_path=None):
         bl, gp = C.c_int(), C.c_int()

@@ -213,3 +213,46 @@ def test_full_batch_sampled_parity_fp32():
         print(f"member {k} {w['n']} velocity rel L2 {rel:.3e}")
         assert rel <= 1e-5, (k, w["n"], rel)
     b.close()
+
+
+@pytest.mark.parametrize("mode", ["BATCH_PERSISTENT_GRAPH", "BATCH_EAGER"])
+def test_retired_members_keep_their_state(mode):
+    """Members retired with set_active keep their state and step count while
+    the others advance; every member still equals its solo run bit for bit.
+    Members at different step counts cannot be stepped together; the retired
+    ones can, once they share a step count; retiring everything makes step a
+    no-op."""
+    v = _vlbm()
+    announce(f"batch retirement {mode}")
+    b, meshes = _batch(SMALL_BATCH, "fp32")
+    solo = _solo(SMALL_BATCH, meshes, "fp32")
+    b.set_mode(getattr(v, mode))
+    b.step(40)
+    r0 = b.residuals()
+    keep = [True, False, True, False, True]
+    b.set_active(keep)
+    b.step(70)                       # two 32-step graphs and an eager remainder
+    r1 = b.residuals()
+    for k, s in enumerate(solo):
+        s.step(110 if keep[k] else 40)
+    b.sync()
+    for k, (x, y) in enumerate(zip(_pops(b.members), _pops(solo))):
+        assert torch.equal(x, y), (k, float((x - y).abs().max()))
+        assert b.members[k].t == (110 if keep[k] else 40)
+    # retired members report their last residual
+    assert np.array_equal(r1[[1, 3]], r0[[1, 3]], equal_nan=True)
+    with pytest.raises(v.VlbmError) as e:
+        b.set_active(None)
+    assert e.value.code == v.ERR_STATE
+    b.set_active([not x for x in keep])   # members 1 and 3 share step 40
+    b.step(70)
+    for k in (1, 3):
+        solo[k].step(70)
+    b.sync()
+    for k, (x, y) in enumerate(zip(_pops(b.members), _pops(solo))):
+        assert torch.equal(x, y), (k, float((x - y).abs().max()))
+    b.set_active([False] * 5)
+    b.step(10)
+    b.sync()
+    assert all(m.t == 110 for m in b.members)
+    b.close()
