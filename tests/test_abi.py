@@ -140,3 +140,14 @@ def test_conv_descriptor_rejected_without_a_device():
             vlbm.vlbm_conv2d_forward(ctypes.byref(d), ctypes.c_void_p(16), None, ctypes.c_void_p(16), None,
                                      ctypes.c_void_p(16), None, None)
         assert e.value.code == vlbm.ERR_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvlbm.so not built")
+def test_batch_calls_reject_a_null_batch():
+    """Batch entry points check their handle on the host."""
+    from paper_2401_17183_amd import vlbm
+    for call, args in ((vlbm.vlbm_batch_set_active, (None, None)), (vlbm.vlbm_batch_step, (None, 1)),
+                       (vlbm.vlbm_batch_residuals, (None, None))):
+        with pytest.raises(vlbm.VlbmError) as e:
+            call(*args)
+        assert e.value.code == vlbm.ERR_ARG
