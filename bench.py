@@ -444,10 +444,10 @@ def main():
     ap.add_argument("--tau-g", type=float, default=None,
                     help="general collision matrix: relaxation time of the non-hydrodynamic part "
                          "(default: BGK; 1 = regularised)")
-    ap.add_argument("--train", type=int, default=1024, help="surrogate: training meshes")
+    ap.add_argument("--train", type=int, default=4096, help="surrogate: training meshes")
     ap.add_argument("--val", type=int, default=128, help="surrogate: validation meshes")
     ap.add_argument("--test", type=int, default=64, help="surrogate: test meshes")
-    ap.add_argument("--epochs", type=int, default=60, help="surrogate: training epochs")
+    ap.add_argument("--epochs", type=int, default=200, help="surrogate: training epochs")
     ap.add_argument("--batch", type=int, default=32, help="surrogate: minibatch")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate: peak learning rate")
     ap.add_argument("--tol", type=float, default=1e-6, help="surrogate: steady residual target")
