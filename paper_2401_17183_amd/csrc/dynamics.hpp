@@ -202,6 +202,49 @@ __device__ __forceinline__ T feq_dir(const CellGeo<L, T, AT, ST>& g, const EqCoe
   return e.rho * T(L::w(a)) * (T(1) + T(L::INV_T0) * cU + T(L::INV_2T0) * H2G + T(L::INV_6T03) * H3R);
 }
 
+// Directions a and a + 1 are opposite (c_(a+1) = -c_a) for every odd a.
+template <class L>
+constexpr bool opposite_pair(int a) {
+  if (a < 1 || a + 1 >= L::Q || L::w(a) != L::w(a + 1)) return false;
+  for (int i = 0; i < L::D; ++i)
+    if (L::c(a + 1, i) != -L::c(a, i)) return false;
+  return true;
+}
+
+// f^eq of an opposite pair (a, a + 1): the part of eq. (equilibrium) even in c,
+// rho w (1 + H2:G/(2 T0)), is shared and the odd part, rho w (c.U/T0 +
+// H3:R/(6 T0^3)), changes sign, so f^eq_a = even + odd and f^eq_(a+1) =
+// even - odd cost one evaluation.
+template <class L, class T, class AT, int ST, int a>
+__device__ __forceinline__ void feq_parts(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, T& even, T& odd) {
+  constexpr int D = L::D;
+  static_assert(opposite_pair<L>(a), "feq_parts takes a direction a whose opposite is a + 1");
+  const T t0 = T(L::T0);
+  T cU = 0, cUt = 0, cr = 0, cgc = 0;
+  int cc = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int ci = L::c(a, i);
+    if (ci == 0) continue;
+    cc += ci * ci;
+    cU += T(ci) * e.U[i];
+    cUt += T(ci) * e.Ut[i];
+    cr += T(ci) * e.r[i];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int cj = L::c(a, j);
+      if (cj == 0) continue;
+      cgc += T(ci * cj) * gval(g, i, j);
+    }
+  }
+  const T cGc = t0 * (cgc - T(cc)) + cUt * cUt;
+  const T H2G = cGc * T(L::INV_T0) - e.trG;
+  const T H3R = T(3) * t0 * (cgc * cUt - T(cc) * cU) + cUt * cUt * cUt - T(3) * t0 * cr;
+  const T rw = e.rho * T(L::w(a));
+  even = rw * (T(1) + T(L::INV_2T0) * H2G);
+  odd = rw * (T(L::INV_T0) * cU + T(L::INV_6T03) * H3R);
+}
+
 template <class L, class T, class AT, int ST, int a = 0>
 __device__ __forceinline__ void feq_all(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, T* fe) {
   if constexpr (a < L::Q) {
@@ -241,9 +284,9 @@ __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const E
   if constexpr (p < L::Q) {
     T ap[L::D], am[L::D];
     a_pair<L, T, AT, ST>(g, p, p + 1, ap, am);
-    const T fp = feq_dir<L, T, AT, ST, p>(g, e);
-    const T fm = feq_dir<L, T, AT, ST, p + 1>(g, e);
-    const T df = fp - fm;
+    T even, odd;
+    feq_parts<L, T, AT, ST, p>(g, e, even, odd);
+    const T fp = even + odd, fm = even - odd, df = T(2) * odd;
 #pragma unroll
     for (int i = 0; i < L::D; ++i) {
       X[i] += ap[i] * fp + am[i] * fm;
@@ -260,6 +303,31 @@ __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const E
   }
 }
 
+// dN of an opposite pair (a, a + 1): the stress part w J H2:dPi/T0 is even in
+// c and the force part w J c.F/T0 odd, so dN_a = even + odd and dN_(a+1) =
+// even - odd.
+template <class L, class T, int a>
+__device__ __forceinline__ void delta_n_parts(T J, const T* Ft, const T* dpi, T trdpi, T& even, T& odd) {
+  constexpr int D = L::D;
+  static_assert(opposite_pair<L>(a), "delta_n_parts takes a direction a whose opposite is a + 1");
+  T cF = 0, cpc = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int ci = L::c(a, i);
+    if (ci == 0) continue;
+    cF += T(ci) * Ft[i];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int cj = L::c(a, j);
+      if (cj == 0) continue;
+      cpc += T(ci * cj) * dpi[up<D>(i, j)];
+    }
+  }
+  const T wJ = T(L::w(a)) * J;
+  even = wJ * (T(L::INV_T0) * (T(L::INV_T0) * cpc - trdpi));
+  odd = wJ * (T(L::INV_T0) * cF);
+}
+
 // Pass 2: Y^i = sum_a A^i_a dN_a, dN with the volume J.
 template <class L, class T, class AT, int ST, int a = 1>
 __device__ __forceinline__ void pass_dn_j(const CellGeo<L, T, AT, ST>& g, T J, const T* Ft, const T* dpi, T trdpi,
@@ -267,8 +335,9 @@ __device__ __forceinline__ void pass_dn_j(const CellGeo<L, T, AT, ST>& g, T J, c
   if constexpr (a < L::Q) {
     T ap[L::D], am[L::D];
     a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
-    const T dp = delta_n_dir<L, T, a>(J, Ft, dpi, trdpi);
-    const T dm = delta_n_dir<L, T, a + 1>(J, Ft, dpi, trdpi);
+    T even, odd;
+    delta_n_parts<L, T, a>(J, Ft, dpi, trdpi, even, odd);
+    const T dp = even + odd, dm = even - odd;
 #pragma unroll
     for (int i = 0; i < L::D; ++i) Y[i] += ap[i] * dp + am[i] * dm;
     pass_dn_j<L, T, AT, ST, a + 2>(g, J, Ft, dpi, trdpi, Y);
@@ -282,13 +351,21 @@ __device__ __forceinline__ void pass_dn(const CellGeo<L, T, AT, ST>& g, const T*
 
 // Output pass: N'_a = N_a - s (N_a - J f^eq_a) + dN_a  (eqs. (lbe), (collide));
 // s = 1/tau for BGK, and dPi carries the stress term of a general M.
-template <class L, class T, class AT, int ST, class NS, int a = 0>
+template <class L, class T, class AT, int ST, class NS, int a = 1>
 __device__ __forceinline__ void pass_out(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, const NS* N, const T* Ft,
                                          const T* dpi, T trdpi, T s, T* Np) {
+  if constexpr (a == 1) {   // rest direction: c = 0, no force part
+    const T n = T(N[0]);
+    Np[0] = n - (n - g.j() * feq_dir<L, T, AT, ST, 0>(g, e)) * s + delta_n_dir<L, T, 0>(g.j(), Ft, dpi, trdpi);
+  }
   if constexpr (a < L::Q) {
-    const T n = T(N[a]);
-    Np[a] = n - (n - g.j() * feq_dir<L, T, AT, ST, a>(g, e)) * s + delta_n_dir<L, T, a>(g.j(), Ft, dpi, trdpi);
-    pass_out<L, T, AT, ST, NS, a + 1>(g, e, N, Ft, dpi, trdpi, s, Np);
+    T fe, fo, de, dd;
+    feq_parts<L, T, AT, ST, a>(g, e, fe, fo);
+    delta_n_parts<L, T, a>(g.j(), Ft, dpi, trdpi, de, dd);
+    const T np = T(N[a]), nm = T(N[a + 1]);
+    Np[a] = np - (np - g.j() * (fe + fo)) * s + (de + dd);
+    Np[a + 1] = nm - (nm - g.j() * (fe - fo)) * s + (de - dd);
+    pass_out<L, T, AT, ST, NS, a + 2>(g, e, N, Ft, dpi, trdpi, s, Np);
   }
 }
 
