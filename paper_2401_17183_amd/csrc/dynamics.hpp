@@ -387,14 +387,91 @@ __device__ __forceinline__ T finish_dpi(const CellGeo<L, T, AT, ST>& g, T (*M)[L
 }
 
 // State of one cell's collision between its phases.
-template <class L, class T> struct CollState {
+template <class L, class T, class MT = T> struct CollState {
   T rho, invJ, half_inv_rho, cJ;
   T U[L::D], BC[L::D];          // BC = B - (1 - s) C / 2 - Z / 2 (constant part of J F)
   T Ut[L::D], Ft[L::D];
   T dpi[nup<L::D>()], trdpi;
   EqCoef<L, T> e;
+  MT lm[L::D * (L::D + nup<L::D>() + 1)];      // link moments P, Q, R (link_moments), type of A
   int iters;                    // iterations used; max_iter + 1 when the cap was hit
 };
+
+// sum_a A^i_a dN_a is linear in Ft and dPi (eq. (deltaN)):
+//   sum_a A^i_a dN_a = J/T0 [P^{ik} Ft_k + Q^{i,jk} dPi_jk / T0 - R^i tr dPi],
+//   P^{ik} = sum_a A^i_a w_a c^k_a,  Q^{i,jk} = sum_a A^i_a w_a c^j_a c^k_a,
+//   R^i = sum_a A^i_a w_a,
+// with geometry-only moments, so the fixed point needs no pass over the
+// directions for it.  Held in the storage type of A (words [P | Q over the
+// upper triangle, the off-diagonal entries doubled | R] per component i): in
+// FP32 they weight the small force and stress corrections only, where their
+// rounding stays far below the fixed point's tolerance.
+template <class L> constexpr int lm_words() { return L::D + nup<L::D>() + 1; }
+
+// Adds the opposite pair (a, a + 1) to the link moments m[i][word]: with
+// c_(a+1) = -c_a, P takes A_a - A_(a+1) and Q, R take A_a + A_(a+1).
+template <class L, class T, int a>
+__device__ __forceinline__ void add_link_moments(const T* ap, const T* am, T (*m)[lm_words<L>()]) {
+  constexpr int D = L::D;
+  constexpr int NU = nup<D>();
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T dif = T(L::w(a)) * (ap[i] - am[i]);
+    const T sum = T(L::w(a)) * (ap[i] + am[i]);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (L::c(a, k) != 0) m[i][k] += T(L::c(a, k)) * dif;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int k = j; k < D; ++k) {
+        const int cc = (j == k ? 1 : 2) * L::c(a, j) * L::c(a, k);
+        if (cc != 0) m[i][D + up<D>(j, k)] += T(cc) * sum;
+      }
+    m[i][D + NU] += sum;
+  }
+}
+
+// sum_a A^i_a dN_a from the link moments (narrow words are widened at each use).
+template <class L, class T, class MT>
+__device__ __forceinline__ void dn_from_moments(const MT* lm, T J, const T* Ft, const T* dpi, T trdpi, T* Y) {
+  constexpr int D = L::D;
+  constexpr int NU = nup<D>();
+  constexpr int W = lm_words<L>();
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T f = 0, q = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) f += widen<T>(lm[i * W + k]) * Ft[k];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) q += widen<T>(lm[i * W + D + k]) * dpi[k];
+    Y[i] = J * T(L::INV_T0) * (f + T(L::INV_T0) * q - widen<T>(lm[i * W + D + NU]) * trdpi);
+  }
+}
+
+// The sums of phase 1 over the opposite pairs (a, a + 1), each pair's A read
+// and widened once: rho J, J rho U, C, B and (ST > 0) the link moments.
+template <class L, class T, class AT, int ST, class NS, int a = 1>
+__device__ __forceinline__ void prepare_pairs(const CellGeo<L, T, AT, ST>& g, const NS* N, T& rhoJ, T* mom, T* C, T* B,
+                                              T (*m)[lm_words<L>()]) {
+  if constexpr (a < L::Q) {
+    constexpr int D = L::D;
+    static_assert(opposite_pair<L>(a), "prepare_pairs walks opposite pairs (a, a + 1)");
+    T ap[D], am[D];
+    a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
+    const T np = T(N[a]), nm = T(N[a + 1]);
+    rhoJ += np + nm;
+    const T dn = np - nm;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * dn;
+      C[i] += ap[i] * np + am[i] * nm;
+      B[i] -= T(0.5) * (am[i] * np + ap[i] * nm);
+    }
+    if constexpr (ST != 0) add_link_moments<L, T, a>(ap, am, m);
+    prepare_pairs<L, T, AT, ST, NS, a + 2>(g, N, rhoJ, mom, C, B, m);
+  }
+}
 
 // Phase 1: moments (eqs. (dist), (moments), (vcurvi)) and the parts of
 // eq. (compo-constr) that do not change during the fixed point:
@@ -403,26 +480,20 @@ template <class L, class T> struct CollState {
 //   the stress term, linear in dPi).
 template <class L, class T, class AT, int ST, class NS>
 __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r,
-                                                CollState<L, T>& st) {
+                                                CollState<L, T, AT>& st) {
   constexpr int D = L::D;
   constexpr int Q = L::Q;
-  T rhoJ = 0;
-  T mom[D], C[D], B[D];
+  constexpr int W = lm_words<L>();
+  T rhoJ = T(N[0]);
+  T mom[D], C[D], B[D], m[ST ? D : 1][W];
 #pragma unroll
   for (int i = 0; i < D; ++i) mom[i] = C[i] = B[i] = 0;
+  if constexpr (ST != 0)
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const T n = T(N[a]);
-    rhoJ += n;
+    for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * n;
-      if (a > 0) {
-        C[i] += T(g.a(a, i)) * n;
-        B[i] -= T(0.5) * T(g.a(opp(a), i)) * n;
-      }
-    }
-  }
+      for (int k = 0; k < W; ++k) m[i][k] = 0;
+  prepare_pairs<L, T, AT, ST, NS>(g, N, rhoJ, mom, C, B, m);
   st.rho = rhoJ / g.j();
   st.invJ = T(1) / g.j();
   st.half_inv_rho = T(0.5) / st.rho;
@@ -432,14 +503,22 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
     st.U[i] = mom[i] / rhoJ;
     st.BC[i] = B[i] - T(0.5) * (T(1) - r.s) * C[i];
   }
+  // with A in LDS the registers hold the link moments instead of a pass over A
+  if constexpr (ST != 0)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < W; ++k) st.lm[i * W + k] = AT(m[i][k]);
   if (r.general) {   // wave-uniform
     // dN is J times a function of dPi: with J = 1 and dPi = c1 S2 the product
-    // J dPi = c1 S2 is the same
+    // J dPi = c1 S2 is the same.  Z and the stress term of the iterations
+    // cancel to the small non-equilibrium part, so both take the same moments.
     T S2[nup<D>()], Z[D], zero[D];
     const T tr = second_moment<L, T, NS>(N, r.c1, S2);
 #pragma unroll
     for (int i = 0; i < D; ++i) Z[i] = zero[i] = 0;
-    pass_dn_j<L, T, AT, ST>(g, T(1), zero, S2, tr, Z);
+    if constexpr (ST != 0) dn_from_moments<L, T, AT>(st.lm, T(1), zero, S2, tr, Z);
+    else pass_dn_j<L, T, AT, ST>(g, T(1), zero, S2, tr, Z);
 #pragma unroll
     for (int i = 0; i < D; ++i) st.BC[i] -= T(0.5) * Z[i];
   }
@@ -457,7 +536,7 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
 // constant and sits in BC).
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, const Relax<T>& r, T tol, int max_iter,
-                                                T* F, CollState<L, T>& st, int min_iter = 1) {
+                                                T* F, CollState<L, T, AT>& st, int min_iter = 1) {
   constexpr int D = L::D;
   const T k = T(1) - T(0.5) / r.tau;
   int it = 1;
@@ -496,9 +575,13 @@ __device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, 
         }
     }
     T Y[D];
+    if constexpr (ST != 0) {
+      dn_from_moments<L, T, AT>(st.lm, gl.j(), st.Ft, st.dpi, st.trdpi, Y);
+    } else {
 #pragma unroll
-    for (int i = 0; i < D; ++i) Y[i] = 0;
-    pass_dn<L, T, AT, ST>(gl, st.Ft, st.dpi, st.trdpi, Y);
+      for (int i = 0; i < D; ++i) Y[i] = 0;
+      pass_dn<L, T, AT, ST>(gl, st.Ft, st.dpi, st.trdpi, Y);
+    }
     T change = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -519,7 +602,7 @@ __device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, 
 // general M the population part c1 S2 / J of the stress term joins dPi here.
 template <class L, class T, class AT, int ST, class NS>
 __device__ __forceinline__ void collide_output(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r,
-                                               const CollState<L, T>& st, T* Np) {
+                                               const CollState<L, T, AT>& st, T* Np) {
   if (r.general) {
     T dpi[nup<L::D>()];
     T tr = second_moment<L, T, NS>(N, r.c1 * st.invJ, dpi);
@@ -540,7 +623,7 @@ struct CollideOut {
 template <class L, class T, class AT, int ST, class NS>
 __device__ __forceinline__ CollideOut collide(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r, T tol,
                                               int max_iter, T* Np, T* F, T* Ut_out, T* U_out, T& rho_out) {
-  CollState<L, T> st;
+  CollState<L, T, AT> st;
   collide_prepare<L, T, AT, ST, NS>(g, N, r, st);
   collide_iterate<L, T, AT, ST>(g, r, tol, max_iter, F, st);
   collide_output<L, T, AT, ST, NS>(g, N, r, st, Np);

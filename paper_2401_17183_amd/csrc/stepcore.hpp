@@ -161,17 +161,20 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   T F[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) F[i] = word(a.fcache, i, nc)[cell];
-  CollState<L, T> st;
+  CollState<L, T, S> st;
   const Relax<T> rx = make_relax<T>(a.tau, a.tau_g, GEN ? 1 : 0);
   collide_prepare<L, T, S, ST, NR>(g, N, rx, st);
   collide_iterate<L, T, S, ST>(g, rx, a.tol, a.max_iter, F, st, a.min_iter);
   if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
 #pragma unroll
   for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
-  // gather again (cache hits) rather than keeping N live across the fixed point;
-  // decoded 16-bit populations stay in registers (their re-gather would also
-  // re-read and re-apply the link references)
-  if constexpr (!PopCodec<P>::shifted && sizeof(T) == 8) {
+  // gather again (cache hits) rather than keeping N live across the fixed point
+  // where registers are short: FP64 populations, and the far-field and general
+  // collision variants.  Decoded 16-bit populations stay in registers (their
+  // re-gather would also re-read and re-apply the link references), and so do
+  // FP32 populations of the plain variant, whose fixed point leaves room.
+  constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && (sizeof(P) == 8 || FF != 0 || GEN);
+  if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
     // here instead of being kept (or spilled) across the fixed point
     int xr = x, yr = y, zr = z, cr = cell;
