@@ -44,6 +44,7 @@ __device__ __forceinline__ void pin(V& v) {
 
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ void pin_scalars(CellGeo<L, T, AT, ST>& g, T& rho) {
+  if constexpr (ST != 0) asm volatile("" : "+s"(g.lofs));   // wave-uniform: a scalar register
   pin(g.J);
 #pragma unroll
   for (int k = 0; k < nup<L::D>(); ++k) pin(g.gup[k]);
@@ -61,21 +62,21 @@ __device__ __forceinline__ T widen(AT v) {
   return T(v);
 }
 
-// A_p and A_q (all components) in the arithmetic type, the narrow values
-// loaded together before any is widened: the loads of a group are in flight
-// at once instead of one LDS round trip per value.
+// A_p and A_q (all components) in the arithmetic type.  From LDS (ST > 0) the
+// loads carry the per-iteration offset lofs, so neither they nor their
+// widening can be hoisted out of the fixed point and no register barrier is
+// needed: the waits for the loads fall where the values are used.
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ void a_pair(const CellGeo<L, T, AT, ST>& g, int p, int q, T* ap, T* aq) {
-  AT v[2 * L::D];
 #pragma unroll
   for (int i = 0; i < L::D; ++i) {
-    v[i] = g.a(p, i);
-    v[L::D + i] = g.a(q, i);
-  }
-#pragma unroll
-  for (int i = 0; i < L::D; ++i) {
-    ap[i] = widen<T>(v[i]);
-    aq[i] = widen<T>(v[L::D + i]);
+    if constexpr (ST != 0) {
+      ap[i] = T(g.a(p, i));
+      aq[i] = T(g.a(q, i));
+    } else {
+      ap[i] = widen<T>(g.a(p, i));
+      aq[i] = widen<T>(g.a(q, i));
+    }
   }
 }
 
