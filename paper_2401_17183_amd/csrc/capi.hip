@@ -177,6 +177,8 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
     for (int k = 0; k < 3; ++k) m->wrap[i][k] = (active && k < d) ? topo->wrap[i][k] : 0.0;
   }
   m->box.ncells = (int)nc;
+  m->box.inv_n[0] = 1.0 / m->box.n[0];
+  m->box.inv_n[1] = 1.0 / m->box.n[1];
   int rc = dev_alloc(&m->coords, ncoord * sizeof(double));
   if (rc) {
     delete m;
@@ -335,7 +337,7 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   if ((rc = dev_alloc(&s->pop[0], s->pop_bytes))) return bail(rc);
   if ((rc = dev_alloc(&s->pop[1], s->pop_bytes))) return bail(rc);
   const int words = pack_words(m->lattice);
-  if ((rc = dev_alloc(&s->geo, nc * words * geometry_bytes(s->p.precision)))) return bail(rc);
+  if ((rc = dev_alloc(&s->geo, pack_elements(words, nc) * geometry_bytes(s->p.precision)))) return bail(rc);
   if (storage_is_16(s->p.precision)) {
     if ((rc = dev_alloc(&s->rown, nc * m->Q * sb))) return bail(rc);
     if ((rc = dev_alloc(&s->rsrc, nc * m->Q * sb))) return bail(rc);

@@ -162,7 +162,19 @@ struct Box {
   int n[3];        // real cells per axis (n[2] = 1 in 2-D)
   int face[3][2];  // VLBM_PERIODIC / VLBM_WALL / VLBM_FARFIELD
   int ncells;
+  double inv_n[2]; // 1 / n[0], 1 / n[1] (cell_coords)
 };
+
+// (x, y, z) of a cell index without integer division: with c < 2^30 and
+// n <= 2^20, (c + 1/2) / n lies at least 1/(2n) >= 2^-21 from an integer and
+// the FP64 product (c + 1/2) * fl(1/n) is within 2^-22 of it, so its floor is
+// the exact quotient.
+__device__ __forceinline__ void cell_coords(const Box& b, int cell, int& x, int& y, int& z) {
+  const int r = int(floor((double(cell) + 0.5) * b.inv_n[0]));
+  x = cell - r * b.n[0];
+  z = int(floor((double(r) + 0.5) * b.inv_n[1]));
+  y = r - z * b.n[1];
+}
 
 // Kind of the source of a pulled link.
 enum LinkKind { LINK_INTERIOR = 0, LINK_WALL = 1, LINK_FARFIELD = 2 };
@@ -317,6 +329,21 @@ template <class L> struct Pack {
   static constexpr int UINF = AEXT + L::D;                    // present if far field
   static constexpr int WORDS = UINF + L::D;
 };
+
+// The packed geometry is tiled by wavefronts: the words of 64 consecutive
+// cells are stored word by word, [cell / 64][word][cell % 64].  A wave reads
+// 64 consecutive elements per word (as with one array per word), and all the
+// words of its cells lie within immediate offsets of one per-lane address.
+constexpr int kGeoTile = 64;
+template <class L>
+__host__ __device__ __forceinline__ size_t pack_index(int word, int cell) {
+  const unsigned c = (unsigned)cell;
+  return (size_t)(c / kGeoTile) * (Pack<L>::WORDS * kGeoTile) + (size_t)word * kGeoTile + (size_t)(c % kGeoTile);
+}
+// Elements of a packed geometry of nc cells (the last tile is whole).
+inline size_t pack_elements(int words, size_t nc) {
+  return (nc + kGeoTile - 1) / kGeoTile * kGeoTile * (size_t)words;
+}
 
 inline int pack_words(int lattice) {
   switch (lattice) {

@@ -417,19 +417,19 @@ __device__ __forceinline__ void add_link_moments(const T* ap, const T* am, T (*m
   constexpr int NU = nup<D>();
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    const T dif = T(L::w(a)) * (ap[i] - am[i]);
-    const T sum = T(L::w(a)) * (ap[i] + am[i]);
+    const T dif = ap[i] - am[i];
+    const T sum = ap[i] + am[i];
 #pragma unroll
     for (int k = 0; k < D; ++k)
-      if (L::c(a, k) != 0) m[i][k] += T(L::c(a, k)) * dif;
+      if (L::c(a, k) != 0) m[i][k] += T(L::w(a) * L::c(a, k)) * dif;
 #pragma unroll
     for (int j = 0; j < D; ++j)
 #pragma unroll
       for (int k = j; k < D; ++k) {
         const int cc = (j == k ? 1 : 2) * L::c(a, j) * L::c(a, k);
-        if (cc != 0) m[i][D + up<D>(j, k)] += T(cc) * sum;
+        if (cc != 0) m[i][D + up<D>(j, k)] += T(L::w(a) * cc) * sum;
       }
-    m[i][D + NU] += sum;
+    m[i][D + NU] += T(L::w(a)) * sum;
   }
 }
 
@@ -495,13 +495,15 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
 #pragma unroll
       for (int k = 0; k < W; ++k) m[i][k] = 0;
   prepare_pairs<L, T, AT, ST, NS>(g, N, rhoJ, mom, C, B, m);
-  st.rho = rhoJ / g.j();
+  // two divisions: 1/J and 1/(rho J)
+  const T inv_rhoJ = T(1) / rhoJ;
   st.invJ = T(1) / g.j();
-  st.half_inv_rho = T(0.5) / st.rho;
+  st.rho = rhoJ * st.invJ;
+  st.half_inv_rho = T(0.5) * g.j() * inv_rhoJ;
   st.cJ = g.j() * r.s;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    st.U[i] = mom[i] / rhoJ;
+    st.U[i] = mom[i] * inv_rhoJ;
     st.BC[i] = B[i] - T(0.5) * (T(1) - r.s) * C[i];
   }
   // with A in LDS the registers hold the link moments instead of a pass over A

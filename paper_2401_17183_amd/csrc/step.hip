@@ -41,11 +41,11 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   if (cell >= box.ncells) return;
   const long nc = box.ncells;
-  geo[Pack<L>::J * nc + cell] = S(J[cell]);
+  geo[pack_index<L>(Pack<L>::J, cell)] = S(J[cell]);
   for (int i = 0; i < D; ++i)
-    for (int j = i; j < D; ++j) geo[(Pack<L>::GUP + up<D>(i, j)) * nc + cell] = S(gup[(i * D + j) * nc + cell]);
+    for (int j = i; j < D; ++j) geo[pack_index<L>(Pack<L>::GUP + up<D>(i, j), cell)] = S(gup[(i * D + j) * nc + cell]);
   for (int al = 1; al < L::Q; ++al)
-    for (int i = 0; i < D; ++i) geo[(Pack<L>::A + (al - 1) * D + i) * nc + cell] = S(A[(al * D + i) * nc + cell]);
+    for (int i = 0; i < D; ++i) geo[pack_index<L>(Pack<L>::A + (al - 1) * D + i, cell)] = S(A[(al * D + i) * nc + cell]);
   const double G[3] = {G0, G1, G2};
   const double ui[3] = {u0, u1, u2};
   for (int i = 0; i < D; ++i) {
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
       ae += G[k] * gco[(i * D + k) * nc + cell];
       uc += ui[k] * gco[(i * D + k) * nc + cell];
     }
-    if (has_force) geo[(Pack<L>::AEXT + i) * nc + cell] = S(ae);
-    if (has_ff) geo[(Pack<L>::UINF + i) * nc + cell] = S(uc);
+    if (has_force) geo[pack_index<L>(Pack<L>::AEXT + i, cell)] = S(ae);
+    if (has_ff) geo[pack_index<L>(Pack<L>::UINF + i, cell)] = S(uc);
   }
 }
 

@@ -54,14 +54,16 @@ template <class L, class S, class T, int ST>
 __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ geo, int nc, int cell, int has_force,
                                                           S* lds) {
   CellGeo<L, T, S, ST> g;
-  g.J = word(geo, Pack<L>::J, nc)[cell];
+  // this cell's element of word 0 of its tile; word w is w * kGeoTile further
+  const S* __restrict__ gw = geo + pack_index<L>(0, cell);
+  g.J = gw[Pack<L>::J * kGeoTile];
 #pragma unroll
-  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = word(geo, Pack<L>::GUP + k, nc)[cell];
+  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = gw[(Pack<L>::GUP + k) * kGeoTile];
 #pragma unroll
   for (int a = 1; a < L::Q; ++a)
 #pragma unroll
     for (int i = 0; i < L::D; ++i) {
-      const S v = word(geo, Pack<L>::A + (a - 1) * L::D + i, nc)[cell];
+      const S v = gw[(Pack<L>::A + (a - 1) * L::D + i) * kGeoTile];
       if constexpr (ST == 0) g.Areg[a][i] = v;
       else lds[((a - 1) * L::D + i) * ST] = v;
     }
@@ -71,7 +73,7 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
   g.lds = lds;
   g.lofs = 0;
 #pragma unroll
-  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? word(geo, Pack<L>::AEXT + i, nc)[cell] : S(0);
+  for (int i = 0; i < L::D; ++i) g.aext[i] = has_force ? gw[(Pack<L>::AEXT + i) * kGeoTile] : S(0);
   return g;
 }
 
@@ -115,7 +117,7 @@ __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo
   if (FF == 1 || (FF == 2 && a.has_ff)) {   // compile-time or wave-uniform
     T Uinf[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) Uinf[i] = T(word(a.geo, Pack<L>::UINF + i, nc)[cell]);
+    for (int i = 0; i < D; ++i) Uinf[i] = T(a.geo[pack_index<L>(Pack<L>::UINF + i, cell)]);
     T fe[Q];
     feq_farfield<L, T>(g, a.rho_inf, Uinf, fe);
 #pragma unroll
@@ -142,10 +144,8 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   using NR = typename std::conditional<PopCodec<P>::shifted, float, P>::type;
   if (cell >= a.box.ncells) return;
   const int nc = a.box.ncells;
-  const int x = cell % a.box.n[0];
-  const int r = cell / a.box.n[0];
-  const int y = r % a.box.n[1];
-  const int z = r / a.box.n[1];
+  int x, y, z;
+  cell_coords(a.box, cell, x, y, z);
   // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19); so
   // does D3Q39 in FP64 (its 114 A words cannot live in registers)
   constexpr int ST = (sizeof(S) == 4 || L::Q > 21) ? BLOCK : 0;
