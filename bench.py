@@ -113,10 +113,11 @@ STEP_SOURCES = ["paper_2401_17183_amd/csrc/common.hpp", "paper_2401_17183_amd/cs
 BATCH_SOURCES = STEP_SOURCES[:3] + ["paper_2401_17183_amd/csrc/batch.hip"]
 
 
-def profiled_traffic(profile, sources):
+def profiled_traffic(profile, sources, require=None):
     """HBM bytes per launch from a committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None when
-    there is no summary or the kernel sources changed since it was taken."""
+    there is no summary, the kernel sources changed since it was taken, or one of
+    the `require` entries (e.g. the launch shape) differs from the summary's."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -132,6 +133,8 @@ def profiled_traffic(profile, sources):
                 k, v = line.split(" = ", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_digest") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in vals:
+        return None
+    if any(vals.get(k) != str(v) for k, v in (require or {}).items()):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -263,8 +266,9 @@ def run_batch(args, torch, vlbm):
     achieved = bpc * cells / (main["ms_per_step"] / 1e3) / 1e9
     finite = all(bool(torch.isfinite(m.moments()["u"]).all().item()) for m in b.members[:8])
     traffic = None
-    if args.precision == "fp32" and (block, gpc) == (256, 0):
-        traffic = profiled_traffic("k_batch_d2q9_bump256_fp32.md", BATCH_SOURCES)
+    if args.precision == "fp32":
+        traffic = profiled_traffic("k_batch_d2q9_bump256_fp32.md", BATCH_SOURCES,
+                                   {"launch_block": block, "launch_grid_per_cu": gpc})
     out = {
         "metric": METRIC,
         "value": main["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": main["steps"], "warmup": args.warmup,
