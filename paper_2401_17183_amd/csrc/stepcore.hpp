@@ -169,11 +169,12 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
 #pragma unroll
   for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
   // gather again (cache hits) rather than keeping N live across the fixed point
-  // where registers are short: FP64 populations, and the far-field and general
-  // collision variants.  Decoded 16-bit populations stay in registers (their
-  // re-gather would also re-read and re-apply the link references), and so do
-  // FP32 populations of the plain variant, whose fixed point leaves room.
-  constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && (sizeof(P) == 8 || FF != 0 || GEN);
+  // where registers are short: FP64 populations and the general collision
+  // variant.  Decoded 16-bit populations stay in registers (their re-gather
+  // would also re-read and re-apply the link references), and so do FP32
+  // populations of the BGK variants (the far-field one spills a few values
+  // around the fixed point and still runs faster than with a second gather).
+  constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && (sizeof(P) == 8 || GEN);
   if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
     // here instead of being kept (or spilled) across the fixed point
