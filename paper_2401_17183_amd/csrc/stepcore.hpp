@@ -89,8 +89,12 @@ __device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const Li
     int kind;
     if constexpr (L::SPEED == 1) kind = link_at<L, al>(plan, cell, src);
     else kind = link_source<L>(a.box, al, x, y, z, src);
-    const int dir = kind == LINK_INTERIOR ? al : opp(al);
-    const P h = word(a.in, 0, nc)[(size_t)dir * nc + src];
+    // slot al of src, or (bounced / far field: src = cell) slot opp(al) of the
+    // cell, as an element offset from the pair's lower slot array: the base is
+    // wave-uniform and the offset (< 2 nc <= 2^31) a 32-bit lane value
+    constexpr int lo = opp(al) < al ? opp(al) : al;
+    const unsigned e = (unsigned)src + (unsigned)nc * (kind == LINK_INTERIOR ? unsigned(al - lo) : unsigned(opp(al) - lo));
+    const P h = word(a.in, lo, nc)[e];
     if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rsrc, al, nc)[cell], a.inv_scale);
     else N[al] = h;
     ff |= DirMask<L>(kind == LINK_FARFIELD ? 1 : 0) << al;

@@ -133,6 +133,27 @@ def test_stream_only_is_bit_exact(w):
     same(cpu(s.populations()), os_.N.reshape(os_.lat.Q, -1))
 
 
+@pytest.mark.parametrize("lattice,n", [("D2Q9", ((1 << 20) - 3, 3)), ("D2Q9", (5, 1 << 20)),
+                                       ("D3Q19", (3, 7, (1 << 17) + 1))],
+                         ids=["D2Q9 (2^20-3)x3", "D2Q9 5x2^20", "D3Q19 3x7x(2^17+1)"])
+def test_long_axes_stream_only_is_bit_exact(lattice, n):
+    """Axes up to the 2^20-cell maximum: the step kernel's cell coordinates
+    (quotients by FP64 reciprocals), the periodic wrap and the wavefront-tiled
+    geometry over tens of thousands of tiles; advection is the oracle's
+    permutation bit for bit."""
+    w = W.wavy_periodic(lattice, n, 0.05)
+    announce(f"stream-only long axes {w['name']}")
+    os_ = sim_of(w, stream_only=True)
+    rng = np.random.default_rng(5)
+    N0 = rng.random((os_.lat.Q,) + os_.mesh.shape)
+    os_.set_state(N0)
+    s, _ = gpu_sim(w, stream_only=True)
+    s.set_populations(N0.reshape(os_.lat.Q, -1))
+    s.step(3)
+    os_.step(3)
+    assert np.array_equal(cpu(s.populations()), os_.N.reshape(os_.lat.Q, -1))
+
+
 @pytest.mark.parametrize("w,steps", [(W.tanh_channel_2d(64, 32), 100), (W.wavy_channel_3d(16, 12, 8), 100),
                                      (W.ogrid_3d(8, 96, 4, rmax=1.5, dx_factor=1.3), 50)],
                          ids=lambda x: str(x) if isinstance(x, int) else x["name"])
