@@ -538,19 +538,19 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
 // for a general M, dN includes the stress term, whose population part Z is
 // constant and sits in BC).
 template <class L, class T, class AT, int ST>
-__device__ __forceinline__ void collide_iterate(const CellGeo<L, T, AT, ST>& g, const Relax<T>& r, T tol, int max_iter,
+__device__ __forceinline__ void collide_iterate(CellGeo<L, T, AT, ST>& gl, const Relax<T>& r, T tol, int max_iter,
                                                 T* F, CollState<L, T, AT>& st, int min_iter = 1) {
   constexpr int D = L::D;
   const T k = T(1) - T(0.5) / r.tau;
   int it = 1;
   int done = 0;
-  CellGeo<L, T, AT, ST> gl = g;
-  T rho_l = st.rho;
+  T& rho_l = st.rho;
   for (; it <= max_iter; ++it) {
     // Re-define the per-cell scalars each iteration (empty register
-    // constraints): quantities derived from them (c.g.c per direction, rho w,
-    // widened g^{ij}) are then recomputed instead of being kept live across
-    // iterations, which keeps the register footprint and occupancy reasonable.
+    // constraints, in place: the values do not change): quantities derived from
+    // them (c.g.c per direction, rho w, widened g^{ij}) are then recomputed
+    // instead of being kept live across iterations, which keeps the register
+    // footprint and occupancy reasonable.
     pin_scalars<L, T, AT, ST>(gl, rho_l);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -624,7 +624,7 @@ struct CollideOut {
 
 // The whole collision of one cell with N held in registers throughout.
 template <class L, class T, class AT, int ST, class NS>
-__device__ __forceinline__ CollideOut collide(const CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r, T tol,
+__device__ __forceinline__ CollideOut collide(CellGeo<L, T, AT, ST>& g, const NS* N, const Relax<T>& r, T tol,
                                               int max_iter, T* Np, T* F, T* Ut_out, T* U_out, T& rho_out) {
   CollState<L, T, AT> st;
   collide_prepare<L, T, AT, ST, NS>(g, N, r, st);

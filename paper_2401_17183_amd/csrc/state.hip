@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_init(StateArgs<S> a) {
   int x, y, z;
   cell_xyz(a.box, cell, x, y, z);
   double Uinf[D];
-  const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
+  CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
   const double rho = a.rho_in ? a.rho_in[cell] : 1.0;
   double Ut[D];
   for (int i = 0; i < D; ++i) {
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(StateArgs<S> a) {
   int x, y, z;
   cell_xyz(a.box, cell, x, y, z);
   double Uinf[L::D];
-  const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
+  CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
   double N[L::Q];
   DirMask<L> wm;
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_refs_own(StateArgs<S> a) {
   if (cell >= a.box.ncells) return;
   const long nc = a.box.ncells;
   double Uinf[D];
-  const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
+  CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
   double Ut[D], N[L::Q], F[D];
   for (int i = 0; i < D; ++i) Ut[i] = 0;
   if (!consistent_equilibrium<L, double>(g, 1.0, Ut, a.tau, a.tol, a.max_iter, N, F)) atomicAdd(a.flag, 1);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(StateArgs<S> a) {
   int x, y, z;
   cell_xyz(a.box, cell, x, y, z);
   double Uinf[D];
-  const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
+  CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
   double N[L::Q];
   DirMask<L> wm;
   gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
     int x, y, z;
     cell_xyz(a.box, cell, x, y, z);
     double Uinf[D];
-    const CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
+    CellGeo<L, double> g = load_fp64<L, S>(a, cell, Uinf);
     double N[Q];
     DirMask<L> wm;
     gather64<L, S>(a, g, Uinf, cell, x, y, z, N, wm);

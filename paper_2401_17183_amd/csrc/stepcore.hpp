@@ -155,7 +155,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   constexpr int ST = (sizeof(S) == 4 || L::Q > 21) ? BLOCK : 0;
   __shared__ S sA[ST ? (Q - 1) * D * BLOCK : 1];
   NR N[Q];
-  const CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
+  CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
   gather<L, P, S, T, NR, ST, FF>(a, g, x, y, z, cell, N);
   if (a.stream_only) {
 #pragma unroll
@@ -176,8 +176,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   // where registers are short: FP64 populations and the general collision
   // variant.  Decoded 16-bit populations stay in registers (their re-gather
   // would also re-read and re-apply the link references), and so do FP32
-  // populations of the BGK variants (the far-field one spills a few values
-  // around the fixed point and still runs faster than with a second gather).
+  // populations of the BGK variants.
   constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && (sizeof(P) == 8 || GEN);
   if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
