@@ -394,7 +394,7 @@ template <class L, class T, class MT = T> struct CollState {
   T Ut[L::D], Ft[L::D];
   T dpi[nup<L::D>()], trdpi;
   EqCoef<L, T> e;
-  MT lm[L::D * (L::D + nup<L::D>() + 1)];      // link moments P, Q, R (link_moments), type of A
+  MT lm[L::D * (L::D + nup<L::D>() + 1)];      // link moments P, Q, R (add_link_moments), type of A
   int iters;                    // iterations used; max_iter + 1 when the cap was hit
 };
 
@@ -536,7 +536,8 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
 //   sum_a A_a N'_a = (1 - s) C + J s sum_a A_a f^eq_a + sum_a A_a dN_a
 // so that no per-direction array is live inside the loop (s = 1/tau for BGK;
 // for a general M, dN includes the stress term, whose population part Z is
-// constant and sits in BC).
+// constant and sits in BC).  With A staged in LDS the last sum comes from the
+// link moments, so an iteration walks the directions once (for X and dPi).
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ void collide_iterate(CellGeo<L, T, AT, ST>& gl, const Relax<T>& r, T tol, int max_iter,
                                                 T* F, CollState<L, T, AT>& st, int min_iter = 1) {
