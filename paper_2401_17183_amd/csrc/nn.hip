@@ -213,14 +213,17 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(Conv c, Gemm g) {
 // Weight gradient: gw[co][k] += sum_m gy[m][co] A(m, k), gb[co] += sum_m gy[m][co].
 // A 64 (co) x 64 (k) tile per block; 32 output pixels per step are staged in LDS
 // transposed (pixel index fastest) so that each MFMA operand fragment is one
-// 16-byte LDS read; blocks split the pixel range and add their partial tiles
-// with FP32 atomics.
+// 16-byte LDS read; blocks split the pixel range (blockIdx.z).  With a
+// workspace, each split stores its partial tile in slice z of part (weights at
+// [co][k], then the bias at [C_out * K + co]) and the slices are summed in a
+// fixed order (k_sum_slices, k_wgrad_reduce), so the result does not depend on
+// scheduling; without one, the splits add their tiles with FP32 atomics.
 constexpr int kLd = 40;   // LDS row length in 16-bit words (80 B, keeps 16 B alignment)
 
 __global__ __launch_bounds__(kThreads) void k_wgrad(Conv c, const uint16_t* __restrict__ x,
                                                     const uint16_t* __restrict__ skip,
                                                     const uint16_t* __restrict__ gy, float* gw, float* gb,
-                                                    int chunks_per_block) {
+                                                    int chunks_per_block, float* part) {
   __shared__ __attribute__((aligned(16))) uint16_t sG[64 * kLd];
   __shared__ __attribute__((aligned(16))) uint16_t sA[64 * kLd];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -280,10 +283,43 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(Conv c, const uint16_t* __re
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int o = co0 + wm * 32 + 16 * i + 4 * (lane >> 4) + r;
-        if (o < c.cout && kk < K) unsafeAtomicAdd(&gw[(int64_t)o * K + kk], acc[i][j][r]);
+        if (o < c.cout && kk < K) {
+          if (part) part[(int64_t)blockIdx.z * ((int64_t)c.cout * (K + 1)) + (int64_t)o * K + kk] = acc[i][j][r];
+          else unsafeAtomicAdd(&gw[(int64_t)o * K + kk], acc[i][j][r]);
+        }
       }
     }
-  if (blockIdx.x == 0 && t < 64 && co0 + t < c.cout) unsafeAtomicAdd(&gb[co0 + t], bsum);
+  if (blockIdx.x == 0 && t < 64 && co0 + t < c.cout) {
+    if (part) part[(int64_t)blockIdx.z * ((int64_t)c.cout * (K + 1)) + (int64_t)c.cout * K + co0 + t] = bsum;
+    else unsafeAtomicAdd(&gb[co0 + t], bsum);
+  }
+}
+
+// dst[g][e] = sum over z in [g G, min((g + 1) G, slices)) of src[z][e], in that
+// order (slices of m elements).
+__global__ void k_sum_slices(const float* __restrict__ src, float* dst, int64_t m, int slices, int G) {
+  const int groups = (slices + G - 1) / G;
+  const int64_t total = (int64_t)groups * m;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(i / m);
+    const int64_t e = i - (int64_t)g * m;
+    const int z1 = (g + 1) * G < slices ? (g + 1) * G : slices;
+    float acc = 0.f;
+    for (int z = g * G; z < z1; ++z) acc += src[z * m + e];
+    dst[i] = acc;
+  }
+}
+
+// gw[e] += sum over z of part[z][e] (e < n), gb[e - n] likewise (n <= e < m),
+// in slice order.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, float* gw, float* gb, int64_t n, int64_t m,
+                               int slices) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int z = 0; z < slices; ++z) acc += part[z * m + e];
+    if (e < n) gw[e] += acc;
+    else gb[e - n] += acc;
+  }
 }
 
 __global__ void k_pack_w(Conv c, const float* __restrict__ w, uint16_t* w16, uint16_t* wt16) {
@@ -462,16 +498,65 @@ hipError_t conv_backward_data(const Conv& c, const uint16_t* gy, const uint16_t*
   return hipSuccess;
 }
 
-hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t* skip, const uint16_t* gy,
-                                float* gw, float* gb, hipStream_t st) {
-  const int K = 9 * c.ctot();
-  const int kt = (K + 63) / 64, ctl = (c.cout + 63) / 64;
+namespace {
+// Launch shape of k_wgrad: pixel chunks per block and the number of splits.
+// splits <= want for every batch size (it depends on the tile counts only).
+struct WgradShape {
+  int K, kt, ctl;
+  int64_t want, cpb, splits;
+};
+WgradShape wgrad_shape(const Conv& c) {
+  WgradShape w;
+  w.K = 9 * c.ctot();
+  w.kt = (w.K + 63) / 64;
+  w.ctl = (c.cout + 63) / 64;
   const int64_t chunks = (c.out_pixels() + 31) / 32;
-  const int64_t want = (2048 + (int64_t)kt * ctl - 1) / ((int64_t)kt * ctl);
-  const int64_t splits = want < chunks ? (want > 0 ? want : 1) : chunks;
-  const int64_t cpb = (chunks + splits - 1) / splits;
-  dim3 grid((unsigned)kt, (unsigned)ctl, (unsigned)((chunks + cpb - 1) / cpb));
-  k_wgrad<<<grid, kThreads, 0, st>>>(c, x, skip, gy, gw, gb, (int)cpb);
+  w.want = (2048 + (int64_t)w.kt * w.ctl - 1) / ((int64_t)w.kt * w.ctl);
+  const int64_t s = w.want < chunks ? (w.want > 0 ? w.want : 1) : chunks;
+  w.cpb = (chunks + s - 1) / s;
+  w.splits = (chunks + w.cpb - 1) / w.cpb;
+  return w;
+}
+}  // namespace
+
+// Slices summed per thread in each level of the ordered reduction.
+constexpr int kSliceGroup = 32;
+
+// Workspace floats for `slices` slices of m elements: the slices, then the
+// group sums of the levels needed to bring them down to kSliceGroup.
+int64_t reduce_workspace(int64_t slices, int64_t m) {
+  int64_t total = slices * m;
+  for (int64_t s = slices; s > kSliceGroup; s = (s + kSliceGroup - 1) / kSliceGroup)
+    total += (s + kSliceGroup - 1) / kSliceGroup * m;
+  return total;
+}
+
+int64_t conv_backward_weight_workspace(const Conv& c) {
+  const WgradShape w = wgrad_shape(c);
+  return reduce_workspace(w.want > 0 ? w.want : 1, (int64_t)c.cout * (w.K + 1));
+}
+
+hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t* skip, const uint16_t* gy,
+                                float* gw, float* gb, hipStream_t st, float* work, int64_t work_floats) {
+  const WgradShape w = wgrad_shape(c);
+  const int64_t n = (int64_t)c.cout * w.K, m = n + c.cout;
+  const bool ordered = work && work_floats >= reduce_workspace(w.splits, m);
+  dim3 grid((unsigned)w.kt, (unsigned)w.ctl, (unsigned)w.splits);
+  k_wgrad<<<grid, kThreads, 0, st>>>(c, x, skip, gy, gw, gb, (int)w.cpb, ordered ? work : nullptr);
+  if (ordered) {
+    // groups of kSliceGroup consecutive slices, level by level, then the sum
+    // of the remaining slices into gw and gb: a fixed order at every level
+    float* src = work;
+    int64_t slices = w.splits;
+    while (slices > kSliceGroup) {
+      float* dst = src + slices * m;
+      const int64_t groups = (slices + kSliceGroup - 1) / kSliceGroup;
+      k_sum_slices<<<grid_for(groups * m), kThreads, 0, st>>>(src, dst, m, (int)slices, kSliceGroup);
+      src = dst;
+      slices = groups;
+    }
+    k_wgrad_reduce<<<grid_for(m), kThreads, 0, st>>>(src, gw, gb, n, m, (int)slices);
+  }
   return hipGetLastError();
 }
 

@@ -36,9 +36,14 @@ hipError_t conv_forward(const Conv& c, const uint16_t* x, const uint16_t* skip, 
 // gx (primary input, stored resolution) and gskip accumulate (+=); either may be null
 hipError_t conv_backward_data(const Conv& c, const uint16_t* gy, const uint16_t* wt, float* gx, float* gskip,
                               hipStream_t st);
-// gw [C_out][9][C_in + C_skip] and gb [C_out] accumulate (+=)
+// gw [C_out][9][C_in + C_skip] and gb [C_out] accumulate (+=).  With a device
+// workspace of at least conv_backward_weight_workspace(c) floats the partial
+// sums are added in a fixed order (bit-reproducible); without one, with FP32
+// atomics.
 hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t* skip, const uint16_t* gy,
-                                float* gw, float* gb, hipStream_t st);
+                                float* gw, float* gb, hipStream_t st, float* work = nullptr,
+                                int64_t work_floats = 0);
+int64_t conv_backward_weight_workspace(const Conv& c);
 hipError_t pack_weights(const Conv& c, const float* w, uint16_t* w16, uint16_t* wt16, hipStream_t st);
 hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                 float c1, float c2, hipStream_t st);

@@ -84,6 +84,8 @@ struct Net {
   float* gout = nullptr;
   uint16_t* gy16 = nullptr;
   double* loss = nullptr;
+  float* wwork = nullptr;    // partial weight-gradient tiles (ordered reduction)
+  int64_t wwork_n = 0;
   int64_t step = 0;
 };
 
@@ -151,7 +153,7 @@ void free_net(Net* n) {
   if (!n) return;
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   void* ptrs[] = {n->params, n->grads, n->m, n->v, n->w16, n->wt16, n->in16, n->act, n->gact, n->out32,
-                  n->gout, n->gy16, n->loss};
+                  n->gout, n->gy16, n->loss, n->wwork};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete n;
@@ -208,7 +210,7 @@ int gradient(Net* n, const float* x, const float* t, int batch) {
     NN_TRY(vlbm::nn::relu_grad(g, i == last ? nullptr : n->act + L.act_off, n->gy16, nout, L.c.relu, n->stream));
     const uint16_t* skip = L.skip >= 0 ? input_of(n, L.skip) : nullptr;
     NN_TRY(vlbm::nn::conv_backward_weight(L.c, input_of(n, L.src), skip, n->gy16, n->grads + L.w_off,
-                                          n->grads + L.b_off, n->stream));
+                                          n->grads + L.b_off, n->stream, n->wwork, n->wwork_n));
     if (L.src >= 0)
       NN_TRY(vlbm::nn::conv_backward_data(L.c, n->gy16, n->wt16 + L.w_off, grad_of(n, L.src),
                                           L.skip >= 0 ? grad_of(n, L.skip) : nullptr, n->stream));
@@ -327,6 +329,14 @@ int vlbm_surrogate_create(int height, int width, int max_batch, const float* par
   A(alloc(&n->gout, pixels * kOut));
   A(alloc(&n->gy16, n->max_out * max_batch));
   A(alloc(&n->loss, 1));
+  // the weight gradients add their split partial sums in a fixed order, so
+  // training is bit-reproducible; the workspace fits the largest layer at any
+  // batch size
+  for (const Layer& L : n->layers) {
+    const int64_t need = vlbm::nn::conv_backward_weight_workspace(L.c);
+    if (need > n->wwork_n) n->wwork_n = need;
+  }
+  A(alloc(&n->wwork, n->wwork_n));
   if (e != hipSuccess) {
     free_net(n);
     return fail(VLBM_ERR_NOMEM, "surrogate: device allocation failed (%s)", hipGetErrorString(e));
