@@ -315,7 +315,9 @@ int vlbm_conv2d_forward(const vlbm_conv_desc* d, const uint16_t* x, const uint16
  * when upsampled) and gskip += d/dskip; FP32, either may be NULL. */
 int vlbm_conv2d_backward_data(const vlbm_conv_desc* d, const uint16_t* gy, const uint16_t* wt, float* gx,
                               float* gskip, void* stream);
-/* gw += d/dw, gb += d/dbias (FP32, accumulated with atomics). */
+/* gw += d/dw, gb += d/dbias (FP32, the pixel splits accumulated with atomics,
+ * so the last bits depend on scheduling; the surrogate object below adds them
+ * in a fixed order from its own workspace instead). */
 int vlbm_conv2d_backward_weight(const vlbm_conv_desc* d, const uint16_t* x, const uint16_t* skip,
                                 const uint16_t* gy, float* gw, float* gb, void* stream);
 /* BF16 copies (round to nearest even) of FP32 weights w: w_bf16 in the same
@@ -349,7 +351,9 @@ int vlbm_surrogate_create(int height, int width, int max_batch, const float* par
 int vlbm_surrogate_forward(vlbm_surrogate s, const float* x, int batch, float* y);
 /* Forward + mean squared error over the 3 outputs + backward.  loss (host,
  * nullable; synchronises when given), grad (device, nullable) receives the
- * gradient with respect to the parameter vector. */
+ * gradient with respect to the parameter vector, bit-reproducible for given
+ * weights and inputs (the reported loss is summed with an atomic and may differ
+ * in its last bit). */
 int vlbm_surrogate_gradient(vlbm_surrogate s, const float* x, const float* target, int batch, double* loss,
                             float* grad);
 /* Adam update with the last gradient (step count kept by the object). */
