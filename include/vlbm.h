@@ -351,9 +351,8 @@ int vlbm_surrogate_create(int height, int width, int max_batch, const float* par
 int vlbm_surrogate_forward(vlbm_surrogate s, const float* x, int batch, float* y);
 /* Forward + mean squared error over the 3 outputs + backward.  loss (host,
  * nullable; synchronises when given), grad (device, nullable) receives the
- * gradient with respect to the parameter vector, bit-reproducible for given
- * weights and inputs (the reported loss is summed with an atomic and may differ
- * in its last bit). */
+ * gradient with respect to the parameter vector; both are bit-reproducible for
+ * given weights and inputs (partial sums are added in a fixed order). */
 int vlbm_surrogate_gradient(vlbm_surrogate s, const float* x, const float* target, int batch, double* loss,
                             float* grad);
 /* Adam update with the last gradient (step count kept by the object). */

@@ -378,8 +378,10 @@ __global__ void k_unpack_output(const float* __restrict__ out, float* y, int64_t
   }
 }
 
+// Per-block sums of squared errors into part[blockIdx.x]; k_loss_sum adds the
+// blocks in a fixed order, so the loss is bit-reproducible.
 __global__ __launch_bounds__(kThreads) void k_mse(const float* __restrict__ out, const float* __restrict__ t,
-                                                  float* gout, double* loss, int64_t pixels, int cpad, int ct,
+                                                  float* gout, double* part, int64_t pixels, int cpad, int ct,
                                                   double inv_count) {
   __shared__ double red[kThreads / 64];
   double s = 0.0;
@@ -401,8 +403,18 @@ __global__ __launch_bounds__(kThreads) void k_mse(const float* __restrict__ out,
   if (threadIdx.x == 0) {
     double b = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) b += red[w];
-    unsafeAtomicAdd(loss, b * inv_count);
+    part[blockIdx.x] = b;
   }
+}
+
+// *loss = inv_count * sum of part[0 .. nblocks): one wave, each lane summing a
+// fixed strided subset in order, then a fixed butterfly across the lanes.
+__global__ __launch_bounds__(64) void k_loss_sum(const double* __restrict__ part, int nblocks, double inv_count,
+                                                 double* loss) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 64) s += part[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (threadIdx.x == 0) *loss = s * inv_count;
 }
 
 int grid_for(int64_t n) {
@@ -592,9 +604,12 @@ hipError_t unpack_output(const float* out, float* y, int64_t pixels, int cpad, i
 }
 
 hipError_t mse(const float* out, const float* t, float* gout, double* loss, int64_t pixels, int cpad, int ct,
-               hipStream_t st) {
+               double* part, hipStream_t st) {
   const double inv = 1.0 / ((double)pixels * ct);
-  k_mse<<<grid_for(pixels * cpad), kThreads, 0, st>>>(out, t, gout, loss, pixels, cpad, ct, inv);
+  const int nb = grid_for(pixels * cpad);
+  if (nb > kMseBlocks) return hipErrorInvalidValue;   // grid_for caps at 4096 blocks
+  k_mse<<<nb, kThreads, 0, st>>>(out, t, gout, part, pixels, cpad, ct, inv);
+  k_loss_sum<<<1, 64, 0, st>>>(part, nb, inv, loss);
   return hipGetLastError();
 }
 

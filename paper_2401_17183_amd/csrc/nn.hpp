@@ -54,9 +54,11 @@ hipError_t relu_grad(const float* g, const uint16_t* act, uint16_t* out16, int64
 hipError_t pack_input(const float* x, uint16_t* x16, int64_t pixels, int cin, int cpad, hipStream_t st);
 // y[pixels][cout] = out[pixels][cpad] for the first cout channels
 hipError_t unpack_output(const float* out, float* y, int64_t pixels, int cpad, int cout, hipStream_t st);
-// loss += sum (out - t)^2 / count over the first ct channels; gout = 2 (out - t) / count there, 0 elsewhere
+// loss = sum (out - t)^2 / count over the first ct channels (in a fixed order; part: device
+// workspace of kMseBlocks doubles); gout = 2 (out - t) / count there, 0 elsewhere
+constexpr int kMseBlocks = 4096;
 hipError_t mse(const float* out, const float* t, float* gout, double* loss, int64_t pixels, int cpad, int ct,
-               hipStream_t st);
+               double* part, hipStream_t st);
 
 }  // namespace nn
 }  // namespace vlbm

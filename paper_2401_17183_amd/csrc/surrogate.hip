@@ -84,6 +84,7 @@ struct Net {
   float* gout = nullptr;
   uint16_t* gy16 = nullptr;
   double* loss = nullptr;
+  double* lossp = nullptr;   // per-block loss partials (ordered reduction)
   float* wwork = nullptr;    // partial weight-gradient tiles (ordered reduction)
   int64_t wwork_n = 0;
   int64_t step = 0;
@@ -153,7 +154,7 @@ void free_net(Net* n) {
   if (!n) return;
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   void* ptrs[] = {n->params, n->grads, n->m, n->v, n->w16, n->wt16, n->in16, n->act, n->gact, n->out32,
-                  n->gout, n->gy16, n->loss, n->wwork};
+                  n->gout, n->gy16, n->loss, n->lossp, n->wwork};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete n;
@@ -200,8 +201,7 @@ int gradient(Net* n, const float* x, const float* t, int batch) {
   const int64_t pixels = (int64_t)batch * n->H * n->W;
   NN_TRY(vlbm::nn::fill(n->grads, n->nparams, 0.f, n->stream));
   NN_TRY(vlbm::nn::fill(n->gact, n->act_total, 0.f, n->stream));
-  NN_TRY(hipMemsetAsync(n->loss, 0, sizeof(double), n->stream));
-  NN_TRY(vlbm::nn::mse(n->out32, t, n->gout, n->loss, pixels, kOut, kTargets, n->stream));
+  NN_TRY(vlbm::nn::mse(n->out32, t, n->gout, n->loss, pixels, kOut, kTargets, n->lossp, n->stream));
   const int last = (int)n->layers.size() - 1;
   for (int i = last; i >= 0; --i) {
     const Layer& L = n->layers[i];
@@ -329,6 +329,7 @@ int vlbm_surrogate_create(int height, int width, int max_batch, const float* par
   A(alloc(&n->gout, pixels * kOut));
   A(alloc(&n->gy16, n->max_out * max_batch));
   A(alloc(&n->loss, 1));
+  A(alloc(&n->lossp, vlbm::nn::kMseBlocks));
   // the weight gradients add their split partial sums in a fixed order, so
   // training is bit-reproducible; the workspace fits the largest layer at any
   // batch size

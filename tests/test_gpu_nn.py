@@ -253,10 +253,11 @@ def test_surrogate_training_reduces_loss():
 
 
 def test_surrogate_training_is_bit_reproducible():
-    """The network's weight gradients add their per-split partial sums in a
+    """The network's weight gradients and its loss add their partial sums in a
     fixed order (no atomics), so two networks trained from the same weights on
-    the same batches hold bit-identical gradients and weights; a smaller batch
-    than the network was built for takes the same path."""
+    the same batches report bit-identical losses and hold bit-identical
+    gradients and weights; a smaller batch than the network was built for
+    takes the same path."""
     v = _vlbm()
     announce("surrogate bit-reproducible training 16x32, batches 4 and 3, 6 steps")
     rng = np.random.default_rng(17)
@@ -265,13 +266,12 @@ def test_surrogate_training_is_bit_reproducible():
     x = torch.tensor(rng.uniform(-1, 1, (N, H, W, 3)), dtype=torch.float32)
     t = torch.tensor(0.5 * rng.standard_normal((N, H, W, 3)), dtype=torch.float32)
     a, b = v.Surrogate(H, W, N, p0), v.Surrogate(H, W, N, p0)
-    _, ga = a.gradient(x, t)
-    _, gb = b.gradient(x, t)
-    assert torch.equal(ga, gb)
+    la, ga = a.gradient(x, t)
+    lb, gb = b.gradient(x, t)
+    assert la == lb and torch.equal(ga, gb)
     for k in range(6):
         n = N if k % 2 == 0 else N - 1
-        a.train_step(x[:n], t[:n], 1e-3, want_loss=False)
-        b.train_step(x[:n], t[:n], 1e-3, want_loss=False)
+        assert a.train_step(x[:n], t[:n], 1e-3) == b.train_step(x[:n], t[:n], 1e-3)
     pa, sa = a.params()
     pb, sb = b.params()
     assert sa == sb == 6
