@@ -173,11 +173,12 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
 #pragma unroll
   for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
   // gather again (cache hits) rather than keeping N live across the fixed point
-  // where registers are short: FP64 populations and the general collision
-  // variant.  Decoded 16-bit populations stay in registers (their re-gather
-  // would also re-read and re-apply the link references), and so do FP32
-  // populations of the BGK variants.
-  constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && (sizeof(P) == 8 || GEN);
+  // where registers are short: the general collision variant with FP64
+  // arithmetic.  Decoded 16-bit populations stay in registers (their re-gather
+  // would also re-read and re-apply the link references), and so do the
+  // populations of the BGK variants (FP64 ones in accumulation registers: that
+  // kernel runs one wave per SIMD either way).
+  constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && GEN;
   if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
     // here instead of being kept (or spilled) across the fixed point
