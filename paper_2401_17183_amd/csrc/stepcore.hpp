@@ -104,7 +104,8 @@ __device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const Li
 
 // Pull N_a(q) = N'_a(q - c_a) (eq. (adv)).  Every load is unconditional and in
 // bounds (a bounced or far-field link reads the cell's own opposite slot), so
-// no lane diverges; far-field links then take J f^eq(rho_inf, U_inf, U_inf).
+// no lane diverges; far-field links then take J f^eq(rho_inf, U_inf, U_inf),
+// evaluated only in the cells that have such a link.
 // FF: 0 = no far-field links, 1 = far-field links, 2 = decided at run time
 // (has_ff); a compile-time choice keeps the fill out of the control flow.
 template <class L, class P, class S, class T, class NR, int ST, int FF = 2>
@@ -118,7 +119,9 @@ __device__ __forceinline__ void gather(const StepArgs<P, S, T>& a, const CellGeo
   if constexpr (L::SPEED == 1) plan = link_plan<L>(a.box, x, y, z);
   DirMask<L> ff = 0;
   gather_dirs<L, P, S, T, NR>(a, plan, x, y, z, cell, N, ff);
-  if (FF == 1 || (FF == 2 && a.has_ff)) {   // compile-time or wave-uniform
+  // compile-time or wave-uniform, then only cells with a far-field link (a wave
+  // without one skips the equilibrium)
+  if ((FF == 1 || (FF == 2 && a.has_ff)) && ff != 0) {
     T Uinf[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) Uinf[i] = T(a.geo[pack_index<L>(Pack<L>::UINF + i, cell)]);
