@@ -112,8 +112,9 @@ typedef struct {
   double max_abs_A;                  /* max |A^i_a|, the contracted Theta           */
 } vlbm_geom_report;
 
-/* FP64 geometry precompute on the device, once per mesh (Sec. 2.1: the
- * quantities "can be pre-computed before starting" a simulation):
+/* FP64 geometry precompute on the device, once per mesh (Sec. 2.1 notes that
+ * the geometric coefficients depend on the mesh only, so they are computed
+ * once, before the time stepping):
  * D_{+-i} (eq. (distance)), beta_i and g_i (eq. (tangent)), J (eq. (jacobian)),
  * g^i (eq. (covectors)), g^{ij} (eq. (inverse)) on real cells and the first
  * ghost layer, then the link coefficients
