@@ -28,19 +28,59 @@ HBM_PEAK_GBS = 8000.0
 
 
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp32c": 4, "fp16s": 2, "bf16s": 2}
+# modes that store deviations from a 16-bit per-slot reference
+SHIFTED = ("fp32", "fp16s", "bf16s")
+REBASE_EVERY = 10
 
 
 def algorithmic_bytes_per_cell(Q, d, precision, has_force, has_farfield=False):
-    """Bytes one step must move per cell: the Q populations read once and
-    written once, the packed per-cell geometry words (J, g^{ij} upper, A^i_a for
-    a >= 1, a_ext when a body force acts, U_inf when there is a far field; FP64
-    words for FP64 storage, FP32 otherwise), and for the 16-bit storage modes
-    the two 16-bit reference states (the cell's own and its link sources')."""
+    """Bytes one fused step launch must move per cell: the Q populations read
+    once and written once, the packed per-cell geometry words (J, g^{ij} upper,
+    A^i_a for a >= 1, a_ext when a body force acts, U_inf when there is a far
+    field; FP64 words for FP64 storage, FP32 otherwise, with a second FP32
+    word per g^{ij} for FP32 storage, whose arithmetic is FP64), and for the deviation
+    storage modes the Q 16-bit references of the slots (each read by its
+    writer and, at the offset of the population, by its reader: one array)."""
     sb = STORAGE_BYTES[precision]
     gb = 8 if precision == "fp64" else 4
     words = 1 + d * (d + 1) // 2 + (Q - 1) * d + (d if has_force else 0) + (d if has_farfield else 0)
-    refs = 2 * Q * 2 if sb == 2 else 0
+    if precision == "fp32":   # FP64 arithmetic on FP32 words: g^{ij} as a hi + lo pair
+        words += d * (d + 1) // 2
+    refs = Q * 2 if precision in SHIFTED else 0
     return 2 * Q * sb + words * gb + refs
+
+
+def rebase_bytes_per_cell(Q, precision):
+    """Bytes one re-basing launch moves per cell: populations and references
+    read and written once (deviation storage only)."""
+    return 2 * Q * (STORAGE_BYTES[precision] + 2) if precision in SHIFTED else 0
+
+
+def host_cpu():
+    """Host cores and CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cores": os.cpu_count(), "cpu_model": model}
+
+
+def copy_ceiling(vlbm):
+    """STREAM-style rates of the device (library kernels, 2 GiB buffers):
+    the best of regular and non-temporal accesses for copy, read and write."""
+    out = {}
+    for kind in ("copy", "read", "write"):
+        best = 0.0
+        for nt in (False, True):
+            g, _ = vlbm.membench(kind, nontemporal=nt, bytes_=2 << 30, reps=8)
+            best = max(best, g)
+        out[kind] = round(best, 1)
+    return out
 
 
 def make_workload(name):
@@ -101,8 +141,10 @@ def cpu_baseline(workload="channel", seconds_target=12.0, tau_g=None, tau=None):
                 s.step(1)
             steps += 1
         dt = time.perf_counter() - t0
-    return {"value": round(cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{label}, FP64, {steps} steps, {dt:.1f} s, 1 thread"}
+    out = {"value": round(cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "sample": f"{label}, FP64, {steps} steps, {dt:.1f} s, 1 thread"}
+    out.update(host_cpu())
+    return out
 
 
 # committed counter summaries per single-mesh workload: <stem>_<precision>[_tau..][_taug..].md
@@ -156,17 +198,14 @@ def _timed(torch, stream, fn, steps):
     return e0.elapsed_time(e1)
 
 
-def _copy_ref(torch, out):
-    """One plain 1 GiB device-to-device copy (the reference the HBM counters are
-    scaled by), timed with HIP events: its achieved GB/s is the practical copy
-    ceiling on this device."""
-    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    stream = torch.cuda.current_stream()
-    dst.copy_(src)   # warm
-    ms = _timed(torch, stream, lambda n: [dst.copy_(src) for _ in range(n)], 5) / 5
-    out["config"]["copy_ref_bytes"] = 2 * src.numel() * 4
-    out["config"]["copy_ref_GBps"] = round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)
+def _copy_ref(torch, out, vlbm):
+    """One plain 1 GiB device copy with the library's STREAM copy kernel
+    (k_copy; the reference the HBM counters are scaled by), its best rate
+    beside it."""
+    g, grid = vlbm.membench("copy", nontemporal=False, bytes_=1 << 30, reps=1)
+    out["config"]["copy_ref_bytes"] = 2 << 30
+    out["config"]["copy_ref_GBps"] = round(g, 1)
+    out["config"]["copy_ref_grid"] = grid
 
 
 def collision_name(tau_g):
@@ -192,16 +231,13 @@ def run_single(args, torch, vlbm):
     sim.step(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()   # the Sim launches on torch's current stream
+    blob = sim.save()                      # the state the timed steps start from
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ms = _timed(torch, stream, sim.step, args.steps)
     wall = time.perf_counter() - t0
     ms_per_step = ms / args.steps
     mlups = cells * args.steps / (ms / 1e3) / 1e6
-    has_force = any(v != 0 for v in w.get("body_force", (0, 0, 0)))
-    has_ff = any(f == vlbm.FARFIELD for face in w["faces"] for f in face)
-    bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, args.precision, has_force, has_ff)
-    achieved = bpc * cells / (ms_per_step / 1e3) / 1e9
     state = "ok"
     try:
         mo = sim.moments()
@@ -209,10 +245,30 @@ def run_single(args, torch, vlbm):
     except vlbm.VlbmError as e:   # the timed steps ran; the state they reached is reported
         finite = False
         state = str(e)
+    # the same steps again from the same state: durations of each kernel from
+    # HIP events around its launches, then the fixed point's iteration counts
+    print("[bench] kernel durations and fixed-point statistics of the same steps", file=sys.stderr, flush=True)
+    sim.restore(blob)
+    sim.kernel_timing(True)
+    sim.step(args.steps)
+    kt = sim.kernel_timing(False)
+    sim.restore(blob)
+    sim.step_stats(True)
+    sim.step(args.steps)
+    st = sim.step_stats(False)
+    del blob
+    k_ms = kt["step_ms"] / max(kt["step_launches"], 1)
+    rb_ms = kt["rebase_ms"] / kt["rebase_launches"] if kt["rebase_launches"] else None
+    has_force = any(v != 0 for v in w.get("body_force", (0, 0, 0)))
+    has_ff = any(f == vlbm.FARFIELD for face in w["faces"] for f in face)
+    bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, args.precision, has_force, has_ff)
+    achieved = bpc * cells / (k_ms / 1e3) / 1e9
     traffic = None
     if args.workload in PROFILE_STEM:
         tag = ("" if args.tau is None else f"_tau{args.tau:g}") + ("" if args.tau_g is None else f"_taug{args.tau_g:g}")
         traffic = profiled_traffic(f"{PROFILE_STEM[args.workload]}_{args.precision}{tag}.md", STEP_SOURCES)
+    print("[bench] STREAM-style ceiling", file=sys.stderr, flush=True)
+    ceil = copy_ceiling(vlbm)
     return {
         "metric": METRIC,
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -221,13 +277,21 @@ def run_single(args, torch, vlbm):
         "data": "synthetic",
         "config": {"workload": w["name"] + f" {args.precision.upper()}", "cells": cells, "lattice": w["lattice"],
                    "tau": w["tau"], "collision": collision_name(args.tau_g), "storage": STORAGE[args.precision],
-                   "wall_s": round(wall, 3), "finite": finite, "state": state},
+                   "wall_s": round(wall, 3), "finite": finite, "state": state,
+                   "fp_iters_per_cell_step": round(st["iters_per_cell"], 3),
+                   "fp_wave_max_iters_per_step": round(st["wave_max_iters"], 3),
+                   "k_step_ms": round(k_ms, 5), "k_rebase_ms": None if rb_ms is None else round(rb_ms, 5),
+                   "rebase_every": REBASE_EVERY if args.precision in SHIFTED else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "algorithmic_bytes_per_launch": bpc * cells,
-                     "bytes_per_cell": bpc, "kernel": "k_step"},
+                     "bytes_per_cell": bpc, "kernel": "k_step",
+                     "kernel_ms": round(k_ms, 5),
+                     "copy_ceiling_GBps": ceil["copy"], "read_ceiling_GBps": ceil["read"],
+                     "write_ceiling_GBps": ceil["write"],
+                     "frac_of_copy_ceiling": round(achieved / ceil["copy"], 4) if ceil["copy"] else None},
     }
 
 
@@ -238,10 +302,7 @@ def run_batch(args, torch, vlbm):
     meshes = [vlbm.Mesh.from_workload(w) for w in ws]
     params = [vlbm.make_params(w["tau"], body_force=w["body_force"], precision=args.precision, tau_g=args.tau_g)
               for w in ws]
-    b = vlbm.Batch(meshes, params)
-    for w, m in zip(ws, b.members):
-        rho, u = W.channel_vortex_fields(w)
-        m.reinit(rho=rho.ravel(), u=u.reshape(2, -1))
+    b = vlbm.Batch(meshes, params)   # every member starts at rest
     cells = b.info()["cells"]
     stream = torch.cuda.ExternalStream(b.info()["stream"])
     print("[bench] autotune", file=sys.stderr, flush=True)
@@ -477,7 +538,7 @@ def main():
     else:
         out = run_single(args, torch, vlbm)
     if args.copy_ref:
-        _copy_ref(torch, out)
+        _copy_ref(torch, out, vlbm)
     if not args.no_cpu and args.workload not in ("surrogate", "train"):
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, tau_g=args.tau_g, tau=args.tau)

@@ -147,9 +147,10 @@ typedef struct {
                             H the projector onto the Hermite content of order <= 2, so the
                             stress relaxes at 1/tau (eq. (matrix)) and the rest at 1/tau_g
                             (1: regularised collision); must exceed 1/2                 */
-  int32_t rebase_every;  /* FP16S / BF16S: every k steps the 16-bit references are re-based
-                            on the current state, so that the stored deviations restart
-                            near zero (0: every 10 steps; < 0: never); ignored otherwise */
+  int32_t rebase_every;  /* FP32 / FP16S / BF16S (deviation storage): every k steps the
+                            16-bit references are re-based on the current state, so that
+                            the stored deviations restart near zero (0: every 10 steps;
+                            < 0: never); ignored for FP64 and FP32C                    */
 } vlbm_params;
 
 /* Create a simulation on a precomputed mesh and set the initial state
@@ -164,12 +165,43 @@ int vlbm_init(vlbm_mesh m, const vlbm_params* p, const double* rho, const double
               void* stream, vlbm_sim* out);
 
 /* Advance nsteps time steps: the fused pull-advection (eq. (adv)) + collision
- * (eq. (collide), BGK or the general matrix of tau_g) (16-bit modes: plus the
- * re-basing of the references every rebase_every steps) + inertial force (eqs. (compo-constr),
- * (delta-flux), (deltaN)) + curvilinear equilibrium (eq. (equilibrium)) update
- * of eq. (lbe), with the implicit force solved per cell as a converged fixed
- * point.  Asynchronous: returns after enqueueing on the sim's stream. */
+ * (eq. (collide), BGK or the general matrix of tau_g) (deviation storage: plus
+ * the re-basing of the references every rebase_every steps) + inertial force
+ * (eqs. (compo-constr), (delta-flux), (deltaN)) + curvilinear equilibrium
+ * (eq. (equilibrium)) update of eq. (lbe), with the implicit force solved per
+ * cell as a converged fixed point.  Asynchronous: returns after enqueueing on
+ * the sim's stream.  Cells whose fixed point hits fp_max_iter are counted on
+ * the device and reported by the next vlbm_sync or vlbm_moments. */
 int vlbm_step(vlbm_sim s, int64_t nsteps);
+
+/* Wait for the sim's enqueued work.  Returns VLBM_ERR_NOCONVERGE when a step
+ * since the last report ran some cell on an inertial force whose fixed point
+ * (eq. (compo-constr)) hit fp_max_iter, with the count of such cell-steps in
+ * vlbm_last_error(); the count is then reset.  VLBM_ERR_DEVICE on a device
+ * error. */
+int vlbm_sync(vlbm_sim s);
+
+/* Statistics of the per-cell fixed point of the steps taken while enabled
+ * (off by default; enabling it costs a few wavefront ballots and four atomic
+ * adds per wavefront and step).  out (host, may be NULL) receives, since the
+ * previous read: [0] the sum over cell-steps of the iterations, [1] the sum
+ * over wavefront-steps of the wavefront's largest count (the lanes of a
+ * wavefront iterate together), [2] the cell-steps and [3] the wavefront-steps
+ * counted; the counters are then reset.  Synchronises when out is not NULL. */
+int vlbm_step_stats(vlbm_sim s, int enable, uint64_t* out);
+
+/* Durations of the kernels launched by vlbm_step while enabled, from HIP
+ * events recorded on the sim's stream around each launch (off by default).
+ * out (host [4], may be NULL) receives, since the previous read: [0] total
+ * milliseconds and [1] count of the fused step launches, [2] and [3] the same
+ * for the re-basing launches of the deviation storage; the record is then
+ * cleared.  Synchronises when out is not NULL. */
+int vlbm_kernel_timing(vlbm_sim s, int enable, double* out);
+
+/* Change the fixed point's cap and tolerance for the following steps (the
+ * meaning of vlbm_params.fp_max_iter and fp_tol, with the same defaults for
+ * values <= 0 and < 0).  Host-only; VLBM_ERR_ARG for a null sim. */
+int vlbm_set_fixed_point(vlbm_sim s, int32_t max_iter, double tol);
 
 /* Output mapping (eq. (result)) of the current state, computed in FP64 after a
  * dry-run of the collision fixed point:
@@ -177,7 +209,9 @@ int vlbm_step(vlbm_sim s, int64_t nsteps);
  *  u    device double [d][cells]: Euclidean velocity Ut^i g_i (the shifted
  *       velocity Ut = U + F/(2 rho) that obeys the continuity equation);
  *  U    device double [d][cells] or NULL: contravariant first moment U^i.
- * Synchronises the stream.  Errors: VLBM_ERR_NOCONVERGE, VLBM_ERR_DEVICE. */
+ * Synchronises the stream.  Errors: VLBM_ERR_NOCONVERGE when the dry run or
+ * a step since the last report (see vlbm_sync) hit the fixed point's cap (the
+ * outputs are written either way), VLBM_ERR_DEVICE. */
 int vlbm_moments(vlbm_sim s, double* rho, double* u, double* U);
 
 /* Current arrived populations N_a(q, t) as FP64 into device double [Q][cells]
@@ -364,6 +398,18 @@ int vlbm_surrogate_train_step(vlbm_surrogate s, const float* x, const float* tar
 /* Copy the FP32 parameter vector out (synchronises); step (nullable) = Adam steps taken. */
 int vlbm_surrogate_params(vlbm_surrogate s, float* out, int64_t* step);
 int vlbm_surrogate_destroy(vlbm_surrogate s);
+
+/* ---------------------------- measurement -------------------------------- */
+
+/* STREAM-style bandwidth of the device: kind 0 read-only, 1 write-only,
+ * 2 copy, over device buffers of `bytes` each (allocated and freed by the
+ * call; use >= 2 GiB, well beyond the 256 MB last-level cache), 16-byte
+ * accesses, regular or non-temporal (nontemporal != 0) loads and stores.
+ * Several grid shapes are timed with HIP events over `reps` launches each on
+ * `stream`; *gbps receives the best rate in GB/s (copy counts its reads and
+ * writes), *best_grid (may be NULL) that launch's block count.  Synchronises.
+ * Errors: VLBM_ERR_ARG, VLBM_ERR_NOMEM, VLBM_ERR_DEVICE. */
+int vlbm_membench(int kind, int nontemporal, size_t bytes, int reps, void* stream, double* gbps, int* best_grid);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* vlbm_last_error(void);

@@ -33,6 +33,22 @@ __global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_batch(const StepArgs<P
   }
 }
 
+// Re-basing of every active member's references (rebase_cell, as for a single
+// mesh), over the same tile table; args of the parity whose input buffer holds
+// the state just written.
+template <class L, class P, class S, class T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_rebase(const StepArgs<P, S, T>* __restrict__ args,
+                                                        const Tile* __restrict__ tiles, int ntiles, int parity) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    const StepArgs<P, S, T> a = args[2 * tl.mesh + parity];
+    const int cell = tl.first + threadIdx.x;
+    if (cell < a.box.ncells)
+      rebase_cell<L, P>(const_cast<PopE<P>*>(a.in), const_cast<PopR<P>*>(a.rown), a.box.ncells, cell, a.scale,
+                        a.inv_scale);
+  }
+}
+
 __global__ void k_gather(const double* const* __restrict__ src, double* dst, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = *src[i];
@@ -95,21 +111,36 @@ hipError_t launch_batch_typed(BatchObj* b, int parity) {
   return hipGetLastError();
 }
 
+template <class L, class P, class S, class T, int BLOCK>
+hipError_t launch_rebase_typed(BatchObj* b, int parity) {
+  if constexpr (!PopCodec<P>::shifted) {
+    return hipSuccess;
+  } else {
+    const int grid = b->grid_per_cu > 0 ? std::min(b->ntiles, b->grid_per_cu * b->cus) : b->ntiles;
+    const StepArgs<P, S, T>* args = static_cast<const StepArgs<P, S, T>*>(b->d_args);
+    k_batch_rebase<L, P, S, T, BLOCK><<<grid, BLOCK, 0, b->stream>>>(args, b->d_tiles, b->ntiles, parity);
+    return hipGetLastError();
+  }
+}
+
+// what: 0 = step with the given parity, 1 = re-base the buffer of that parity
 template <class L, class P, class S, class T>
-hipError_t launch_batch_block(BatchObj* b, int parity) {
+hipError_t launch_batch_block(BatchObj* b, int parity, int what) {
   switch (b->block) {
-    case 64: return launch_batch_typed<L, P, S, T, 64>(b, parity);
-    case 128: return launch_batch_typed<L, P, S, T, 128>(b, parity);
-    default: return launch_batch_typed<L, P, S, T, 256>(b, parity);
+    case 64: return what ? launch_rebase_typed<L, P, S, T, 64>(b, parity) : launch_batch_typed<L, P, S, T, 64>(b, parity);
+    case 128:
+      return what ? launch_rebase_typed<L, P, S, T, 128>(b, parity) : launch_batch_typed<L, P, S, T, 128>(b, parity);
+    default:
+      return what ? launch_rebase_typed<L, P, S, T, 256>(b, parity) : launch_batch_typed<L, P, S, T, 256>(b, parity);
   }
 }
 
 template <class L>
-hipError_t launch_batch_lattice(BatchObj* b, int parity) {
+hipError_t launch_batch_lattice(BatchObj* b, int parity, int what) {
   switch (b->precision) {
-    case VLBM_FP64: return launch_batch_block<L, double, double, double>(b, parity);
-    case VLBM_FP32: return launch_batch_block<L, float, float, double>(b, parity);
-    default: return launch_batch_block<L, float, float, float>(b, parity);
+    case VLBM_FP64: return launch_batch_block<L, double, double, double>(b, parity, what);
+    case VLBM_FP32: return launch_batch_block<L, F32Dev, float, double>(b, parity, what);
+    default: return launch_batch_block<L, float, float, float>(b, parity, what);
   }
 }
 
@@ -117,7 +148,7 @@ template <class L>
 hipError_t upload_lattice(BatchObj* b) {
   switch (b->precision) {
     case VLBM_FP64: return upload_args<double, double, double>(b);
-    case VLBM_FP32: return upload_args<float, float, double>(b);
+    case VLBM_FP32: return upload_args<F32Dev, float, double>(b);
     default: return upload_args<float, float, float>(b);
   }
 }
@@ -126,7 +157,12 @@ hipError_t upload_lattice(BatchObj* b) {
 
 hipError_t batch_launch(BatchObj* b, int parity) {
   if (b->ntiles == 0) return hipSuccess;   // no active member
-  return b->lattice == VLBM_D2Q9 ? launch_batch_lattice<D2Q9>(b, parity) : launch_batch_lattice<D3Q19>(b, parity);
+  return b->lattice == VLBM_D2Q9 ? launch_batch_lattice<D2Q9>(b, parity, 0) : launch_batch_lattice<D3Q19>(b, parity, 0);
+}
+
+hipError_t batch_rebase(BatchObj* b, int parity) {
+  if (b->ntiles == 0 || b->rebase <= 0) return hipSuccess;
+  return b->lattice == VLBM_D2Q9 ? launch_batch_lattice<D2Q9>(b, parity, 1) : launch_batch_lattice<D3Q19>(b, parity, 1);
 }
 
 hipError_t batch_upload(BatchObj* b) {
@@ -149,7 +185,10 @@ void batch_drop_graphs(BatchObj* b) {
     }
 }
 
-// Capture graph_steps consecutive steps (parities alternate) starting at parity p.
+// Capture graph_steps consecutive steps (parities alternate) starting at parity p,
+// at a step count that is a multiple of the re-basing period (graph_steps is
+// one too): the references are re-based after the steps that reach a multiple
+// of it, as for a single mesh.
 hipError_t batch_capture(BatchObj* b, int p, bool per_member) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
@@ -170,6 +209,7 @@ hipError_t batch_capture(BatchObj* b, int p, bool per_member) {
         if (le != hipSuccess) break;
       }
     }
+    if (le == hipSuccess && b->rebase > 0 && (k + 1) % b->rebase == 0) le = batch_rebase(b, par ^ 1);
   }
   e = hipStreamEndCapture(b->stream, &g);
   if (le != hipSuccess) {

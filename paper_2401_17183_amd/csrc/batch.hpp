@@ -24,7 +24,8 @@ struct BatchObj {
   int block = 256, grid_per_cu = 4, cus = 256;
   int mode = 0;                // VLBM_BATCH_*
   hipGraphExec_t exec[2] = {nullptr, nullptr};   // per starting parity
-  int graph_steps = 32;
+  int graph_steps = 32;         // steps per captured graph: even, and a multiple of rebase
+  int rebase = 0;               // shifted storage: re-basing period of the references (0: none)
   int64_t t = 0;
   int64_t total_cells = 0;
   bool any_ff = false;               // some member has far-field links
@@ -34,6 +35,8 @@ struct BatchObj {
 };
 
 hipError_t batch_launch(BatchObj* b, int parity);
+// shifted storage: re-base every active member's buffer of parity `parity`
+hipError_t batch_rebase(BatchObj* b, int parity);
 hipError_t batch_upload(BatchObj* b);
 hipError_t batch_capture(BatchObj* b, int p, bool per_member);
 void batch_drop_graphs(BatchObj* b);

@@ -85,6 +85,31 @@ struct CkptHeader {
   int64_t bytes;
 };
 
+// Event pairs recorded around kernel launches while a sim's timing is on:
+// kind 0 = step, 1 = re-basing.  Events are reused across reads.
+struct EventPool {
+  std::vector<hipEvent_t> ev;      // 2 per recorded launch
+  std::vector<int> kind;
+  size_t used = 0;                 // launches recorded since the last read
+  ~EventPool() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t begin(hipStream_t s, int k) {
+    if (2 * used + 2 > ev.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+      }
+      kind.push_back(k);
+    }
+    kind[used] = k;
+    return hipEventRecord(ev[2 * used], s);
+  }
+  hipError_t end(hipStream_t s) { return hipEventRecord(ev[2 * used++ + 1], s); }
+};
+
 }  // namespace
 
 extern "C" {
@@ -281,11 +306,12 @@ static void free_sim(SimObj* s) {
   dev_free(s->geo);
   dev_free(s->fcache);
   dev_free(s->rown);
-  dev_free(s->rsrc);
   dev_free(s->audit_ring);
   dev_free(s->audit_partial);
   dev_free(s->u_prev);
   dev_free(s->flags);
+  dev_free(s->stats);
+  delete static_cast<EventPool*>(s->timing);
   delete s;
 }
 
@@ -338,10 +364,8 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   if ((rc = dev_alloc(&s->pop[1], s->pop_bytes))) return bail(rc);
   const int words = pack_words(m->lattice);
   if ((rc = dev_alloc(&s->geo, pack_elements(words, nc) * geometry_bytes(s->p.precision)))) return bail(rc);
-  if (storage_is_16(s->p.precision)) {
-    if ((rc = dev_alloc(&s->rown, nc * m->Q * sb))) return bail(rc);
-    if ((rc = dev_alloc(&s->rsrc, nc * m->Q * sb))) return bail(rc);
-  }
+  if (storage_shifted(s->p.precision))   // 16-bit references
+    if ((rc = dev_alloc(&s->rown, nc * m->Q * 2))) return bail(rc);
   if ((rc = dev_alloc(&s->fcache, nc * d * fcache_elem(s->p.precision)))) return bail(rc);
   s->audit_cap = 4096;
   if ((rc = dev_alloc(&s->audit_ring, sizeof(vlbm_audit) * s->audit_cap))) return bail(rc);
@@ -349,12 +373,14 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   if ((rc = dev_alloc(&s->audit_partial, sizeof(double) * s->audit_blocks * audit_words()))) return bail(rc);
   if ((rc = dev_alloc(&s->u_prev, sizeof(double) * nc * d))) return bail(rc);
   if ((rc = dev_alloc(&s->flags, sizeof(int) * 4))) return bail(rc);
+  if ((rc = dev_alloc(&s->stats, sizeof(unsigned long long) * 4))) return bail(rc);
   hipError_t e = hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * 4, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->fcache, 0, nc * d * fcache_elem(s->p.precision), s->stream);
   if (e == hipSuccess) e = launch_pack(s);
-  if (e == hipSuccess && storage_is_16(s->p.precision)) e = launch_refs(s);
+  if (e == hipSuccess && storage_shifted(s->p.precision)) e = launch_refs(s);
   if (e == hipSuccess) e = launch_init(s, rho, u, s->flags);
   int hflag = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream);
@@ -418,12 +444,19 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s) return fail(VLBM_ERR_ARG, "null sim");
   if (nsteps < 0) return fail(VLBM_ERR_ARG, "nsteps < 0");
-  const int rebase = s->p.rebase_every == 0 ? 10 : s->p.rebase_every;
+  const int rebase = rebase_period(s->p);
+  EventPool* ep = s->timing_on ? static_cast<EventPool*>(s->timing) : nullptr;
   for (int64_t k = 0; k < nsteps; ++k) {
+    if (ep) HIP_TRY(ep->begin(s->stream, 0));
     HIP_TRY(launch_step(s));
+    if (ep) HIP_TRY(ep->end(s->stream));
     s->buf ^= 1;
     s->t++;
-    if (rebase > 0 && storage_is_16(s->p.precision) && s->t % rebase == 0) HIP_TRY(launch_rebase(s));
+    if (rebase > 0 && storage_shifted(s->p.precision) && s->t % rebase == 0) {
+      if (ep) HIP_TRY(ep->begin(s->stream, 1));
+      HIP_TRY(launch_rebase(s));
+      if (ep) HIP_TRY(ep->end(s->stream));
+    }
     if (s->p.audit_every > 0 && s->t % s->p.audit_every == 0) {
       int rc = vlbm_audit_now(sh);
       if (rc) return rc;
@@ -432,15 +465,84 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
   return ok();
 }
 
+// Count of cell-steps whose fixed point hit its cap since the last report
+// (flags[2]); reset once read.  Synchronises the stream.
+static int take_step_unconverged(SimObj* s, int* count) {
+  HIP_TRY(hipMemcpyAsync(count, s->flags + 2, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (*count) HIP_TRY(hipMemsetAsync(s->flags + 2, 0, sizeof(int), s->stream));
+  return VLBM_OK;
+}
+
+int vlbm_sync(vlbm_sim sh) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  int n = 0;
+  const int rc = take_step_unconverged(s, &n);
+  if (rc) return rc;
+  if (n) return fail(VLBM_ERR_NOCONVERGE, "fixed point hit its cap in %d cell-steps", n);
+  return ok();
+}
+
+int vlbm_step_stats(vlbm_sim sh, int enable, uint64_t* out) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  if (out) {
+    unsigned long long h[4];
+    HIP_TRY(hipMemcpyAsync(h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemsetAsync(s->stats, 0, sizeof(h), s->stream));
+    for (int k = 0; k < 4; ++k) out[k] = h[k];
+  }
+  s->stats_on = enable ? 1 : 0;
+  return ok();
+}
+
+int vlbm_kernel_timing(vlbm_sim sh, int enable, double* out) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  if (!s->timing) {
+    s->timing = new (std::nothrow) EventPool();
+    if (!s->timing) return fail(VLBM_ERR_NOMEM, "host allocation failed");
+  }
+  EventPool* ep = static_cast<EventPool*>(s->timing);
+  if (out) {
+    for (int k = 0; k < 4; ++k) out[k] = 0.0;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t i = 0; i < ep->used; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ep->ev[2 * i], ep->ev[2 * i + 1]));
+      out[2 * ep->kind[i]] += ms;
+      out[2 * ep->kind[i] + 1] += 1.0;
+    }
+  }
+  if (out || !enable) ep->used = 0;
+  s->timing_on = enable ? 1 : 0;
+  return ok();
+}
+
+int vlbm_set_fixed_point(vlbm_sim sh, int32_t max_iter, double tol) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s) return fail(VLBM_ERR_ARG, "null sim");
+  s->p.fp_max_iter = max_iter > 0 ? max_iter : 50;
+  s->p.fp_tol = tol >= 0 ? tol : (s->p.precision == VLBM_FP64 ? 1e-14 : (s->p.precision == VLBM_FP32 ? 1e-10 : 1e-7));
+  return ok();
+}
+
 int vlbm_moments(vlbm_sim sh, double* rho, double* u, double* U) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s || !rho || !u) return fail(VLBM_ERR_ARG, "vlbm_moments: null argument");
+  int steps_unconv = 0;
+  int rc = take_step_unconverged(s, &steps_unconv);
+  if (rc) return rc;
   HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
   HIP_TRY(launch_moments(s, rho, u, U, s->flags));
   int hflag = 0;
   HIP_TRY(hipMemcpyAsync(&hflag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (hflag) return fail(VLBM_ERR_NOCONVERGE, "fixed point did not converge in %d cells", hflag);
+  if (steps_unconv)
+    return fail(VLBM_ERR_NOCONVERGE, "fixed point hit its cap in %d cell-steps of the steps taken", steps_unconv);
   return ok();
 }
 
@@ -482,10 +584,10 @@ int vlbm_audits(vlbm_sim sh, vlbm_audit* out, int cap, int* n_out) {
   return ok();
 }
 
-// 16-bit modes: the checkpoint also holds the writers' references (re-based
+// Shifted modes: the checkpoint also holds the slots' references (re-based
 // during the run, so they are part of the state).
 static size_t ref_bytes(const SimObj* s) {
-  return storage_is_16(s->p.precision) ? (size_t)s->mesh->box.ncells * s->mesh->Q * 2 : 0;
+  return storage_shifted(s->p.precision) ? (size_t)s->mesh->box.ncells * s->mesh->Q * 2 : 0;
 }
 
 int vlbm_save(vlbm_sim sh, void* buf, size_t cap, size_t* used) {
@@ -526,11 +628,9 @@ int vlbm_restore(vlbm_sim sh, const void* buf, size_t size) {
                     hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(s->fcache, static_cast<const char*>(buf) + sizeof(h) + s->pop_bytes, fbytes,
                     hipMemcpyHostToDevice));
-  if (rbytes) {   // the writers' references, then the readers' copies gathered from them
+  if (rbytes)
     HIP_TRY(hipMemcpy(s->rown, static_cast<const char*>(buf) + sizeof(h) + s->pop_bytes + fbytes, rbytes,
                       hipMemcpyHostToDevice));
-    HIP_TRY(launch_refs_src(s));
-  }
   s->t = h.t;
   s->have_u_prev = 0;
   return ok();
@@ -588,9 +688,22 @@ int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int co
     const int rc = create_sim(m, &params[i], nullptr, nullptr, b->stream, &s);
     if (rc) return bail(rc);
     b->members.push_back(s);
+    const int rb = storage_shifted(prec) ? rebase_period(s->p) : 0;
+    if (i == 0) {
+      b->rebase = rb > 0 ? rb : 0;
+    } else if ((rb > 0 ? rb : 0) != b->rebase) {
+      fail(VLBM_ERR_ARG, "member %d: every member needs the same re-basing period", i);
+      return bail(VLBM_ERR_ARG);
+    }
     b->total_cells += m->box.ncells;
     b->any_ff = b->any_ff || s->has_farfield;
     b->any_general = b->any_general || general_collision(s->p);
+  }
+  // graphs hold an even number of steps (parity) that is a multiple of the
+  // re-basing period, at least 32
+  if (b->rebase > 0) {
+    int gs = b->rebase % 2 ? 2 * b->rebase : b->rebase;
+    b->graph_steps = gs * ((32 + gs - 1) / gs);
   }
   b->active.assign(b->members.size(), 1);
   if (batch_upload(b) != hipSuccess) {
@@ -685,13 +798,17 @@ int vlbm_batch_config(vlbm_batch bh, int block, int grid_per_cu) {
   return ok();
 }
 
-static int batch_one_step_eager(BatchObj* b, int parity, bool per_member) {
+// One step of every active member; `t` is the members' step count before it.
+// The references are re-based after a step that reaches a multiple of the
+// re-basing period, as vlbm_step does for a single mesh.
+static int batch_one_step_eager(BatchObj* b, int parity, bool per_member, int64_t t) {
   if (!per_member) {
     HIP_TRY(batch_launch(b, parity));
   } else {
     for (size_t m = 0; m < b->members.size(); ++m)
       if (b->active[m]) HIP_TRY(launch_step(b->members[m]));
   }
+  if (b->rebase > 0 && (t + 1) % b->rebase == 0) HIP_TRY(batch_rebase(b, parity ^ 1));
   return VLBM_OK;
 }
 
@@ -725,6 +842,13 @@ int vlbm_batch_step(vlbm_batch bh, int64_t nsteps) {
   const bool graphs = b->mode == VLBM_BATCH_PERSISTENT_GRAPH || b->mode == VLBM_BATCH_EAGER_GRAPH;
   int64_t done = 0;
   if (graphs) {
+    // graphs start at a multiple of the re-basing period
+    while (b->rebase > 0 && done < nsteps && lead->t % b->rebase != 0) {
+      const int rc = batch_one_step_eager(b, lead->buf, per_member, lead->t);
+      if (rc) return rc;
+      batch_advance(b, 1);
+      ++done;
+    }
     while (nsteps - done >= b->graph_steps) {
       const int par = lead->buf;
       if (!b->exec[par]) {
@@ -737,7 +861,7 @@ int vlbm_batch_step(vlbm_batch bh, int64_t nsteps) {
     }
   }
   for (; done < nsteps; ++done) {
-    const int rc = batch_one_step_eager(b, lead->buf, per_member);
+    const int rc = batch_one_step_eager(b, lead->buf, per_member, lead->t);
     if (rc) return rc;
     batch_advance(b, 1);
   }
@@ -776,7 +900,8 @@ int vlbm_batch_sync(vlbm_batch bh) {
   int unconv = 0;
   for (SimObj* s : b->members) {
     int h = 0;
-    HIP_TRY(hipMemcpy(&h, s->flags, sizeof(int), hipMemcpyDeviceToHost));
+    const int rc = take_step_unconverged(s, &h);
+    if (rc) return rc;
     unconv += h;
   }
   if (unconv) return fail(VLBM_ERR_NOCONVERGE, "fixed point hit its cap in %d cell-steps", unconv);
@@ -822,14 +947,15 @@ int vlbm_batch_autotune(vlbm_batch bh, int trial_steps, const char* cache_path, 
   auto fc_bytes = [](const SimObj* s) {
     return s->fcache ? (size_t)s->mesh->box.ncells * s->mesh->d * fcache_elem(s->p.precision) : (size_t)0;
   };
+  auto rf_bytes = [](const SimObj* s) { return ref_bytes(s); };
   auto drop = [&]() {
     for (Snap& x : snap) dev_free(x.mem);
     snap.clear();
   };
   for (SimObj* s : b->members) {
     void* p = nullptr;
-    const size_t fb = fc_bytes(s);
-    if (dev_alloc((char**)&p, s->pop_bytes + fb)) {
+    const size_t fb = fc_bytes(s), rb = rf_bytes(s);
+    if (dev_alloc((char**)&p, s->pop_bytes + fb + rb)) {
       drop();
       return VLBM_ERR_NOMEM;
     }
@@ -837,6 +963,9 @@ int vlbm_batch_autotune(vlbm_batch bh, int trial_steps, const char* cache_path, 
     hipError_t e = hipMemcpyAsync(p, s->pop[s->buf], s->pop_bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess && fb)
       e = hipMemcpyAsync(static_cast<char*>(p) + s->pop_bytes, s->fcache, fb, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && rb)
+      e = hipMemcpyAsync(static_cast<char*>(p) + s->pop_bytes + fb, s->rown, rb, hipMemcpyDeviceToDevice,
+                         b->stream);
     if (e != hipSuccess) {
       drop();
       return fail(VLBM_ERR_DEVICE, "autotune snapshot: %s", hipGetErrorString(e));
@@ -875,12 +1004,15 @@ int vlbm_batch_autotune(vlbm_batch bh, int trial_steps, const char* cache_path, 
   (void)hipStreamSynchronize(b->stream);
   for (size_t i = 0; i < b->members.size(); ++i) {
     SimObj* s = b->members[i];
-    const size_t fb = fc_bytes(s);
+    const size_t fb = fc_bytes(s), rb = rf_bytes(s);
     s->buf = snap[i].buf;
     s->t = snap[i].t;
     hipError_t e = hipMemcpyAsync(s->pop[s->buf], snap[i].mem, s->pop_bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess && fb)
       e = hipMemcpyAsync(s->fcache, static_cast<char*>(snap[i].mem) + s->pop_bytes, fb, hipMemcpyDeviceToDevice,
+                         b->stream);
+    if (e == hipSuccess && rb)
+      e = hipMemcpyAsync(s->rown, static_cast<char*>(snap[i].mem) + s->pop_bytes + fb, rb, hipMemcpyDeviceToDevice,
                          b->stream);
     if (e != hipSuccess && !rc) rc = fail(VLBM_ERR_DEVICE, "autotune restore: %s", hipGetErrorString(e));
   }

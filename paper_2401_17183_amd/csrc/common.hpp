@@ -119,17 +119,32 @@ template <class L> using DirMask = typename std::conditional<(L::Q > 32), unsign
 inline int lattice_speed(int lattice) { return lattice == VLBM_D2Q21 || lattice == VLBM_D3Q39 ? 3 : 1; }
 
 // ---------------------------------------------------------------------------
-// Population storage codecs.  FP64/FP32 store N itself.  The 16-bit modes
-// store h = round16(s (N - R)), a scaled deviation from a per-link reference R:
-// the post-collision rest state of the cell that wrote the slot.  R is itself
-// held in the 16-bit type, so writer and reader add back the same value.
+// Population storage codecs, keyed by a storage tag P.  E is the stored element
+// type and R the type of the per-slot reference.  FP64 and plain FP32 (the tag
+// float) store N itself.  The shifted modes store a scaled deviation from a
+// reference held in the 16-bit type at the slot: h = s (N - R), with R the
+// post-collision state of the cell that wrote the slot, re-based on the state
+// every few steps.  Writer and reader add back the same R, so R only has to be
+// a representable number close to N:
+//   __half / __hip_bfloat16   16-bit deviations (FP32 arithmetic),
+//   F32Dev                    FP32 deviations from an FP16 reference, decoded
+//                             exactly into the (FP64) arithmetic type; the
+//                             rounding of the stored number is then relative
+//                             to N - R, not to N.
 // ---------------------------------------------------------------------------
+struct F32Dev {};
+
 template <class P> struct PopCodec {
+  using E = P;
+  using R = P;
   static constexpr bool shifted = false;
-  template <class T> __device__ __forceinline__ static T decode(P h, P, float) { return T(h); }
-  template <class T> __device__ __forceinline__ static P encode(T n, P, float) { return P(n); }
+  template <class T> __device__ __forceinline__ static T decode(E h, R, float) { return T(h); }
+  template <class T> __device__ __forceinline__ static E encode(T n, R, float) { return E(n); }
+  template <class T> __device__ __forceinline__ static R reference(T n) { return R(n); }
 };
 template <> struct PopCodec<__half> {
+  using E = __half;
+  using R = __half;
   static constexpr bool shifted = true;
   template <class T> __device__ __forceinline__ static T decode(__half h, __half r, float inv_s) {
     return T(__half2float(r)) + T(__half2float(h)) * T(inv_s);
@@ -137,8 +152,11 @@ template <> struct PopCodec<__half> {
   template <class T> __device__ __forceinline__ static __half encode(T n, __half r, float s) {
     return __float2half_rn(float((n - T(__half2float(r))) * T(s)));
   }
+  template <class T> __device__ __forceinline__ static R reference(T n) { return __float2half_rn(float(n)); }
 };
 template <> struct PopCodec<__hip_bfloat16> {
+  using E = __hip_bfloat16;
+  using R = __hip_bfloat16;
   static constexpr bool shifted = true;
   template <class T> __device__ __forceinline__ static T decode(__hip_bfloat16 h, __hip_bfloat16 r, float inv_s) {
     return T(__bfloat162float(r)) + T(__bfloat162float(h)) * T(inv_s);
@@ -146,7 +164,49 @@ template <> struct PopCodec<__hip_bfloat16> {
   template <class T> __device__ __forceinline__ static __hip_bfloat16 encode(T n, __hip_bfloat16 r, float s) {
     return __float2bfloat16(float((n - T(__bfloat162float(r))) * T(s)));
   }
+  template <class T> __device__ __forceinline__ static R reference(T n) { return __float2bfloat16(float(n)); }
 };
+template <> struct PopCodec<F32Dev> {
+  using E = float;
+  using R = __half;
+  static constexpr bool shifted = true;
+  // FP16 + FP32 -> FP64 is exact; the arithmetic type is FP64 for this storage
+  template <class T> __device__ __forceinline__ static T decode(float h, __half r, float) {
+    return T(__half2float(r)) + T(h);
+  }
+  template <class T> __device__ __forceinline__ static float encode(T n, __half r, float) {
+    return float(n - T(__half2float(r)));
+  }
+  // FP16's range ends at 65504: a population beyond it keeps the largest
+  // finite reference (the FP32 deviation carries the rest)
+  template <class T> __device__ __forceinline__ static R reference(T n) {
+    const float v = float(n);
+    return __float2half_rn(fminf(fmaxf(v, -65504.0f), 65504.0f));
+  }
+};
+template <class P> using PopE = typename PopCodec<P>::E;
+template <class P> using PopR = typename PopCodec<P>::R;
+
+// Re-basing of one cell's slots (shifted modes): every slot the cell wrote
+// takes its own rounding to the reference type as its new reference and is
+// re-encoded against it, so the stored deviations restart near zero.  Shared
+// by the single-mesh and the batched re-basing kernels, so both give the same
+// bits.
+template <class L, class P>
+__device__ __forceinline__ void rebase_cell(PopE<P>* __restrict__ pop, PopR<P>* __restrict__ rown, int nc, int cell,
+                                            float scale, float inv_scale) {
+  using C = PopCodec<P>;
+  using T = typename std::conditional<std::is_same<P, F32Dev>::value, double, float>::type;
+#pragma unroll
+  for (int al = 0; al < L::Q; ++al) {
+    const size_t i = (size_t)al * (size_t)nc + (size_t)cell;
+    const T n = C::template decode<T>(pop[i], rown[i], inv_scale);
+    const PopR<P> r = C::template reference<T>(n);
+    rown[i] = r;
+    pop[i] = C::template encode<T>(n, r, scale);
+  }
+}
+
 
 // Number of stored g^{ij} words (upper triangle) and its index map.
 template <int D> __host__ __device__ constexpr int nup() { return D * (D + 1) / 2; }
@@ -320,14 +380,21 @@ struct MeshObj {
   vlbm_geom_report report{};
 };
 
-// Geometry pack words for the step kernels (SoA, stride = ncells).
+// Geometry pack words for the step kernels (SoA, stride = ncells).  With FP32
+// words and FP64 arithmetic g^{ij} is held as a pair hi + lo of FP32 words
+// (hi = fl32(g), lo = fl32(g - hi), about 48 bits): g^{ij} sets the metric part
+// of the equilibrium stress, which balances the inertial force of a resting
+// fluid, and FP32 rounding of it alone acts as a spurious force (on slow flows
+// it dominates the FP32-storage error); J and A in FP32 are harmless.  The lo
+// words are read only by that combination (zero for FP64 words).
 template <class L> struct Pack {
   static constexpr int J = 0;
   static constexpr int GUP = 1;
   static constexpr int A = GUP + nup<L::D>();                 // A^i_a for a >= 1
   static constexpr int AEXT = A + (L::Q - 1) * L::D;          // present if force
   static constexpr int UINF = AEXT + L::D;                    // present if far field
-  static constexpr int WORDS = UINF + L::D;
+  static constexpr int GUPLO = UINF + L::D;                   // low words of g^{ij}
+  static constexpr int WORDS = GUPLO + nup<L::D>();
 };
 
 // The packed geometry is tiled by wavefronts: the words of 64 consecutive
@@ -363,10 +430,10 @@ struct SimObj {
   void* pop[2] = {nullptr, nullptr};
   size_t pop_bytes = 0;
   void* geo = nullptr;    // precision pack
-  void* rown = nullptr;     // 16-bit modes: [Q][cells] reference of the slot this cell writes
-  void* rsrc = nullptr;     // 16-bit modes: [Q][cells] reference of the slot this cell reads
+  void* rown = nullptr;     // shifted modes: [Q][cells] 16-bit reference of each slot (read by the slot's
+                            // writer and, at the same offset as the population, by its reader)
   void* fcache = nullptr;   // [d][cells]: converged inertial force of the last step (fixed-point start),
-                            // in the arithmetic type (FP64 except for FP32C)
+                            // FP64 with FP64 storage, FP32 otherwise
   int has_force = 0, has_farfield = 0;
   // audits
   void* audit_ring = nullptr;   // device vlbm_audit[cap]
@@ -376,7 +443,14 @@ struct SimObj {
   int audit_blocks = 0;
   double* u_prev = nullptr;     // device [d][cells]
   int have_u_prev = 0;
-  int* flags = nullptr;         // device int[4]: 0 = unconverged count, 1 = max iters
+  int* flags = nullptr;         // device int[4]: 0 = unconverged cells of a dry run (init, moments),
+                                //                2 = unconverged cell-steps of the step kernel
+  unsigned long long* stats = nullptr;   // device [4]: fixed-point statistics of the steps (when stats_on)
+  int stats_on = 0;
+  // kernel timing (vlbm_kernel_timing): event pairs around the step and the
+  // re-basing launches, resolved when read
+  int timing_on = 0;
+  void* timing = nullptr;   // host-side event pool (capi.hip)
 };
 
 // The general collision matrix is used when tau_g is set and differs from tau
@@ -385,15 +459,16 @@ inline int general_collision(const vlbm_params& p) { return p.tau_g != 0.0 && p.
 
 inline bool storage_is_fp64(int precision) { return precision == VLBM_FP64; }
 inline bool storage_is_16(int precision) { return precision == VLBM_FP16S || precision == VLBM_BF16S; }
+// modes whose slots hold deviations from a 16-bit per-slot reference
+inline bool storage_shifted(int precision) { return storage_is_16(precision) || precision == VLBM_FP32; }
 inline size_t pop_elem(int precision) {
   return precision == VLBM_FP64 ? 8 : (storage_is_16(precision) ? 2 : 4);
 }
-// scale s of the 16-bit deviations: FP16 needs it to keep small deviations
-// out of its subnormal range, BF16 shares FP32's exponent range
-// Scale of the stored FP16 deviations (N - reference) * scale.  FP16 keeps its
+// Scale s of the stored FP16 deviations (N - reference) * s.  FP16 keeps its
 // relative precision at any scale, but its range ends at 65504: deviations grow
 // with the cell volume J, so the scale is the largest power of two up to 4096
-// that keeps deviations up to 4 J_max representable.
+// that keeps deviations up to 4 J_max representable.  BF16 shares FP32's
+// exponent range and FP32 deviations need no scale.
 inline float pop_scale(int precision, double max_J) {
   if (precision != VLBM_FP16S) return 1.0f;
   const double jm = max_J > 1e-30 ? max_J : 1e-30;
@@ -402,9 +477,13 @@ inline float pop_scale(int precision, double max_J) {
   while (s > 1.0f / 1024.0f && s > cap) s *= 0.5f;
   return s;
 }
-inline size_t fcache_elem(int precision) {
-  return (precision == VLBM_FP32C || storage_is_16(precision)) ? 4 : 8;
-}
+// The force cache only seeds the fixed point (the converged F does not depend
+// on it): FP32 except with FP64 storage.
+inline size_t fcache_elem(int precision) { return precision == VLBM_FP64 ? 8 : 4; }
+// Re-basing period of the references (steps; vlbm_params.rebase_every: 0 =
+// default, < 0 = never).
+constexpr int kDefaultRebase = 10;
+inline int rebase_period(const vlbm_params& p) { return p.rebase_every == 0 ? kDefaultRebase : p.rebase_every; }
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial);
@@ -416,8 +495,7 @@ hipError_t launch_get_pop(SimObj* s, double* N);
 hipError_t launch_set_pop(SimObj* s, const double* N);
 hipError_t launch_audit(SimObj* s, int slot);
 hipError_t launch_refs(SimObj* s);
-hipError_t launch_rebase(SimObj* s);     // 16-bit modes: references re-based on the current state
-hipError_t launch_refs_src(SimObj* s);   // 16-bit modes: rsrc gathered again from rown
+hipError_t launch_rebase(SimObj* s);     // shifted modes: references re-based on the current state
 
 int geometry_partial_blocks(const MeshObj* m);
 

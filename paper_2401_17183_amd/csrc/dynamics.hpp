@@ -14,8 +14,11 @@ namespace vlbm {
 // link coefficients A live either in registers (STRIDE = 0) or in LDS, word
 // (a - 1) * D + i at lds[word * STRIDE] (STRIDE = threads per block).
 template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
+  // g^{ij} carries a low word when the words are narrower than the arithmetic
+  static constexpr bool LO = sizeof(AT) < sizeof(T);
   AT J;
   AT gup[nup<L::D>()];     // g^{ij}, upper triangle
+  AT gup_lo[LO ? nup<L::D>() : 1];   // g^{ij} - gup (FP32 words, FP64 arithmetic)
   AT aext[L::D];           // a_ext^i = G . g^i
   AT Areg[STRIDE ? 1 : L::Q][L::D];
   const AT* lds;
@@ -30,7 +33,8 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
 
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ T gval(const CellGeo<L, T, AT, ST>& g, int i, int j) {
-  return T(g.gup[up<L::D>(i, j)]);
+  if constexpr (CellGeo<L, T, AT, ST>::LO) return T(g.gup[up<L::D>(i, j)]) + T(g.gup_lo[up<L::D>(i, j)]);
+  else return T(g.gup[up<L::D>(i, j)]);
 }
 
 template <class V>
@@ -47,7 +51,10 @@ __device__ __forceinline__ void pin_scalars(CellGeo<L, T, AT, ST>& g, T& rho) {
   if constexpr (ST != 0) asm volatile("" : "+s"(g.lofs));   // wave-uniform: a scalar register
   pin(g.J);
 #pragma unroll
-  for (int k = 0; k < nup<L::D>(); ++k) pin(g.gup[k]);
+  for (int k = 0; k < nup<L::D>(); ++k) {
+    pin(g.gup[k]);
+    if constexpr (CellGeo<L, T, AT, ST>::LO) pin(g.gup_lo[k]);
+  }
 #pragma unroll
   for (int i = 0; i < L::D; ++i) pin(g.aext[i]);
   pin(rho);
@@ -602,6 +609,22 @@ __device__ __forceinline__ void collide_iterate(CellGeo<L, T, AT, ST>& gl, const
   st.iters = done ? it : max_iter + 1;
 }
 
+// Between phases 2 and 3: the equilibrium and the force part of dN take the
+// newest F (the output of the last iteration), and dPi stays that of the last
+// iteration.  The stopping rule bounds |F_k - F_(k-1)|; the distance of F_k
+// from the fixed point is smaller than that of F_(k-1) by the contraction
+// factor, so the output sits closer to the converged step for the same number
+// of iterations (any convergent solver reaches the same N').
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void collide_refresh(const CellGeo<L, T, AT, ST>& g, const T* F, CollState<L, T, AT>& st) {
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    st.Ft[i] = F[i] + st.rho * g.ae(i);
+    st.Ut[i] = st.U[i] + st.Ft[i] * st.half_inv_rho;
+  }
+  st.e = eq_coef<L, T, AT, ST>(g, st.rho, st.U, st.Ut);
+}
+
 // Phase 3: N' of the last iteration (eqs. (lbe), (collide), (deltaN)); for a
 // general M the population part c1 S2 / J of the stress term joins dPi here.
 template <class L, class T, class AT, int ST, class NS>
@@ -630,6 +653,7 @@ __device__ __forceinline__ CollideOut collide(CellGeo<L, T, AT, ST>& g, const NS
   CollState<L, T, AT> st;
   collide_prepare<L, T, AT, ST, NS>(g, N, r, st);
   collide_iterate<L, T, AT, ST>(g, r, tol, max_iter, F, st);
+  collide_refresh<L, T, AT, ST>(g, F, st);
   collide_output<L, T, AT, ST, NS>(g, N, r, st, Np);
 #pragma unroll
   for (int i = 0; i < L::D; ++i) {

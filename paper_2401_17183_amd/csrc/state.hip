@@ -10,6 +10,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kAuditWords = 13;
 
+// S: population storage tag (PopCodec).
 template <class S> struct StateArgs {
   Box box;
   const double* J;
@@ -20,10 +21,9 @@ template <class S> struct StateArgs {
   double G[3], uinf[3];
   double rho_inf, tau, tau_g, tol;
   int general, max_iter;
-  const S* in;         // populations to gather from (N'(t-1))
-  S* out;              // populations to scatter into
-  const S* rsrc;       // 16-bit modes: reference of each arriving link
-  S* rown;             // 16-bit modes: reference of each written slot
+  const PopE<S>* in;   // populations to gather from (N'(t-1))
+  PopE<S>* out;        // populations to scatter into
+  PopR<S>* rown;       // shifted modes: reference of each slot (same layout as the populations)
   float scale, inv_scale;
   const double* rho_in;
   const double* u_in;
@@ -85,8 +85,8 @@ __device__ inline void gather64(const StateArgs<S>& a, const CellGeo<L, double>&
     int src;
     const int kind = link_source<L>(a.box, al, x, y, z, src);
     const int dir = kind == LINK_INTERIOR ? al : opp(al);
-    N[al] = PopCodec<S>::template decode<double>(a.in[dir * nc + src], a.rsrc ? a.rsrc[al * nc + cell] : S(0),
-                                                 a.inv_scale);
+    const long i = dir * nc + src;
+    N[al] = PopCodec<S>::template decode<double>(a.in[i], a.rown ? a.rown[i] : PopR<S>(0), a.inv_scale);
     if (kind == LINK_WALL) wallmask |= DirMask<L>(1) << al;
     if (kind == LINK_FARFIELD) ff |= DirMask<L>(1) << al;
   }
@@ -109,9 +109,8 @@ __device__ inline void unstream_store(const StateArgs<S>& a, int cell, int x, in
     const int kind = link_source<L>(a.box, al, x, y, z, src);
     if (kind == LINK_FARFIELD) continue;
     const int dir = kind == LINK_INTERIOR ? al : opp(al);
-    // the reader's reference is the writer's: rsrc of the arriving link
-    a.out[dir * nc + src] =
-        PopCodec<S>::template encode<double>(N[al], a.rsrc ? a.rsrc[al * nc + cell] : S(0), a.scale);
+    const long i = dir * nc + src;
+    a.out[i] = PopCodec<S>::template encode<double>(N[al], a.rown ? a.rown[i] : PopR<S>(0), a.scale);
   }
 }
 
@@ -171,9 +170,9 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(StateArgs<S> a) {
   for (int al = 0; al < L::Q; ++al) a.N_out[al * nc + cell] = N[al];
 }
 
-// 16-bit storage references: the post-collision rest state of every cell
+// Shifted-storage references: the post-collision rest state of every cell
 // (rest consistent equilibrium, rho = 1, u = 0, then one collision), rounded to
-// the storage type, is the reference of the slots the cell writes (rown).
+// the reference type, is the first reference of the slots the cell writes.
 template <class L, class S>
 __global__ __launch_bounds__(kBlock) void k_refs_own(StateArgs<S> a) {
   constexpr int D = L::D;
@@ -190,43 +189,16 @@ __global__ __launch_bounds__(kBlock) void k_refs_own(StateArgs<S> a) {
   const CollideOut o = collide<L, double, double, 0, double>(g, N, make_relax<double>(a.tau, a.tau_g, a.general), a.tol,
                                                          a.max_iter, Np, F, Ut, U, rho);
   if (o.iters > a.max_iter) atomicAdd(a.flag, 1);
-  for (int al = 0; al < L::Q; ++al) a.rown[al * nc + cell] = S(Np[al]);
+  for (int al = 0; al < L::Q; ++al) a.rown[al * nc + cell] = PopCodec<S>::template reference<double>(Np[al]);
 }
 
-// Re-basing of the 16-bit references on the current state: every slot the cell
-// wrote (its post-collision N'_a, encoded against rown[a]) takes its own
-// 16-bit rounding as the new reference and is re-encoded against it, so the
-// stored deviations restart near zero and FP16/BF16 keep their relative
-// precision on a small number.  k_refs_src then refreshes rsrc.
+// Re-basing of the references on the current state (rebase_cell): the
+// reader decodes at the offset it gathers from, so nothing else changes.
 template <class L, class S>
 __global__ __launch_bounds__(kBlock) void k_rebase(StateArgs<S> a) {
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   if (cell >= a.box.ncells) return;
-  const long nc = a.box.ncells;
-  for (int al = 0; al < L::Q; ++al) {
-    const long i = al * nc + cell;
-    const double n = PopCodec<S>::template decode<double>(a.in[i], a.rown[i], a.inv_scale);
-    const S r = S(n);
-    a.rown[i] = r;
-    a.out[i] = PopCodec<S>::template encode<double>(n, r, a.scale);
-  }
-}
-
-// ... and, gathered along the links, the reference of each arriving link (rsrc).
-template <class L, class S>
-__global__ __launch_bounds__(kBlock) void k_refs_src(StateArgs<S> a) {
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
-  if (cell >= a.box.ncells) return;
-  const long nc = a.box.ncells;
-  int x, y, z;
-  cell_xyz(a.box, cell, x, y, z);
-  S* rsrc = const_cast<S*>(a.rsrc);
-  for (int al = 0; al < L::Q; ++al) {
-    int src;
-    const int kind = link_source<L>(a.box, al, x, y, z, src);
-    const int dir = kind == LINK_INTERIOR ? al : opp(al);
-    rsrc[al * nc + cell] = a.rown[dir * nc + src];
-  }
+  rebase_cell<L, S>(const_cast<PopE<S>*>(a.in), a.rown, a.box.ncells, cell, a.scale, a.inv_scale);
 }
 
 // Output mapping: rho, u = Ut^i g_i (Euclidean), U^i (eq. (result) and the
@@ -423,10 +395,9 @@ StateArgs<S> make_args(SimObj* s) {
   // the FP64 dry run converges to FP64 roundoff whatever the storage precision
   a.tol = fmin(s->p.fp_tol, 1e-13);
   a.max_iter = s->p.fp_max_iter;
-  a.in = static_cast<const S*>(s->pop[s->buf]);
-  a.out = static_cast<S*>(s->pop[s->buf]);
-  a.rsrc = static_cast<const S*>(s->rsrc);
-  a.rown = static_cast<S*>(s->rown);
+  a.in = static_cast<const PopE<S>*>(s->pop[s->buf]);
+  a.out = static_cast<PopE<S>*>(s->pop[s->buf]);
+  a.rown = static_cast<PopR<S>*>(s->rown);
   a.scale = pop_scale(s->p.precision, s->mesh->report.max_J);
   a.inv_scale = 1.0f / a.scale;
   a.flag = s->flags;
@@ -463,16 +434,9 @@ hipError_t dispatch(SimObj* s, int what, const double* r_in, const double* u_in,
       break;
     case 5:
       k_refs_own<L, S><<<nb, kBlock, 0, st>>>(a);
-      if (hipGetLastError() != hipSuccess) break;
-      k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
       break;
     case 6:
       k_rebase<L, S><<<nb, kBlock, 0, st>>>(a);
-      if (hipGetLastError() != hipSuccess) break;
-      k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
-      break;
-    case 7:
-      k_refs_src<L, S><<<nb, kBlock, 0, st>>>(a);
       break;
     case 4: {
       a.u_prev = s->u_prev;
@@ -506,6 +470,7 @@ hipError_t dispatch_lattice(SimObj* s, int what, const double* r_in, const doubl
         return dispatch<L, __hip_bfloat16>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
       else
         return hipErrorInvalidValue;
+    case VLBM_FP32: return dispatch<L, F32Dev>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
     default: return dispatch<L, float>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
   }
 }
@@ -540,12 +505,8 @@ hipError_t launch_set_pop(SimObj* s, const double* N) {
 hipError_t launch_refs(SimObj* s) {
   return dispatch_any(s, 5, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
-hipError_t launch_refs_src(SimObj* s) {
-  if (!storage_is_16(s->p.precision)) return hipSuccess;
-  return dispatch_any(s, 7, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
-}
 hipError_t launch_rebase(SimObj* s) {
-  if (!storage_is_16(s->p.precision)) return hipSuccess;
+  if (!storage_shifted(s->p.precision)) return hipSuccess;
   return dispatch_any(s, 6, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 hipError_t launch_audit(SimObj* s, int slot) {

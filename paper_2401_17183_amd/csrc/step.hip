@@ -43,7 +43,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
   const long nc = box.ncells;
   geo[pack_index<L>(Pack<L>::J, cell)] = S(J[cell]);
   for (int i = 0; i < D; ++i)
-    for (int j = i; j < D; ++j) geo[pack_index<L>(Pack<L>::GUP + up<D>(i, j), cell)] = S(gup[(i * D + j) * nc + cell]);
+    for (int j = i; j < D; ++j) {
+      const double v = gup[(i * D + j) * nc + cell];
+      const S hi = S(v);
+      geo[pack_index<L>(Pack<L>::GUP + up<D>(i, j), cell)] = hi;
+      geo[pack_index<L>(Pack<L>::GUPLO + up<D>(i, j), cell)] = S(v - double(hi));
+    }
   for (int al = 1; al < L::Q; ++al)
     for (int i = 0; i < D; ++i) geo[pack_index<L>(Pack<L>::A + (al - 1) * D + i, cell)] = S(A[(al * D + i) * nc + cell]);
   const double G[3] = {G0, G1, G2};
@@ -102,7 +107,7 @@ template <class L>
 hipError_t step_lattice(SimObj* s) {
   switch (s->p.precision) {
     case VLBM_FP64: return step_typed<L, double, double, double>(s);
-    case VLBM_FP32: return step_typed<L, float, float, double>(s);
+    case VLBM_FP32: return step_typed<L, F32Dev, float, double>(s);
     case VLBM_FP16S:
       if constexpr (L::SPEED == 1) return step_typed<L, __half, float, float>(s);
       else return hipErrorInvalidValue;   // rejected at init

@@ -18,13 +18,14 @@ namespace vlbm {
 #define VLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 8)))
 #endif
 
-// P: population storage type; S: geometry storage type; T: arithmetic type.
+// P: population storage tag (PopCodec); S: geometry storage type; T: arithmetic type.
 template <class P, class S, class T> struct StepArgs {
   Box box;
-  const P* __restrict__ in;
-  P* __restrict__ out;
-  const P* __restrict__ rsrc;   // 16-bit modes: reference of each arriving link
-  const P* __restrict__ rown;   // 16-bit modes: reference of each written slot
+  const PopE<P>* __restrict__ in;
+  PopE<P>* __restrict__ out;
+  // shifted modes: the reference of every slot, [Q][cells]; the writer encodes
+  // against its own slots, the reader decodes at the offset it gathers from
+  const PopR<P>* __restrict__ rown;
   float scale, inv_scale;
   const S* __restrict__ geo;
   T tau, tau_g, tol, rho_inf;
@@ -32,9 +33,37 @@ template <class P, class S, class T> struct StepArgs {
   int max_iter, min_iter;
   int stream_only;
   int has_force, has_ff;
-  T* __restrict__ fcache;       // [D][cells] starting guess in, converged F out
+  // [D][cells] starting guess in, converged F out: FP64 with FP64 storage,
+  // FP32 otherwise (a starting guess only)
+  typename std::conditional<std::is_same<S, double>::value, double, float>::type* __restrict__ fcache;
   int* flags;
+  // optional fixed-point statistics (null: off): [0] sum over cells of the
+  // iterations, [1] sum over wavefronts of their largest count (the lanes of a
+  // wavefront iterate together), [2] cells, [3] wavefronts
+  unsigned long long* stats;
 };
+
+// Wavefront sum and maximum of the per-lane iteration counts, from ballots
+// (which only see the active lanes: a ragged last wavefront has lanes that
+// left early), added by the first active lane to the statistics.
+__device__ __forceinline__ void add_iteration_stats(unsigned long long* stats, int iters) {
+  const unsigned long long act = __ballot(1);
+  unsigned long long sum = 0;
+  int mx = 0;
+  for (int k = 1;; ++k) {   // wave-uniform: ends at the largest count
+    const unsigned long long m = __ballot(iters >= k);
+    if (m == 0ull) break;
+    sum += (unsigned long long)__popcll(m);
+    mx = k;
+  }
+  const int lane = (int)(threadIdx.x & 63);
+  if (lane == __ffsll((long long)act) - 1) {
+    atomicAdd(&stats[0], sum);
+    atomicAdd(&stats[1], (unsigned long long)mx);
+    atomicAdd(&stats[2], (unsigned long long)__popcll(act));
+    atomicAdd(&stats[3], 1ull);
+  }
+}
 
 // Word w of a SoA array: the wave-uniform base (w * nc) is formed in scalar
 // registers, lanes carry only their 32-bit cell offset.
@@ -58,7 +87,10 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
   const S* __restrict__ gw = geo + pack_index<L>(0, cell);
   g.J = gw[Pack<L>::J * kGeoTile];
 #pragma unroll
-  for (int k = 0; k < nup<L::D>(); ++k) g.gup[k] = gw[(Pack<L>::GUP + k) * kGeoTile];
+  for (int k = 0; k < nup<L::D>(); ++k) {
+    g.gup[k] = gw[(Pack<L>::GUP + k) * kGeoTile];
+    if constexpr (CellGeo<L, T, S, ST>::LO) g.gup_lo[k] = gw[(Pack<L>::GUPLO + k) * kGeoTile];
+  }
 #pragma unroll
   for (int a = 1; a < L::Q; ++a)
 #pragma unroll
@@ -94,8 +126,9 @@ __device__ __forceinline__ void gather_dirs(const StepArgs<P, S, T>& a, const Li
     // wave-uniform and the offset (< 2 nc <= 2^31) a 32-bit lane value
     constexpr int lo = opp(al) < al ? opp(al) : al;
     const unsigned e = (unsigned)src + (unsigned)nc * (kind == LINK_INTERIOR ? unsigned(al - lo) : unsigned(opp(al) - lo));
-    const P h = word(a.in, lo, nc)[e];
-    if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rsrc, al, nc)[cell], a.inv_scale);
+    const PopE<P> h = word(a.in, lo, nc)[e];
+    // the slot's reference sits at the same offset of the reference array
+    if constexpr (C::shifted) N[al] = C::template decode<NR>(h, word(a.rown, lo, nc)[e], a.inv_scale);
     else N[al] = h;
     ff |= DirMask<L>(kind == LINK_FARFIELD ? 1 : 0) << al;
     gather_dirs<L, P, S, T, NR, al + 1>(a, plan, x, y, z, cell, N, ff);
@@ -137,7 +170,7 @@ __device__ __forceinline__ void store_slot(const StepArgs<P, S, T>& a, int al, i
   using C = PopCodec<P>;
   const int nc = a.box.ncells;
   if constexpr (C::shifted) word(a.out, al, nc)[cell] = C::template encode<T>(T(v), word(a.rown, al, nc)[cell], a.scale);
-  else word(a.out, al, nc)[cell] = P(v);
+  else word(a.out, al, nc)[cell] = PopE<P>(v);
 }
 
 // One cell of one mesh; BLOCK threads per workgroup share the LDS staging.
@@ -147,8 +180,9 @@ template <class L, class P, class S, class T, int BLOCK, int FF = 2, bool GEN = 
 __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
-  // registers hold populations in the storage type, or FP32 for 16-bit storage
-  using NR = typename std::conditional<PopCodec<P>::shifted, float, P>::type;
+  // registers hold populations in the storage type, decoded deviations in the
+  // arithmetic type (FP32 for 16-bit storage, FP64 for FP32 deviations)
+  using NR = typename std::conditional<PopCodec<P>::shifted, T, PopE<P>>::type;
   if (cell >= a.box.ncells) return;
   const int nc = a.box.ncells;
   int x, y, z;
@@ -173,15 +207,18 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   collide_prepare<L, T, S, ST, NR>(g, N, rx, st);
   collide_iterate<L, T, S, ST>(g, rx, a.tol, a.max_iter, F, st, a.min_iter);
   if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
+  if (a.stats) add_iteration_stats(a.stats, st.iters);   // wave-uniform
+  collide_refresh<L, T, S, ST>(g, F, st);
 #pragma unroll
   for (int i = 0; i < D; ++i) word(a.fcache, i, nc)[cell] = F[i];
   // gather again (cache hits) rather than keeping N live across the fixed point
-  // where registers are short: the general collision variant with FP64
-  // arithmetic.  Decoded 16-bit populations stay in registers (their re-gather
-  // would also re-read and re-apply the link references), and so do the
-  // populations of the BGK variants (FP64 ones in accumulation registers: that
-  // kernel runs one wave per SIMD either way).
-  constexpr bool regather = !PopCodec<P>::shifted && sizeof(T) == 8 && GEN;
+  // where registers are short: FP32 deviations (decoded into FP64 registers;
+  // they re-read their references with them) and the general collision
+  // variant with FP64 arithmetic.  Decoded 16-bit populations stay in
+  // registers, and so do the populations of the other BGK variants (FP64 ones
+  // in accumulation registers: that kernel runs one wave per SIMD either way).
+  constexpr bool regather =
+      std::is_same<P, F32Dev>::value || (!PopCodec<P>::shifted && sizeof(T) == 8 && GEN);
   if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
     // here instead of being kept (or spilled) across the fixed point
@@ -196,7 +233,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   if constexpr (PopCodec<P>::shifted) {
     // the references of the written slots are loaded before the output
     // arithmetic, so their latency hides behind it
-    P ref[Q];
+    PopR<P> ref[Q];
 #pragma unroll
     for (int al = 0; al < Q; ++al) ref[al] = word(a.rown, al, nc)[cell];
     collide_output<L, T, S, ST, NR>(g, N, rx, st, Np);
@@ -215,10 +252,9 @@ template <class P, class S, class T>
 inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   StepArgs<P, S, T> a;
   a.box = s->mesh->box;
-  a.in = static_cast<const P*>(s->pop[s->buf]);
-  a.out = static_cast<P*>(s->pop[s->buf ^ 1]);
-  a.rsrc = static_cast<const P*>(s->rsrc);
-  a.rown = static_cast<const P*>(s->rown);
+  a.in = static_cast<const PopE<P>*>(s->pop[s->buf]);
+  a.out = static_cast<PopE<P>*>(s->pop[s->buf ^ 1]);
+  a.rown = static_cast<const PopR<P>*>(s->rown);
   a.scale = pop_scale(s->p.precision, s->mesh->report.max_J);
   a.inv_scale = 1.0f / a.scale;
   a.geo = static_cast<const S*>(s->geo);
@@ -234,8 +270,9 @@ inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   a.stream_only = s->p.stream_only;
   a.has_force = s->has_force;
   a.has_ff = s->has_farfield;
-  a.flags = s->flags;
-  a.fcache = static_cast<T*>(s->fcache);
+  a.flags = s->flags + 2;   // the step kernel's own count of unconverged cell-steps
+  a.stats = s->stats_on ? s->stats : nullptr;
+  a.fcache = static_cast<decltype(a.fcache)>(s->fcache);
   return a;
 }
 

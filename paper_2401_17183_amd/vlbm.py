@@ -93,6 +93,12 @@ _SIGS = {
     "vlbm_geometry_fields": (C.c_int, [_P, _P, _P, _P, _P]),
     "vlbm_init": (C.c_int, [_P, C.POINTER(vlbm_params), _P, _P, _P, C.POINTER(_P)]),
     "vlbm_step": (C.c_int, [_P, C.c_int64]),
+    "vlbm_sync": (C.c_int, [_P]),
+    "vlbm_step_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_uint64)]),
+    "vlbm_kernel_timing": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
+    "vlbm_membench": (C.c_int, [C.c_int, C.c_int, C.c_size_t, C.c_int, _P, C.POINTER(C.c_double),
+                                C.POINTER(C.c_int)]),
+    "vlbm_set_fixed_point": (C.c_int, [_P, C.c_int32, C.c_double]),
     "vlbm_moments": (C.c_int, [_P, _P, _P, _P]),
     "vlbm_populations": (C.c_int, [_P, _P]),
     "vlbm_set_populations": (C.c_int, [_P, _P]),
@@ -295,6 +301,34 @@ class Sim:
     def step(self, n=1):
         vlbm_step(self.h, int(n))
 
+    def sync(self):
+        """Wait for the enqueued steps; raises VlbmError(ERR_NOCONVERGE) when a
+        step since the last report hit the fixed point's cap."""
+        vlbm_sync(self.h)
+
+    def kernel_timing(self, enable=False):
+        """Kernel durations recorded since the last read (then cleared), and
+        turn the recording on or off for the following steps:
+        {step_ms, step_launches, rebase_ms, rebase_launches}."""
+        out = (C.c_double * 4)()
+        vlbm_kernel_timing(self.h, int(bool(enable)), out)
+        return {"step_ms": out[0], "step_launches": int(out[1]), "rebase_ms": out[2],
+                "rebase_launches": int(out[3])}
+
+    def set_fixed_point(self, max_iter=0, tol=-1.0):
+        vlbm_set_fixed_point(self.h, int(max_iter), float(tol))
+
+    def step_stats(self, enable=False):
+        """Fixed-point statistics since the last read (then reset), and turn
+        their collection on or off for the following steps:
+        {iters_per_cell, wave_max_iters, cell_steps, wave_steps}."""
+        out = (C.c_uint64 * 4)()
+        vlbm_step_stats(self.h, int(bool(enable)), out)
+        cells, waves = int(out[2]), int(out[3])
+        return {"iters_per_cell": out[0] / cells if cells else float("nan"),
+                "wave_max_iters": out[1] / waves if waves else float("nan"),
+                "cell_steps": cells, "wave_steps": waves}
+
     @property
     def t(self):
         v = C.c_int64()
@@ -450,6 +484,17 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def membench(kind, nontemporal=False, bytes_=2 << 30, reps=10):
+    """Best STREAM-style bandwidth in GB/s (kind "read", "write" or "copy")
+    and the grid of that launch, on torch's current stream."""
+    torch = _torch()
+    k = {"read": 0, "write": 1, "copy": 2}[kind]
+    g = C.c_double()
+    grid = C.c_int()
+    vlbm_membench(k, int(bool(nontemporal)), int(bytes_), int(reps), _stream_ptr(torch), C.byref(g), C.byref(grid))
+    return g.value, grid.value
 
 
 def _ptr(t):

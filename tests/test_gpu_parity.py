@@ -183,23 +183,85 @@ def test_fp64_step_parity(w, steps):
     assert np.allclose(cpu(mo["u"]), om["u"].reshape(d, -1), rtol=0, atol=1e-11)
 
 
-@pytest.mark.parametrize("precision,bound", [("fp32", 1e-5), ("fp32c", 1e-3)])
-def test_fp32_velocity_parity(precision, bound):
-    """FP32 storage: velocity relative L2 error vs the FP64 oracle after 200 steps
-    on a stretched channel; <= 1e-5 with FP64 arithmetic (fp32), and the
-    FP32-arithmetic variant (fp32c) stated at its measured level."""
-    w = W.tanh_channel_3d(32, 24, 16, strength=1.5, tau=0.6, G=1e-5)
-    announce(f"{precision} parity tanh(1.5) channel 32x24x16 x200")
-    os_ = sim_of(w)
-    os_.init(w["rho"], w["u"])
+_ORACLE_U = {}
+
+
+def _oracle_u(w, steps):
+    """The oracle's Euclidean velocity after `steps` steps (kept per workload
+    name, so several GPU modes compare with one oracle run)."""
+    key = (w["name"], steps)
+    if key not in _ORACLE_U:
+        os_ = sim_of(w)
+        os_.init(w["rho"], w["u"])
+        os_.step(steps)
+        _ORACLE_U[key] = os_.moments()["u"].reshape(os_.mesh.d, -1)
+    return _ORACLE_U[key]
+
+
+# FP32 storage holds deviations from 16-bit per-slot references (re-based every
+# 10 steps) with FP64 arithmetic: the bar is velocity relative L2 <= 1e-5
+FP32_CASES = [
+    # the channel workload's own stretch, relaxation time, body force and noise
+    # (tanh(2.5), tau = 0.52, G = 1e-6, 1e-3 noise) on a 16x32x8 replica: the
+    # same 32 wall-normal cells as the 64x32x32 replica of the stored-oracle test
+    (W.tanh_channel_3d(16, 32, 8), 200),
+    # a milder channel with a stronger body force
+    (W.tanh_channel_3d(32, 24, 16, strength=1.5, tau=0.6, G=1e-5), 200),
+]
+
+
+@pytest.mark.parametrize("w,steps", FP32_CASES, ids=lambda x: str(x) if isinstance(x, int) else x["name"])
+def test_fp32_velocity_parity(w, steps):
+    """FP32 storage: velocity relative L2 error vs the FP64 oracle <= 1e-5
+    after `steps` steps on stretched channels."""
+    announce(f"fp32 parity {w['name']} x{steps}")
+    s, m = gpu_sim(w, precision="fp32", rho=w["rho"].ravel(), u=w["u"].reshape(3, -1))
+    s.step(steps)
+    u_g = cpu(s.moments()["u"])
+    u_o = _oracle_u(w, steps)
+    rel = np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o)
+    print("fp32 velocity rel L2", rel)
+    assert rel <= 1e-5, rel
+
+
+def test_fp32_parity_channel_replica_against_stored_oracle():
+    """The 64x32x32 replica of the channel workload (tanh(2.5), tau = 0.52,
+    G = 1e-6, seeded 1e-3 noise) in FP32 storage, 1000 steps; the FP64
+    oracle's velocity after 200 and 1000 steps on every fourth x column
+    (tests/golden/make_channel_replica.py) against the GPU's: relative L2
+    <= 1e-5 at both."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "channel_replica_64x32x32.npz")
+    ref = np.load(path)
+    w = W.tanh_channel_3d(64, 32, 32)
+    announce("fp32 channel replica 64x32x32 x1000 vs stored oracle")
+    s, m = gpu_sim(w, precision="fp32", rho=w["rho"].ravel(), u=w["u"].reshape(3, -1))
+    n1, n2, n3 = w["n"]
+    done = 0
+    for k in ref["steps"]:
+        s.step(int(k) - done)
+        done = int(k)
+        u = cpu(s.moments()["u"]).reshape(3, n3, n2, n1)[..., ref["xcols"]]
+        want = ref[f"u_{k}"].astype(np.float64)
+        rel = np.linalg.norm(u - want) / np.linalg.norm(want)
+        print(f"step {k}: fp32 velocity rel L2 {rel:.3e}")
+        assert rel <= 1e-5, (k, rel)
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp16s", "bf16s"])
+def test_fp32_arithmetic_modes_on_channel_replica(precision):
+    """FP32-arithmetic modes on the channel replica of the FP32 test (200
+    steps): they run and stay finite; their velocity error against the oracle
+    is printed (a measured figure, not a bar: FP32 arithmetic on absolute
+    populations resolves velocities of ~1e-4 only to ~1e-2 here)."""
+    w = FP32_CASES[0][0]
+    announce(f"{precision} on {w['name']} x200 (measured)")
     s, m = gpu_sim(w, precision=precision, rho=w["rho"].ravel(), u=w["u"].reshape(3, -1))
     s.step(200)
-    os_.step(200)
     u_g = cpu(s.moments()["u"])
-    u_o = os_.moments()["u"].reshape(3, -1)
-    rel = np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o)
-    print(precision, "velocity rel L2", rel)
-    assert rel <= bound, rel
+    assert np.isfinite(u_g).all()
+    u_o = _oracle_u(w, 200)
+    print(precision, "velocity rel L2 (measured)", np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o))
 
 
 def test_audits_match_oracle_and_balance():
@@ -305,6 +367,23 @@ def test_error_paths():
     with pytest.raises(v.VlbmError) as e:
         v.Sim(m, v.make_params(0.8, fp_max_iter=1, fp_tol=0.0))
     assert e.value.code == v.ERR_NOCONVERGE
+    # forced non-convergence inside the steps: the step kernel's count is
+    # reported by the next sync (and then reset) and by moments
+    s = v.Sim(m, v.make_params(0.8), u=0.01 * np.ones((2, m.ncells)))
+    s.set_fixed_point(1, 0.0)
+    s.step(3)
+    with pytest.raises(v.VlbmError) as e:
+        s.sync()
+    assert e.value.code == v.ERR_NOCONVERGE and "cell-steps" in str(e.value)
+    s.sync()
+    s.step(2)
+    with pytest.raises(v.VlbmError) as e:
+        s.moments()
+    assert e.value.code == v.ERR_NOCONVERGE
+    s.set_fixed_point()
+    s.step(2)
+    s.sync()
+    s.moments()
     # a NaN written from the host is flagged by the audit
     s = v.Sim(m, v.make_params(0.8))
     N = s.populations()
@@ -483,6 +562,45 @@ def test_fp16s_range_follows_cell_volume():
     ratio = float(((b - a).abs() / bound).max())
     print("fp16s round trip worst error / FP16 bound", ratio)
     assert ratio <= 1.0, ratio
+
+
+@pytest.mark.parametrize("precision,bound", [("fp32", 1e-5), ("fp16s", 1e-3), ("bf16s", None)])
+def test_ogrid_precision_study_against_stored_oracle(precision, bound):
+    """Storage precisions on the O-grid, against the FP64 oracle: a radially
+    faithful 256x128x2 replica of the 256x512x64 O-grid workload (the same
+    radii from the cylinder wall at r = 1 to the far field at r = 20, the same
+    dx, Re = 100 inflow, fewer cells around and along the axis), 200 steps
+    from the far-field flow.  The oracle's velocity after 50, 100 and 200
+    steps on every fourth theta row (tests/golden/make_ogrid_replica.py)
+    against the GPU's: relative L2 <= 1e-5 for FP32 storage and <= 1e-3 for
+    FP16 storage; BF16 storage is reported as measured.  The FP64-audited mass
+    drift of each run is printed (16-bit rounding breaks exact conservation)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ogrid_replica_256x128x2.npz")
+    ref = np.load(path)
+    w = W.ogrid_3d(256, 128, 2)
+    n1, n2, n3 = w["n"]
+    nc = n1 * n2 * n3
+    announce(f"O-grid replica 256x128x2 {precision} x200 vs stored oracle")
+    u0 = np.zeros((3, nc))
+    u0[0] = w["u_inf"][0]
+    s, m = gpu_sim(w, precision=precision, rho=np.ones(nc), u=u0)
+    s.audit_now()
+    done = 0
+    for k in ref["steps"]:
+        s.step(int(k) - done)
+        done = int(k)
+        u = cpu(s.moments()["u"]).reshape(3, n3, n2, n1)[:, :, ref["rows"], :]
+        want = ref[f"u_{k}"].astype(np.float64)
+        assert np.isfinite(u).all(), k
+        rel = np.linalg.norm(u - want) / np.linalg.norm(want)
+        print(f"O-grid {precision} step {k}: velocity rel L2 {rel:.3e}")
+        if bound is not None:
+            assert rel <= bound, (k, rel)
+    s.audit_now()
+    a0, a1 = s.audits()
+    print(f"O-grid {precision}: mass drift {a1['mass'] / a0['mass'] - 1:.3e}")
+    assert a1["nonfinite"] == 0
 
 
 def test_ogrid_16bit_storage_against_fp32():
