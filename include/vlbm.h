@@ -124,6 +124,22 @@ typedef struct {
  * J <= 0 (reorder axes for a positive handedness), VLBM_ERR_DEVICE. */
 int vlbm_geometry_precompute(vlbm_mesh m, void* stream, vlbm_geom_report* rep);
 
+/* vlbm_geometry_precompute for callers that cannot allocate device memory
+ * (code in tight loops that re-derive the geometry, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bit for bit, with all
+ * scratch (degenerate-cell flag, per-block diagnostics, the g_i box) in a
+ * static device array of 32 MiB that every GPU the library runs on holds
+ * until the process ends; no device or host allocation.  A mesh needs
+ * (d^2 x box cells + 6 x ceil(cells / 256) + 64) doubles of it, the box being
+ * the real cells plus one link length of layers on every axis (D3Q19: up to
+ * about 440k box cells, e.g. 74^3; D2Q9: about 1M); larger meshes are
+ * rejected with VLBM_ERR_ARG.  Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other threads, other streams) race and must
+ * not be made.  Synchronises the stream; rep as for vlbm_geometry_precompute.
+ * Errors: VLBM_ERR_ARG (null mesh, mesh too large), VLBM_ERR_MESH,
+ * VLBM_ERR_DEVICE. */
+int vlbm_geometry_precompute_noalloc(vlbm_mesh m, void* stream, vlbm_geom_report* rep);
+
 /* Copy FP64 geometry to device arrays (any may be NULL):
  *  J [cells]; gup [d*d][cells] (full symmetric matrix, row-major ij);
  *  A [Q][d][cells] (A of the rest direction is 0); g [d][d][cells] (g_i

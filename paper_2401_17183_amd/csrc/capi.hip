@@ -214,6 +214,10 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
     delete m;
     return fail(VLBM_ERR_DEVICE, "copy of coordinates failed");
   }
+  if ((rc = alloc_mesh_geometry(m))) {
+    vlbm_mesh_destroy(reinterpret_cast<vlbm_mesh>(m));
+    return rc;
+  }
   *out = reinterpret_cast<vlbm_mesh>(m);
   return ok();
 }
@@ -231,51 +235,31 @@ int vlbm_mesh_destroy(vlbm_mesh mh) {
   return ok();
 }
 
-int vlbm_geometry_precompute(vlbm_mesh mh, void* stream, vlbm_geom_report* rep) {
-  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
-  if (!m) return fail(VLBM_ERR_ARG, "null mesh");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace vlbm {
+
+int alloc_mesh_geometry(MeshObj* m) {
   const size_t nc = m->box.ncells;
   const int d = m->d;
   int rc;
-  if (!m->J) {
-    if ((rc = dev_alloc(&m->J, nc * sizeof(double)))) return rc;
-    if ((rc = dev_alloc(&m->gup, nc * d * d * sizeof(double)))) return rc;
-    if ((rc = dev_alloc(&m->gco, nc * d * d * sizeof(double)))) return rc;
-    if ((rc = dev_alloc(&m->g, nc * d * d * sizeof(double)))) return rc;
-    if ((rc = dev_alloc(&m->A, nc * m->Q * d * sizeof(double)))) return rc;
-  }
-  const int nb = geometry_partial_blocks(m);
-  int* dflag = nullptr;
-  double* partial = nullptr;
-  if ((rc = dev_alloc(&dflag, sizeof(int)))) return rc;
-  if ((rc = dev_alloc(&partial, (size_t)nb * 6 * sizeof(double)))) {
-    dev_free(dflag);
-    return rc;
-  }
-  hipError_t e = hipMemsetAsync(dflag, 0, sizeof(int), s);
-  if (e == hipSuccess) e = launch_geometry(m, s, dflag, partial, nb);
-  int flag = 0;
-  double* hp = new double[(size_t)nb * 6];
-  if (e == hipSuccess) e = hipMemcpy(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(hp, partial, (size_t)nb * 6 * sizeof(double), hipMemcpyDeviceToHost);
-  dev_free(dflag);
-  dev_free(partial);
-  if (e != hipSuccess) {
-    delete[] hp;
-    return fail(VLBM_ERR_DEVICE, "geometry precompute: %s", hipGetErrorString(e));
-  }
+  if ((rc = dev_alloc(&m->J, nc * sizeof(double)))) return rc;
+  if ((rc = dev_alloc(&m->gup, nc * d * d * sizeof(double)))) return rc;
+  if ((rc = dev_alloc(&m->gco, nc * d * d * sizeof(double)))) return rc;
+  if ((rc = dev_alloc(&m->g, nc * d * d * sizeof(double)))) return rc;
+  if ((rc = dev_alloc(&m->A, nc * m->Q * d * sizeof(double)))) return rc;
+  return VLBM_OK;
+}
+
+// The report of a geometry pass from its flag and its (already reduced or
+// per-block) diagnostics: r[6] = min J, -max J, min eig, -max eig, min rest
+// f^eq/w, -max |A|.
+int finish_geometry(MeshObj* m, int flag, const double* r, vlbm_geom_report* rep) {
   if (flag) {
-    delete[] hp;
     m->have_geometry = false;
     return fail(VLBM_ERR_MESH, "degenerate mesh:%s%s", (flag & 1) ? " beta undefined (D_i == D_-i)" : "",
                 (flag & 2) ? " J <= 0 (reorder axes for a positive handedness)" : "");
   }
-  double r[6];
-  for (int k = 0; k < 6; ++k) r[k] = INFINITY;
-  for (int b = 0; b < nb; ++b)
-    for (int k = 0; k < 6; ++k) r[k] = fmin(r[k], hp[b * 6 + k]);
-  delete[] hp;
   m->report.min_J = r[0];
   m->report.max_J = -r[1];
   m->report.min_gup_eig = r[2];
@@ -285,6 +269,46 @@ int vlbm_geometry_precompute(vlbm_mesh mh, void* stream, vlbm_geom_report* rep) 
   m->have_geometry = true;
   if (rep) *rep = m->report;
   return ok();
+}
+
+}  // namespace vlbm
+
+extern "C" {
+
+int vlbm_geometry_precompute(vlbm_mesh mh, void* stream, vlbm_geom_report* rep) {
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m) return fail(VLBM_ERR_ARG, "null mesh");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = geometry_partial_blocks(m);
+  const size_t nbox = geometry_box_cells(m);
+  int* dflag = nullptr;
+  double* partial = nullptr;
+  double* gbox = nullptr;
+  int rc;
+  auto release = [&]() {
+    dev_free(dflag);
+    dev_free(partial);
+    dev_free(gbox);
+  };
+  if ((rc = dev_alloc(&dflag, sizeof(int))) || (rc = dev_alloc(&partial, (size_t)nb * 6 * sizeof(double))) ||
+      (rc = dev_alloc(&gbox, sizeof(double) * m->d * m->d * nbox))) {
+    release();
+    return rc;
+  }
+  hipError_t e = hipMemsetAsync(dflag, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_geometry(m, s, dflag, partial, nb, gbox);
+  int flag = 0;
+  std::vector<double> hp((size_t)nb * 6);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess) return fail(VLBM_ERR_DEVICE, "geometry precompute: %s", hipGetErrorString(e));
+  double r[6];
+  for (int k = 0; k < 6; ++k) r[k] = INFINITY;
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < 6; ++k) r[k] = fmin(r[k], hp[b * 6 + k]);
+  return finish_geometry(m, flag, r, rep);
 }
 
 int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double* g) {

@@ -486,7 +486,15 @@ constexpr int kDefaultRebase = 10;
 inline int rebase_period(const vlbm_params& p) { return p.rebase_every == 0 ? kDefaultRebase : p.rebase_every; }
 
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial);
+hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial,
+                           double* gbox);
+size_t geometry_box_cells(const MeshObj* m);
+// Allocates the mesh's FP64 geometry arrays (J, g^{ij}, g^i, g_i, A).
+int alloc_mesh_geometry(MeshObj* m);
+// Report of a geometry pass (capi.hip): flag of degenerate cells and the
+// reduced diagnostics r[6]; sets the thread-local error on failure.
+int finish_geometry(MeshObj* m, int flag, const double* r, vlbm_geom_report* rep);
+int set_error(int code, const char* fmt, ...);
 hipError_t launch_pack(SimObj* s);
 hipError_t launch_init(SimObj* s, const double* rho, const double* u, int* dflag);
 hipError_t launch_step(SimObj* s);

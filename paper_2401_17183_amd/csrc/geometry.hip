@@ -1,7 +1,10 @@
 // FP64 geometry precompute on the device (Sec. 2.1): tangent vectors, volume,
 // co-tangent vectors, inverse metric, and the link coefficients A (Theta of
-// eq. (gamma) contracted with the link velocity), plus a diagnostics report.
+// eq. (gamma) contracted with the link velocity), plus a diagnostics report;
+// and the variant of the precompute that allocates nothing.
 #include <math.h>
+
+#include <mutex>
 
 #include "common.hpp"
 
@@ -254,7 +257,19 @@ __global__ __launch_bounds__(kBlock) void k_links(GeoArgs a) {
 
 int geometry_partial_blocks(const MeshObj* m) { return (m->box.ncells + kBlock - 1) / kBlock; }
 
-hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial) {
+// Cells of the geometry box: the real cells and `layers` layers around them
+// on the d axes (g_i is needed one link beyond every real cell).
+size_t geometry_box_cells(const MeshObj* m) {
+  const int layers = lattice_speed(m->lattice);
+  size_t nbox = 1;
+  for (int i = 0; i < m->d; ++i) nbox *= (size_t)(m->box.n[i] + 2 * layers);
+  return nbox;
+}
+
+// Enqueue the two geometry passes on stream s.  Scratch: dflag (int, cleared
+// by the caller), partial [nblocks_partial][6], gbox [d][d][box cells].
+hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial,
+                           double* gbox) {
   GeoArgs a;
   a.box = m->box;
   a.d = m->d;
@@ -276,26 +291,113 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
   a.A = m->A;
   a.flag = dflag;
   a.partial = partial;
-  hipError_t e = hipMalloc((void**)&a.gbox, sizeof(double) * m->d * m->d * (size_t)a.nbox);
-  if (e != hipSuccess) return e;
+  a.gbox = gbox;
   k_basis<<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
-  if ((e = hipGetLastError()) != hipSuccess) {
-    (void)hipFree(a.gbox);
-    return e;
-  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (m->lattice) {
     case VLBM_D2Q9: k_links<D2Q9><<<nblocks_partial, kBlock, 0, s>>>(a); break;
     case VLBM_D3Q19: k_links<D3Q19><<<nblocks_partial, kBlock, 0, s>>>(a); break;
     case VLBM_D2Q21: k_links<D2Q21><<<nblocks_partial, kBlock, 0, s>>>(a); break;
     default: k_links<D3Q39><<<nblocks_partial, kBlock, 0, s>>>(a); break;
   }
-  if ((e = hipGetLastError()) != hipSuccess) {
-    (void)hipFree(a.gbox);
-    return e;
-  }
-  e = hipStreamSynchronize(s);
-  (void)hipFree(a.gbox);
-  return e;
+  return hipGetLastError();
 }
 
+namespace {
+
+// The precompute that allocates nothing keeps its scratch (degenerate-cell
+// flag, per-block diagnostics and their reduction, the g_i box) in this
+// device array.  Every GPU the library runs on holds its own copy until the
+// process ends; host code reaches it through the per-device address from
+// hipGetSymbolAddress, never through the name.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Address of this device's scratch (looked up once per device, with that
+// device current).
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+__global__ void k_clear_flag(int* flag) { *flag = 0; }
+
+// Minimum of each of the 6 diagnostics over the per-block partials (one
+// block; min is exact in any order, so this equals the host reduction).
+__global__ __launch_bounds__(kBlock) void k_geo_final(const double* partial, int nblocks, double* out) {
+  __shared__ double red[6][kBlock];
+  double v[6];
+  for (int k = 0; k < 6; ++k) v[k] = INFINITY;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+    for (int k = 0; k < 6; ++k) v[k] = fmin(v[k], partial[(size_t)b * 6 + k]);
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) out[k] = red[k][0];
+}
+
+}  // namespace
+
 }  // namespace vlbm
+
+extern "C" int vlbm_geometry_precompute_noalloc(vlbm_mesh mh, void* stream, vlbm_geom_report* rep) {
+  using namespace vlbm;
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m) return set_error(VLBM_ERR_ARG, "null mesh");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = geometry_partial_blocks(m);
+  const size_t nbox = geometry_box_cells(m);
+  // scratch layout (doubles): [0] flag word, [8, 14) reduced diagnostics,
+  // [32, 32 + 6 nb) per-block partials, then the g_i box, 256-byte aligned
+  const size_t part_off = 32;
+  const size_t box_off = (part_off + (size_t)nb * 6 + 31) / 32 * 32;
+  const size_t need = (box_off + (size_t)m->d * m->d * nbox) * sizeof(double);
+  if (need > kScratchBytes)
+    return set_error(VLBM_ERR_ARG,
+                     "vlbm_geometry_precompute_noalloc: the mesh needs %zu bytes of scratch, more than its %zu "
+                     "(use vlbm_geometry_precompute)",
+                     need, kScratchBytes);
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return set_error(VLBM_ERR_DEVICE, "scratch address: %s", hipGetErrorString(e));
+  double* sp = static_cast<double*>(base);
+  int* dflag = reinterpret_cast<int*>(sp);
+  double* reduced = sp + 8;
+  double* partial = sp + part_off;
+  double* gbox = sp + box_off;
+  k_clear_flag<<<1, 1, 0, s>>>(dflag);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = launch_geometry(m, s, dflag, partial, nb, gbox);
+  if (e == hipSuccess) {
+    k_geo_final<<<1, kBlock, 0, s>>>(partial, nb, reduced);
+    e = hipGetLastError();
+  }
+  int flag = 0;
+  double r[6];
+  if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(r, reduced, sizeof(r), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(VLBM_ERR_DEVICE, "geometry precompute: %s", hipGetErrorString(e));
+  return finish_geometry(m, flag, r, rep);
+}

@@ -90,6 +90,7 @@ _SIGS = {
                                    C.POINTER(vlbm_topology), C.c_double, C.POINTER(_P)]),
     "vlbm_mesh_destroy": (C.c_int, [_P]),
     "vlbm_geometry_precompute": (C.c_int, [_P, _P, C.POINTER(vlbm_geom_report)]),
+    "vlbm_geometry_precompute_noalloc": (C.c_int, [_P, _P, C.POINTER(vlbm_geom_report)]),
     "vlbm_geometry_fields": (C.c_int, [_P, _P, _P, _P, _P]),
     "vlbm_init": (C.c_int, [_P, C.POINTER(vlbm_params), _P, _P, _P, C.POINTER(_P)]),
     "vlbm_step": (C.c_int, [_P, C.c_int64]),
@@ -231,10 +232,11 @@ class Mesh:
     def from_workload(cls, w, **kw):
         return cls(w["lattice"], w["n"], w["coords"], w["faces"], w["wrap"], w["dx"], **kw)
 
-    def precompute(self):
+    def precompute(self, noalloc=False):
         torch = _torch()
         rep = vlbm_geom_report()
-        vlbm_geometry_precompute(self.h, _stream_ptr(torch), C.byref(rep))
+        fn = vlbm_geometry_precompute_noalloc if noalloc else vlbm_geometry_precompute
+        fn(self.h, _stream_ptr(torch), C.byref(rep))
         self.report = rep.as_dict()
         return self.report
 
