@@ -67,11 +67,12 @@ def moments(lat, J, N):
     return rho, U
 
 
-def delta_pi(lat, tau, A, fe, Ut, rho, aext):
-    """Symmetrised dPi of eq. (delta-flux) plus the body-force reading."""
+def delta_pi(lat, tau, A, fe, Ut, rho, aext, A_in=None):
+    """Symmetrised dPi of eq. (delta-flux) plus the body-force reading.
+    A_in: the incoming link coefficients (default A_opp(a); see oracle.moving)."""
     opp = lat.opp
     k = 1.0 - 1.0 / (2.0 * tau)
-    S = A + A[opp]
+    S = A + (A[opp] if A_in is None else A_in)
     P = -0.5 * k * np.einsum("ai,aj...,a...->ij...", lat.cf, S, fe)
     ra = rho[None] * aext
     P = P + 0.5 * k * (np.einsum("i...,j...->ij...", Ut, ra) + np.einsum("i...,j...->ij...", ra, Ut))
@@ -87,10 +88,13 @@ def delta_n(lat, J, Ft, dPi):
                           + np.einsum("aij,ij...->a...", H2, dPi) / T0)
 
 
-def inertial_force(lat, J, A, N, Np):
-    """F^i of eq. (compo-constr): J F^i = -1/2 sum_a [A^i_a N'_a + A^i_opp(a) N_a]."""
+def inertial_force(lat, J, A, N, Np, A_in=None):
+    """F^i of eq. (compo-constr): J F^i = -1/2 sum_a [A^i_a N'_a + A^i_opp(a) N_a]
+    (A_in in place of A_opp(a) when given: the incoming coefficients of
+    oracle.moving)."""
+    Ai = A[lat.opp] if A_in is None else A_in
     return (-0.5 * np.einsum("ai...,a...->i...", A, Np)
-            - 0.5 * np.einsum("ai...,a...->i...", A[lat.opp], N)) / J[None]
+            - 0.5 * np.einsum("ai...,a...->i...", Ai, N)) / J[None]
 
 
 def hydrodynamic_projector(lat):
@@ -105,13 +109,15 @@ def collision_matrix(lat, tau, tau_g):
     return -np.eye(lat.Q) / tau_g + (1.0 / tau_g - 1.0 / tau) * hydrodynamic_projector(lat)
 
 
-def collide(geom, tau, N, tol=1e-14, max_iter=50, tau_g=None):
+def collide(geom, tau, N, tol=1e-14, max_iter=50, tau_g=None, A_in=None):
     """Post-collision populations and the converged inertial force.
 
     N (Q, *n) -> (N', info) with info = {F, Ut, U, rho, iters (*n), converged}.
     iters is the per-cell number of fixed-point iterations needed to meet the
     stopping rule (max_iter + 1 where it never did).  tau_g None: BGK;
     otherwise the general collision matrix collision_matrix(lat, tau, tau_g).
+    A_in: incoming link coefficients in place of A_opp(a) (moving meshes,
+    oracle.moving); geom.A holds the outgoing ones.
     """
     lat = geom.lat
     M = None if tau_g is None else collision_matrix(lat, tau, tau_g)
@@ -125,13 +131,13 @@ def collide(geom, tau, N, tol=1e-14, max_iter=50, tau_g=None):
         Ft = F + rho[None] * aext
         Ut = U + Ft / (2.0 * rho[None])
         fe = feq(lat, rho, U, Ut, gup)
-        dPi = delta_pi(lat, tau, A, fe, Ut, rho, aext)
+        dPi = delta_pi(lat, tau, A, fe, Ut, rho, aext, A_in)
         if M is None:
             Om = -(N - J[None] * fe) / tau
         else:
             Om = np.einsum("ab,b...->a...", M, N - J[None] * fe)
         Np = N + Om + delta_n(lat, J, Ft, dPi)
-        Fn = inertial_force(lat, J, A, N, Np)
+        Fn = inertial_force(lat, J, A, N, Np, A_in)
         change = np.max(np.abs(Fn - F), axis=0)
         newly = (change <= tol * rho) & (iters > max_iter)
         iters[newly] = k

@@ -297,3 +297,29 @@ def wavy_channel_3d(n1=16, n2=12, n3=8, amp=0.1, strength=1.0, tau=0.7, G=1e-5, 
             "faces": [(PERIODIC, PERIODIC), (WALL, WALL), (PERIODIC, PERIODIC)],
             "wrap": [(n1 * dx, 0, 0), (0, 0, 0), (0, 0, n3 * dx)], "dx": dx,
             "tau": tau, "body_force": (G, 0.0, 0.0), "rho": np.ones((n3, n2, n1)), "u": u}
+
+
+def moving_coords(w, t, breathe=0.0, omega=0.0, velocity=None, period=40.0):
+    """Node positions and periodic translations of a periodic workload w at
+    integer time t for a mesh in motion: the displacement of w's nodes from
+    the uniform lattice (x - dx q) scaled by 1 + breathe sin(2 pi t / period)
+    (a deforming mesh), the whole mesh turned by the angle omega t about the
+    last axis (a rigid rotation in the (x, y) plane) and shifted by
+    velocity * t (a rigid translation).  Returns (coords (t), wrap (t));
+    t = 0 gives w's own mesh when breathe only scales."""
+    d = len(w["n"])
+    X = np.array(w["coords"], dtype=np.float64)
+    dx = w["dx"]
+    axes = [np.arange(w["n"][i], dtype=np.float64) for i in range(d)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    base = np.stack([grids[d - 1 - i] * dx for i in range(d)], axis=-1)
+    X = base + (X - base) * (1.0 + breathe * np.sin(2.0 * np.pi * t / period))
+    wrap = np.array([np.asarray(v, dtype=np.float64)[:d] for v in w["wrap"]])
+    th = omega * t
+    R = np.eye(d)
+    R[0, 0], R[0, 1], R[1, 0], R[1, 1] = np.cos(th), -np.sin(th), np.sin(th), np.cos(th)
+    X = X @ R.T
+    wrap = wrap @ R.T
+    if velocity is not None:
+        X = X + np.asarray(velocity, dtype=np.float64)[:d] * t
+    return X, wrap

@@ -113,7 +113,7 @@ def test_poiseuille_needs_the_inertial_force(monkeypatch):
     """Planted mistake: without the inertial force the same run leaves the
     analytic profile by orders of magnitude more."""
     good = poiseuille_hold_error(32, steps=300)
-    zero = lambda lat, J, A, N, Np: np.zeros((lat.d,) + J.shape)
+    zero = lambda lat, J, A, N, Np, A_in=None: np.zeros((lat.d,) + J.shape)
     monkeypatch.setattr(C, "inertial_force", zero)
     bad = poiseuille_hold_error(32, steps=300)
     assert bad > 30 * good, (good, bad)
