@@ -190,6 +190,31 @@ int vlbm_init(vlbm_mesh m, const vlbm_params* p, const double* rho, const double
  * the device and reported by the next vlbm_sync or vlbm_moments. */
 int vlbm_step(vlbm_sim s, int64_t nsteps);
 
+/* One time step on a mesh that moves (the paper's closing discussion names
+ * time-varying coordinates as a next step and gives no equations; this is the
+ * library's reading): the mesh goes from its current node positions x(q, t)
+ * to coords_next = x(q, t + 1) (device FP64, the layout of vlbm_mesh_create)
+ * with the periodic translations wrap_next (host double [3][3], row i the
+ * vector of axis i; NULL: unchanged).  A population leaving q at t along c_a
+ * has the lattice velocity e_a(q, t) and arrives at q + c_a with
+ * e_a(q + c_a, t + 1); eqs. (forceI) and (forceO) split the momentum it gains
+ * between the two cells, so eq. (compo-constr) takes the outgoing and
+ * incoming coefficients
+ *   A+^i_a(q, t) = [e_a(q + c_a, t + 1) - e_a(q, t)] . g^i(q, t),
+ *   A-^i_a(q, t) = [e_a(q, t) - e_a(q - c_a, t - 1)] . g^i(q, t)
+ * (eq. (delta-flux) takes A+ + A-); before its first moving step the mesh is
+ * taken as at rest.  The geometry of t + 1 (eqs. (distance) to (gamma)) is
+ * computed on the device every step.  Mass and the mid-link Euclidean
+ * momentum with each e_a at the time the particle has it are conserved; the
+ * audits report that momentum, the output mapping treats the mesh as
+ * momentarily at rest.  FP64 storage, BGK, D2Q9 / D3Q19, periodic axes only,
+ * and the mesh must belong to this simulation alone.  Asynchronous; a mesh
+ * that becomes degenerate is reported by vlbm_sync (VLBM_ERR_MESH).  The mesh
+ * keeps the new positions; a later vlbm_step continues with it at rest.
+ * Errors: VLBM_ERR_ARG, VLBM_ERR_UNSUPPORTED, VLBM_ERR_STATE (shared mesh),
+ * VLBM_ERR_NOMEM, VLBM_ERR_DEVICE. */
+int vlbm_step_moving(vlbm_sim s, const double* coords_next, const double* wrap_next);
+
 /* Wait for the sim's enqueued work.  Returns VLBM_ERR_NOCONVERGE when a step
  * since the last report ran some cell on an inertial force whose fixed point
  * (eq. (compo-constr)) hit fp_max_iter, with the count of such cell-steps in

@@ -17,6 +17,7 @@ int audit_words();
 #include "batch.hpp"
 
 #include <string>
+#include <utility>
 #include <vector>
 
 using namespace vlbm;
@@ -325,6 +326,16 @@ int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double
 }
 
 static void free_sim(SimObj* s) {
+  if (s->mesh) s->mesh->users--;
+  for (double* b : s->mv_box) dev_free(b);
+  dev_free(s->mv_J);
+  dev_free(s->mv_gup);
+  dev_free(s->mv_gco);
+  dev_free(s->mv_g);
+  dev_free(s->mv_A);
+  dev_free(s->Ain);
+  dev_free(s->mv_Ain);
+  dev_free(s->mv_pack);
   dev_free(s->pop[0]);
   dev_free(s->pop[1]);
   dev_free(s->geo);
@@ -364,6 +375,7 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   SimObj* s = new (std::nothrow) SimObj();
   if (!s) return fail(VLBM_ERR_NOMEM, "host allocation failed");
   s->mesh = m;
+  m->users++;
   s->p = *p;
   if (s->p.fp_max_iter <= 0) s->p.fp_max_iter = 50;
   if (s->p.fp_tol < 0)
@@ -468,6 +480,10 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s) return fail(VLBM_ERR_ARG, "null sim");
   if (nsteps < 0) return fail(VLBM_ERR_ARG, "nsteps < 0");
+  if (s->geo_stale) {   // the mesh moved (vlbm_step_moving): re-pack its current geometry
+    HIP_TRY(launch_pack(s));
+    s->geo_stale = 0;
+  }
   const int rebase = rebase_period(s->p);
   EventPool* ep = s->timing_on ? static_cast<EventPool*>(s->timing) : nullptr;
   for (int64_t k = 0; k < nsteps; ++k) {
@@ -504,7 +520,88 @@ int vlbm_sync(vlbm_sim sh) {
   int n = 0;
   const int rc = take_step_unconverged(s, &n);
   if (rc) return rc;
+  if (s->moving) {   // degenerate cells met by the geometry of a moving step
+    int bad = 0;
+    HIP_TRY(hipMemcpy(&bad, s->flags + 1, sizeof(int), hipMemcpyDeviceToHost));
+    if (bad) {
+      HIP_TRY(hipMemset(s->flags + 1, 0, sizeof(int)));
+      return fail(VLBM_ERR_MESH, "the moving mesh became degenerate:%s%s",
+                  (bad & 1) ? " beta undefined (D_i == D_-i)" : "", (bad & 2) ? " J <= 0" : "");
+    }
+  }
   if (n) return fail(VLBM_ERR_NOCONVERGE, "fixed point hit its cap in %d cell-steps", n);
+  return ok();
+}
+
+int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_next) {
+  SimObj* s = reinterpret_cast<SimObj*>(sh);
+  if (!s || !coords_next) return fail(VLBM_ERR_ARG, "vlbm_step_moving: null argument");
+  MeshObj* m = s->mesh;
+  if (s->p.precision != VLBM_FP64)
+    return fail(VLBM_ERR_UNSUPPORTED, "moving meshes are built for FP64 storage and arithmetic");
+  if (m->lattice != VLBM_D2Q9 && m->lattice != VLBM_D3Q19)
+    return fail(VLBM_ERR_UNSUPPORTED, "moving meshes are built for D2Q9 and D3Q19");
+  for (int i = 0; i < m->d; ++i)
+    if (m->box.face[i][0] != VLBM_PERIODIC)
+      return fail(VLBM_ERR_UNSUPPORTED, "moving meshes are built for periodic axes only");
+  if (general_collision(s->p) || s->p.stream_only)
+    return fail(VLBM_ERR_UNSUPPORTED, "moving meshes are built for the BGK collision");
+  if (m->users != 1) return fail(VLBM_ERR_STATE, "the mesh is shared by %d simulations; moving it would change them all",
+                                 m->users);
+  const size_t nc = m->box.ncells;
+  const int d = m->d;
+  const size_t nbox = geometry_box_cells(m);
+  int rc;
+  if (!s->moving) {   // first moving step: the mesh was at rest before it (the box of t - 1 is that of t)
+    for (double*& b : s->mv_box)
+      if ((rc = dev_alloc(&b, sizeof(double) * d * d * nbox))) return rc;
+    if ((rc = dev_alloc(&s->mv_J, nc * sizeof(double))) || (rc = dev_alloc(&s->mv_gup, nc * d * d * sizeof(double))) ||
+        (rc = dev_alloc(&s->mv_gco, nc * d * d * sizeof(double))) || (rc = dev_alloc(&s->mv_g, nc * d * d * sizeof(double))) ||
+        (rc = dev_alloc(&s->mv_A, nc * m->Q * d * sizeof(double))) || (rc = dev_alloc(&s->Ain, nc * m->Q * d * sizeof(double))) ||
+        (rc = dev_alloc(&s->mv_Ain, nc * m->Q * d * sizeof(double))) ||
+        (rc = dev_alloc(&s->mv_pack, moving_pack_elements(m->lattice, nc) * sizeof(double))))
+      return rc;
+    HIP_TRY(hipMemsetAsync(s->flags + 1, 0, sizeof(int), s->stream));
+    // g_i of the current mesh on its box (into the t box; the real-cell arrays
+    // it also writes are the next-time scratch), then t - 1 = t
+    HIP_TRY(launch_basis_of(m, m->coords, m->wrap, s->mv_box[1], s->mv_J, s->mv_gup, s->mv_gco, s->mv_g,
+                            s->flags + 1, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->mv_box[0], s->mv_box[1], sizeof(double) * d * d * nbox, hipMemcpyDeviceToDevice,
+                           s->stream));
+    s->moving = 1;
+  }
+  double wrap[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) wrap[i][k] = (wrap_next && i < d && k < d) ? wrap_next[i * 3 + k] : m->wrap[i][k];
+  // geometry of t + 1
+  HIP_TRY(launch_basis_of(m, coords_next, wrap, s->mv_box[2], s->mv_J, s->mv_gup, s->mv_gco, s->mv_g, s->flags + 1,
+                          s->stream));
+  // coefficients of the step at t, and of the state at t + 1
+  HIP_TRY(launch_links_moving(m, s->mv_box[0], s->mv_box[1], s->mv_box[2], m->J, m->gup, m->gco, s->mv_gco,
+                              s->p.body_force, s->has_force, s->mv_pack, s->mv_Ain, s->mv_A, s->stream));
+  HIP_TRY(launch_step_moving(s, s->mv_pack));
+  s->buf ^= 1;
+  s->t++;
+  // the mesh is now at t + 1: its coordinates, translations and geometry
+  const size_t ncoord = (size_t)m->m[0] * m->m[1] * m->m[2] * d;
+  HIP_TRY(hipMemcpyAsync(m->coords, coords_next, ncoord * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) m->wrap[i][k] = wrap[i][k];
+  std::swap(m->J, s->mv_J);
+  std::swap(m->gup, s->mv_gup);
+  std::swap(m->gco, s->mv_gco);
+  std::swap(m->g, s->mv_g);
+  std::swap(m->A, s->mv_A);
+  std::swap(s->Ain, s->mv_Ain);
+  double* oldest = s->mv_box[0];
+  s->mv_box[0] = s->mv_box[1];
+  s->mv_box[1] = s->mv_box[2];
+  s->mv_box[2] = oldest;
+  s->geo_stale = 1;
+  if (s->p.audit_every > 0 && s->t % s->p.audit_every == 0) {
+    const int arc = vlbm_audit_now(sh);
+    if (arc) return arc;
+  }
   return ok();
 }
 

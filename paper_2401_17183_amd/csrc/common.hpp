@@ -28,6 +28,7 @@ namespace vlbm {
 // cells, so they run on periodic axes only.
 // ---------------------------------------------------------------------------
 struct D2Q9 {
+  static constexpr bool MOVING = false;
   static constexpr int Q = 9;
   static constexpr int D = 2;
   static constexpr int ID = VLBM_D2Q9;
@@ -44,6 +45,7 @@ struct D2Q9 {
 };
 
 struct D3Q19 {
+  static constexpr bool MOVING = false;
   static constexpr int Q = 19;
   static constexpr int D = 3;
   static constexpr int ID = VLBM_D3Q19;
@@ -62,6 +64,7 @@ struct D3Q19 {
 };
 
 struct D2Q21 {
+  static constexpr bool MOVING = false;
   static constexpr int Q = 21;
   static constexpr int D = 2;
   static constexpr int ID = VLBM_D2Q21;
@@ -85,6 +88,7 @@ struct D2Q21 {
 };
 
 struct D3Q39 {
+  static constexpr bool MOVING = false;
   static constexpr int Q = 39;
   static constexpr int D = 3;
   static constexpr int ID = VLBM_D3Q39;
@@ -108,6 +112,14 @@ struct D3Q39 {
                   : a < 33 ? 1.0 / 432.0
                   : 1.0 / 1620.0;
   }
+};
+
+// A lattice on a mesh that moves in time: the same velocities and weights,
+// and each cell carries incoming link coefficients of its own (the outgoing
+// and incoming momentum changes of a hop then involve the mesh at different
+// times) instead of the opposite direction's outgoing ones.
+template <class B> struct Moving : B {
+  static constexpr bool MOVING = true;
 };
 
 __host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
@@ -363,6 +375,7 @@ __device__ __forceinline__ int link_at(const LinkPlan& p, int cell, int& src) {
 // Host-side objects.
 // ---------------------------------------------------------------------------
 struct MeshObj {
+  int users = 0;       // simulations created on the mesh
   int lattice;
   int d, Q;
   Box box;
@@ -390,8 +403,9 @@ struct MeshObj {
 template <class L> struct Pack {
   static constexpr int J = 0;
   static constexpr int GUP = 1;
-  static constexpr int A = GUP + nup<L::D>();                 // A^i_a for a >= 1
-  static constexpr int AEXT = A + (L::Q - 1) * L::D;          // present if force
+  static constexpr int A = GUP + nup<L::D>();                 // A^i_a for a >= 1 (outgoing)
+  static constexpr int AIN = A + (L::Q - 1) * L::D;           // moving meshes: incoming coefficients
+  static constexpr int AEXT = AIN + (L::MOVING ? (L::Q - 1) * L::D : 0);   // present if force
   static constexpr int UINF = AEXT + L::D;                    // present if far field
   static constexpr int GUPLO = UINF + L::D;                   // low words of g^{ij}
   static constexpr int WORDS = GUPLO + nup<L::D>();
@@ -410,6 +424,10 @@ __host__ __device__ __forceinline__ size_t pack_index(int word, int cell) {
 // Elements of a packed geometry of nc cells (the last tile is whole).
 inline size_t pack_elements(int words, size_t nc) {
   return (nc + kGeoTile - 1) / kGeoTile * kGeoTile * (size_t)words;
+}
+
+inline size_t moving_pack_elements(int lattice, size_t nc) {
+  return pack_elements(lattice == VLBM_D2Q9 ? Pack<Moving<D2Q9>>::WORDS : Pack<Moving<D3Q19>>::WORDS, nc);
 }
 
 inline int pack_words(int lattice) {
@@ -447,6 +465,16 @@ struct SimObj {
                                 //                2 = unconverged cell-steps of the step kernel
   unsigned long long* stats = nullptr;   // device [4]: fixed-point statistics of the steps (when stats_on)
   int stats_on = 0;
+  // moving mesh (vlbm_step_moving): g_i boxes of the times t - 1, t, t + 1,
+  // the real-cell geometry of t + 1, the incoming coefficients of the current
+  // state (audits), and the step's pack; allocated at the first moving step
+  int moving = 0;
+  int geo_stale = 0;              // the static pack no longer matches the mesh
+  double* mv_box[3] = {nullptr, nullptr, nullptr};
+  double *mv_J = nullptr, *mv_gup = nullptr, *mv_gco = nullptr, *mv_g = nullptr, *mv_A = nullptr;
+  double* Ain = nullptr;          // [Q][d][cells], null on a static mesh
+  double* mv_Ain = nullptr;
+  double* mv_pack = nullptr;
   // kernel timing (vlbm_kernel_timing): event pairs around the step and the
   // re-basing launches, resolved when read
   int timing_on = 0;
@@ -489,6 +517,12 @@ inline int rebase_period(const vlbm_params& p) { return p.rebase_every == 0 ? kD
 hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partial, int nblocks_partial,
                            double* gbox);
 size_t geometry_box_cells(const MeshObj* m);
+hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double (*wrap)[3], double* gbox, double* J,
+                           double* gup, double* gco, double* g, int* dflag, hipStream_t s);
+hipError_t launch_links_moving(const MeshObj* m, const double* gprev, const double* gcur, const double* gnext,
+                               const double* J, const double* gup, const double* gco, const double* gco_next,
+                               const double* G, int has_force, double* pack, double* Ain_next, double* A_next,
+                               hipStream_t s);
 // Allocates the mesh's FP64 geometry arrays (J, g^{ij}, g^i, g_i, A).
 int alloc_mesh_geometry(MeshObj* m);
 // Report of a geometry pass (capi.hip): flag of degenerate cells and the
@@ -498,6 +532,8 @@ int set_error(int code, const char* fmt, ...);
 hipError_t launch_pack(SimObj* s);
 hipError_t launch_init(SimObj* s, const double* rho, const double* u, int* dflag);
 hipError_t launch_step(SimObj* s);
+// one step on a moving mesh with the given FP64 moving-mesh pack (step.hip)
+hipError_t launch_step_moving(SimObj* s, const double* pack);
 hipError_t launch_moments(SimObj* s, double* rho, double* u, double* U, int* dflag);
 hipError_t launch_get_pop(SimObj* s, double* N);
 hipError_t launch_set_pop(SimObj* s, const double* N);

@@ -21,13 +21,23 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   AT gup_lo[LO ? nup<L::D>() : 1];   // g^{ij} - gup (FP32 words, FP64 arithmetic)
   AT aext[L::D];           // a_ext^i = G . g^i
   AT Areg[STRIDE ? 1 : L::Q][L::D];
+  // moving meshes: the incoming coefficients, after the outgoing ones in LDS
+  AT Ainreg[(L::MOVING && !STRIDE) ? L::Q : 1][L::D];
   const AT* lds;
   int lofs;                // added to every LDS index (0); re-defined per fixed-point iteration
   __device__ __forceinline__ T j() const { return T(J); }
   __device__ __forceinline__ T ae(int i) const { return T(aext[i]); }
+  // outgoing link coefficient A^i_al (eq. (gamma) contracted with c_al)
   __device__ __forceinline__ AT a(int al, int i) const {
     if constexpr (STRIDE == 0) return Areg[al][i];
     else return al == 0 ? AT(0) : lds[lofs + ((al - 1) * L::D + i) * STRIDE];
+  }
+  // incoming one: on a static mesh the opposite direction's outgoing one
+  // (c_opp = -c), on a moving mesh a coefficient of its own
+  __device__ __forceinline__ AT ain(int al, int i) const {
+    if constexpr (!L::MOVING) return a(opp(al), i);
+    else if constexpr (STRIDE == 0) return Ainreg[al][i];
+    else return al == 0 ? AT(0) : lds[lofs + ((L::Q - 1) * L::D + (al - 1) * L::D + i) * STRIDE];
   }
 };
 
@@ -83,6 +93,22 @@ __device__ __forceinline__ void a_pair(const CellGeo<L, T, AT, ST>& g, int p, in
     } else {
       ap[i] = widen<T>(g.a(p, i));
       aq[i] = widen<T>(g.a(q, i));
+    }
+  }
+}
+
+// Incoming coefficients of the pair (p, q) in the arithmetic type (moving
+// meshes only; a static mesh takes the pair's outgoing ones crosswise).
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void ain_pair(const CellGeo<L, T, AT, ST>& g, int p, int q, T* ip, T* iq) {
+#pragma unroll
+  for (int i = 0; i < L::D; ++i) {
+    if constexpr (ST != 0) {
+      ip[i] = T(g.ain(p, i));
+      iq[i] = T(g.ain(q, i));
+    } else {
+      ip[i] = widen<T>(g.ain(p, i));
+      iq[i] = widen<T>(g.ain(q, i));
     }
   }
 }
@@ -295,17 +321,35 @@ __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const E
     T even, odd;
     feq_parts<L, T, AT, ST, p>(g, e, even, odd);
     const T fp = even + odd, fm = even - odd, df = T(2) * odd;
+    if constexpr (!L::MOVING) {
 #pragma unroll
-    for (int i = 0; i < L::D; ++i) {
-      X[i] += ap[i] * fp + am[i] * fm;
-      if constexpr (WITH_XO) Xo[i] += am[i] * fp + ap[i] * fm;
-    }
+      for (int i = 0; i < L::D; ++i) {
+        X[i] += ap[i] * fp + am[i] * fm;
+        if constexpr (WITH_XO) Xo[i] += am[i] * fp + ap[i] * fm;
+      }
 #pragma unroll
-    for (int i = 0; i < L::D; ++i) {
-      const int ci = L::c(p, i);
-      if (ci == 0) continue;
+      for (int i = 0; i < L::D; ++i) {
+        const int ci = L::c(p, i);
+        if (ci == 0) continue;
 #pragma unroll
-      for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * (ap[j] + am[j]) * df;
+        for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * (ap[j] + am[j]) * df;
+      }
+    } else {
+      // S_a = A_a + Ain_a differs between the two members of the pair
+      T ip[L::D], im[L::D];
+      ain_pair<L, T, AT, ST>(g, p, p + 1, ip, im);
+#pragma unroll
+      for (int i = 0; i < L::D; ++i) {
+        X[i] += ap[i] * fp + am[i] * fm;
+        if constexpr (WITH_XO) Xo[i] += ip[i] * fp + im[i] * fm;
+      }
+#pragma unroll
+      for (int i = 0; i < L::D; ++i) {
+        const int ci = L::c(p, i);
+        if (ci == 0) continue;
+#pragma unroll
+        for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * ((ap[j] + ip[j]) * fp - (am[j] + im[j]) * fm);
+      }
     }
     pass_feq<L, T, AT, ST, WITH_XO, p + 2>(g, e, X, Xo, M);
   }
@@ -470,11 +514,21 @@ __device__ __forceinline__ void prepare_pairs(const CellGeo<L, T, AT, ST>& g, co
     const T np = T(N[a]), nm = T(N[a + 1]);
     rhoJ += np + nm;
     const T dn = np - nm;
+    T ip[D], im[D];   // incoming coefficients of the pair
+    if constexpr (L::MOVING) {
+      ain_pair<L, T, AT, ST>(g, a, a + 1, ip, im);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        ip[i] = am[i];
+        im[i] = ap[i];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * dn;
       C[i] += ap[i] * np + am[i] * nm;
-      B[i] -= T(0.5) * (am[i] * np + ap[i] * nm);
+      B[i] -= T(0.5) * (ip[i] * np + im[i] * nm);
     }
     if constexpr (ST != 0) add_link_moments<L, T, a>(ap, am, m);
     prepare_pairs<L, T, AT, ST, NS, a + 2>(g, N, rhoJ, mom, C, B, m);

@@ -306,6 +306,172 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
 
 namespace {
 
+// Link coefficients of a step on a moving mesh (time t to t + 1), per real
+// cell, from g_i on the geometry boxes of the times t - 1, t and t + 1:
+//   outgoing  A+^i_a(q, t) = [e_a(q + c_a, t + 1) - e_a(q, t)] . g^i(q, t)
+//   incoming  A-^i_a(q, t) = [e_a(q, t) - e_a(q - c_a, t - 1)] . g^i(q, t)
+// packed with J(t), g^{ij}(t) and a_ext(t) = G . g^i(t) for the step kernel;
+// and for the state at t + 1 (audits, output mapping) its incoming
+// coefficients A-(t + 1) and its static outgoing ones (the mesh taken as
+// momentarily at rest).
+struct MovingLinkArgs {
+  Box box;
+  int nb[3], nbox, layers;
+  const double *gprev, *gcur, *gnext;      // [d][d][nbox]
+  const double *J, *gup, *gco;             // time t, real cells
+  const double* gco_next;                  // time t + 1, real cells
+  double G[3];
+  int has_force;
+  double* pack;                            // moving-mesh step words (FP64)
+  double* Ain_next;                        // [Q][d][cells]
+  double* A_next;                          // [Q][d][cells]
+};
+
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_links_moving(MovingLinkArgs a) {
+  constexpr int D = L::D;
+  using LM = Moving<L>;
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= a.box.ncells) return;
+  const long nc = a.box.ncells;
+  const int x = cell % a.box.n[0];
+  const int y = (cell / a.box.n[0]) % a.box.n[1];
+  const int z = cell / (a.box.n[0] * a.box.n[1]);
+  const int ly = a.layers;
+  const int bq[3] = {x + ly, y + (D > 1 ? ly : 0), z + (D > 2 ? ly : 0)};
+  auto bidx = [&](int s0, int s1, int s2) { return bq[0] + s0 + a.nb[0] * (bq[1] + s1 + a.nb[1] * (bq[2] + s2)); };
+  // e_a at a box cell from g on a box: c^j g_j
+  auto eat = [&](const double* gb, int al, long b, double* e) {
+    for (int k = 0; k < D; ++k) {
+      double v = 0;
+      for (int j = 0; j < D; ++j) {
+        const int cj = L::c(al, j);
+        if (cj != 0) v += cj * gb[(long)(j * D + k) * a.nbox + b];
+      }
+      e[k] = v;
+    }
+  };
+  auto proj = [&](const double* gco, const double* v, double* out) {
+    for (int i = 0; i < D; ++i) {
+      double s = 0;
+      for (int k = 0; k < D; ++k) s += v[k] * gco[(i * D + k) * nc + cell];
+      out[i] = s;
+    }
+  };
+  double* pk = a.pack;
+  pk[pack_index<LM>(Pack<LM>::J, cell)] = a.J[cell];
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j) {
+      pk[pack_index<LM>(Pack<LM>::GUP + up<D>(i, j), cell)] = a.gup[(i * D + j) * nc + cell];
+      pk[pack_index<LM>(Pack<LM>::GUPLO + up<D>(i, j), cell)] = 0.0;
+    }
+  for (int i = 0; i < D; ++i) {
+    a.Ain_next[(0 * D + i) * nc + cell] = 0.0;
+    a.A_next[(0 * D + i) * nc + cell] = 0.0;
+  }
+  const long b0 = bidx(0, 0, 0);
+  for (int al = 1; al < L::Q; ++al) {
+    const int c0 = L::c(al, 0), c1 = D > 1 ? L::c(al, 1) : 0, c2 = D > 2 ? L::c(al, 2) : 0;
+    const long bp = bidx(c0, c1, c2), bm = bidx(-c0, -c1, -c2);
+    double e_cur[3], e_next_there[3], e_prev_back[3], e_next[3], e_cur_back[3], v[3], r[3];
+    eat(a.gcur, al, b0, e_cur);
+    eat(a.gnext, al, bp, e_next_there);
+    eat(a.gprev, al, bm, e_prev_back);
+    eat(a.gnext, al, b0, e_next);
+    eat(a.gcur, al, bm, e_cur_back);
+    for (int k = 0; k < D; ++k) v[k] = e_next_there[k] - e_cur[k];
+    proj(a.gco, v, r);
+    for (int i = 0; i < D; ++i) pk[pack_index<LM>(Pack<LM>::A + (al - 1) * D + i, cell)] = r[i];
+    for (int k = 0; k < D; ++k) v[k] = e_cur[k] - e_prev_back[k];
+    proj(a.gco, v, r);
+    for (int i = 0; i < D; ++i) pk[pack_index<LM>(Pack<LM>::AIN + (al - 1) * D + i, cell)] = r[i];
+    // the state at t + 1
+    for (int k = 0; k < D; ++k) v[k] = e_next[k] - e_cur_back[k];
+    proj(a.gco_next, v, r);
+    for (int i = 0; i < D; ++i) a.Ain_next[(al * D + i) * nc + cell] = r[i];
+    double e_static_there[3];
+    eat(a.gnext, al, bp, e_static_there);
+    for (int k = 0; k < D; ++k) v[k] = e_static_there[k] - e_next[k];
+    proj(a.gco_next, v, r);
+    for (int i = 0; i < D; ++i) a.A_next[(al * D + i) * nc + cell] = r[i];
+  }
+  for (int i = 0; i < D; ++i) {
+    double ae = 0;
+    for (int k = 0; k < D; ++k) ae += a.G[k] * a.gco[(i * D + k) * nc + cell];
+    pk[pack_index<LM>(Pack<LM>::AEXT + i, cell)] = a.has_force ? ae : 0.0;
+  }
+}
+
+}  // namespace
+
+// g_i on the geometry box and J, g^{ij}, g^i, g_i on the real cells of the
+// node positions `coords` (mesh layout) with periodic translations `wrap`,
+// into the given arrays (pass 1 of the precompute); degenerate cells set bits
+// of *dflag.
+hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double (*wrap)[3], double* gbox, double* J,
+                           double* gup, double* gco, double* g, int* dflag, hipStream_t s) {
+  GeoArgs a;
+  a.box = m->box;
+  a.d = m->d;
+  a.nbox = 1;
+  a.layers = lattice_speed(m->lattice);
+  a.ghost = a.layers + 1;
+  for (int i = 0; i < 3; ++i) {
+    a.m[i] = m->m[i];
+    a.nb[i] = i < m->d ? m->box.n[i] + 2 * a.layers : 1;
+    a.nbox *= a.nb[i];
+    for (int k = 0; k < 3; ++k) a.wrap[i][k] = wrap[i][k];
+  }
+  a.inv2dx = 1.0 / (2.0 * m->dx);
+  a.coords = coords;
+  a.J = J;
+  a.gup = gup;
+  a.gco = gco;
+  a.g = g;
+  a.A = nullptr;
+  a.flag = dflag;
+  a.partial = nullptr;
+  a.gbox = gbox;
+  k_basis<<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// The link coefficients of a step on a moving mesh (k_links_moving).
+hipError_t launch_links_moving(const MeshObj* m, const double* gprev, const double* gcur, const double* gnext,
+                               const double* J, const double* gup, const double* gco, const double* gco_next,
+                               const double* G, int has_force, double* pack, double* Ain_next, double* A_next,
+                               hipStream_t s) {
+  MovingLinkArgs a;
+  a.box = m->box;
+  a.layers = lattice_speed(m->lattice);
+  a.nbox = 1;
+  for (int i = 0; i < 3; ++i) {
+    a.nb[i] = i < m->d ? m->box.n[i] + 2 * a.layers : 1;
+    a.nbox *= a.nb[i];
+    a.G[i] = G[i];
+  }
+  a.gprev = gprev;
+  a.gcur = gcur;
+  a.gnext = gnext;
+  a.J = J;
+  a.gup = gup;
+  a.gco = gco;
+  a.gco_next = gco_next;
+  a.has_force = has_force;
+  a.pack = pack;
+  a.Ain_next = Ain_next;
+  a.A_next = A_next;
+  const int nb = (m->box.ncells + kBlock - 1) / kBlock;
+  switch (m->lattice) {
+    case VLBM_D2Q9: k_links_moving<D2Q9><<<nb, kBlock, 0, s>>>(a); break;
+    case VLBM_D3Q19: k_links_moving<D3Q19><<<nb, kBlock, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;   // rejected by the caller
+  }
+  return hipGetLastError();
+}
+
+namespace {
+
 // The precompute that allocates nothing keeps its scratch (degenerate-cell
 // flag, per-block diagnostics and their reduction, the g_i box) in this
 // device array.  Every GPU the library runs on holds its own copy until the

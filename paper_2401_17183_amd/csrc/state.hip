@@ -38,6 +38,7 @@ template <class S> struct StateArgs {
   int fc64;
   int have_prev;
   double* partial;     // [blocks][kAuditWords]
+  const double* Ain;   // moving mesh: incoming coefficients of the current state, [Q][d][cells] (else null)
 };
 
 template <class L, class S>
@@ -265,7 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
 #pragma unroll
       for (int i = 0; i < D; ++i) {
         const double ci = L::c(al, i);
-        const double Ao = g.a(opp(al), i);
+        // incoming coefficient: the opposite outgoing one on a static mesh
+        const double Ao = a.Ain ? a.Ain[(al * D + i) * nc + cell] : g.a(opp(al), i);
         inner[i] += (ci - 0.5 * Ao) * n;
         if ((wm >> al) & 1) wall[i] += (2.0 * ci - Ao) * n;
       }
@@ -403,6 +405,7 @@ StateArgs<S> make_args(SimObj* s) {
   a.flag = s->flags;
   a.fcache = s->fcache;
   a.fc64 = fcache_elem(s->p.precision) == 8;
+  a.Ain = s->Ain;
   return a;
 }
 

@@ -118,7 +118,27 @@ hipError_t step_lattice(SimObj* s) {
   }
 }
 
+// One step on a moving mesh (FP64; periodic meshes): the pack holds J,
+// g^{ij}, the outgoing and incoming link coefficients and a_ext of time t.
+template <class L, int B>
+hipError_t step_moving_typed(SimObj* s, const double* pack) {
+  StepArgs<double, double, double> a = make_step_args<double, double, double>(s);
+  a.geo = pack;
+  const int nb = (a.box.ncells + B - 1) / B;
+  k_step64<Moving<L>, double, double, double, 0, false, B><<<nb, B, 0, s->stream>>>(a);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_step_moving(SimObj* s, const double* pack) {
+  switch (s->mesh->lattice) {
+    case VLBM_D2Q9: return step_moving_typed<D2Q9, kBlock>(s, pack);
+    // outgoing and incoming coefficients staged in LDS: 55 KB per 64 threads
+    case VLBM_D3Q19: return step_moving_typed<D3Q19, 64>(s, pack);
+    default: return hipErrorInvalidValue;   // rejected by the caller
+  }
+}
 
 hipError_t launch_step(SimObj* s) {
   switch (s->mesh->lattice) {

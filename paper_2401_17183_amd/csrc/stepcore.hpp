@@ -99,6 +99,19 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
       if constexpr (ST == 0) g.Areg[a][i] = v;
       else lds[((a - 1) * L::D + i) * ST] = v;
     }
+  if constexpr (L::MOVING) {
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a)
+#pragma unroll
+      for (int i = 0; i < L::D; ++i) {
+        const S v = gw[(Pack<L>::AIN + (a - 1) * L::D + i) * kGeoTile];
+        if constexpr (ST == 0) g.Ainreg[a][i] = v;
+        else lds[((L::Q - 1) * L::D + (a - 1) * L::D + i) * ST] = v;
+      }
+    if constexpr (ST == 0)
+#pragma unroll
+      for (int i = 0; i < L::D; ++i) g.Ainreg[0][i] = S(0);
+  }
   if constexpr (ST == 0)
 #pragma unroll
     for (int i = 0; i < L::D; ++i) g.Areg[0][i] = S(0);
@@ -188,9 +201,10 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   int x, y, z;
   cell_coords(a.box, cell, x, y, z);
   // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19); so
-  // does D3Q39 in FP64 (its 114 A words cannot live in registers)
-  constexpr int ST = (sizeof(S) == 4 || L::Q > 21) ? BLOCK : 0;
-  __shared__ S sA[ST ? (Q - 1) * D * BLOCK : 1];
+  // do D3Q39 in FP64 (its 114 A words cannot live in registers) and a moving
+  // 3-D mesh in FP64 (outgoing and incoming coefficients, 108 words)
+  constexpr int ST = (sizeof(S) == 4 || L::Q > 21 || (L::MOVING && D == 3)) ? BLOCK : 0;
+  __shared__ S sA[ST ? (L::MOVING ? 2 : 1) * (Q - 1) * D * BLOCK : 1];
   NR N[Q];
   CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
   gather<L, P, S, T, NR, ST, FF>(a, g, x, y, z, cell, N);

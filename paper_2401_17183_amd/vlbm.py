@@ -95,6 +95,7 @@ _SIGS = {
     "vlbm_init": (C.c_int, [_P, C.POINTER(vlbm_params), _P, _P, _P, C.POINTER(_P)]),
     "vlbm_step": (C.c_int, [_P, C.c_int64]),
     "vlbm_sync": (C.c_int, [_P]),
+    "vlbm_step_moving": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "vlbm_step_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_uint64)]),
     "vlbm_kernel_timing": (C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
     "vlbm_membench": (C.c_int, [C.c_int, C.c_int, C.c_size_t, C.c_int, _P, C.POINTER(C.c_double),
@@ -302,6 +303,21 @@ class Sim:
 
     def step(self, n=1):
         vlbm_step(self.h, int(n))
+
+    def step_moving(self, coords_next, wrap_next=None):
+        """One step with the mesh moving to coords_next (mesh layout; host
+        array or device tensor) and periodic translations wrap_next (d x d)."""
+        torch = _torch()
+        X = _dev(torch, coords_next, (int(np.prod(np.shape(coords_next))),))
+        wr = None
+        if wrap_next is not None:
+            w = np.zeros((3, 3))
+            a = np.asarray(wrap_next, dtype=np.float64)
+            w[: a.shape[0], : a.shape[1]] = a
+            wr = (C.c_double * 9)(*w.ravel())
+        _ready(torch)
+        vlbm_step_moving(self.h, _P(X.data_ptr()), wr)
+        self._keep = X   # the call is asynchronous: keep the input alive until the next call
 
     def sync(self):
         """Wait for the enqueued steps; raises VlbmError(ERR_NOCONVERGE) when a
