@@ -221,7 +221,8 @@ def run_single(args, torch, vlbm):
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
     mesh = vlbm.Mesh.from_workload(w)
     p = vlbm.make_params(w["tau"], body_force=w.get("body_force", (0, 0, 0)), rho_inf=w.get("rho_inf", 1.0),
-                         u_inf=w.get("u_inf", (0, 0, 0)), precision=args.precision, tau_g=args.tau_g)
+                         u_inf=w.get("u_inf", (0, 0, 0)), precision=args.precision, tau_g=args.tau_g,
+                         fp_tol=args.fp_tol)
     rho = w.get("rho")
     u = w.get("u")
     sim = vlbm.Sim(mesh, p, rho=None if rho is None else rho.ravel(),
@@ -506,6 +507,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tau", type=float, default=None,
                     help="channel / O-grid: override the workload's relaxation time")
+    ap.add_argument("--fp-tol", type=float, default=-1.0,
+                    help="stopping tolerance of the per-cell fixed point (default: the library's for the precision)")
     ap.add_argument("--tau-g", type=float, default=None,
                     help="general collision matrix: relaxation time of the non-hydrodynamic part "
                          "(default: BGK; 1 = regularised)")

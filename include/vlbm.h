@@ -303,6 +303,8 @@ int vlbm_reinit(vlbm_sim s, const double* rho, const double* u);
 int vlbm_sim_step_count(vlbm_sim s, int64_t* t);
 
 int vlbm_sim_destroy(vlbm_sim s);
+/* A mesh destroyed while simulations still hold it is released with the last
+ * of them (the handle must not be used again either way). */
 int vlbm_mesh_destroy(vlbm_mesh m);
 
 /* ----------------------------------------------------------------------------

@@ -223,9 +223,7 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
   return ok();
 }
 
-int vlbm_mesh_destroy(vlbm_mesh mh) {
-  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
-  if (!m) return ok();
+static void release_mesh(MeshObj* m) {
   dev_free(m->coords);
   dev_free(m->J);
   dev_free(m->gup);
@@ -233,8 +231,20 @@ int vlbm_mesh_destroy(vlbm_mesh mh) {
   dev_free(m->g);
   dev_free(m->A);
   delete m;
+}
+
+int vlbm_mesh_destroy(vlbm_mesh mh) {
+  MeshObj* m = reinterpret_cast<MeshObj*>(mh);
+  if (!m) return ok();
+  // simulations still hold the mesh: it is released with the last of them
+  if (m->users > 0) {
+    m->destroy_pending = true;
+    return ok();
+  }
+  release_mesh(m);
   return ok();
 }
+
 
 }  // extern "C"
 
@@ -326,7 +336,7 @@ int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double
 }
 
 static void free_sim(SimObj* s) {
-  if (s->mesh) s->mesh->users--;
+  MeshObj* mesh = s->mesh;
   for (double* b : s->mv_box) dev_free(b);
   dev_free(s->mv_J);
   dev_free(s->mv_gup);
@@ -348,6 +358,8 @@ static void free_sim(SimObj* s) {
   dev_free(s->stats);
   delete static_cast<EventPool*>(s->timing);
   delete s;
+  // the last simulation of a mesh whose destruction was asked for releases it
+  if (mesh && --mesh->users == 0 && mesh->destroy_pending) release_mesh(mesh);
 }
 
 int vlbm_sim_destroy(vlbm_sim sh) {

@@ -375,7 +375,8 @@ __device__ __forceinline__ int link_at(const LinkPlan& p, int cell, int& src) {
 // Host-side objects.
 // ---------------------------------------------------------------------------
 struct MeshObj {
-  int users = 0;       // simulations created on the mesh
+  int users = 0;                 // simulations that hold the mesh
+  bool destroy_pending = false;  // vlbm_mesh_destroy was called while simulations held it
   int lattice;
   int d, Q;
   Box box;

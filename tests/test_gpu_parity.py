@@ -343,6 +343,23 @@ def test_degenerate_small_meshes_fp64(w):
     assert err <= 1e-12
 
 
+def test_mesh_destroyed_before_its_simulation():
+    """Destroying a mesh that a simulation still holds leaves the simulation
+    working; the mesh is released with it."""
+    v = _vlbm()
+    w = W.wavy_periodic("D2Q9", (12, 10), 0.1)
+    announce("mesh destroyed before its simulation")
+    m = gpu_mesh(w)
+    s = v.Sim(m, v.make_params(0.8))
+    ref = v.Sim(gpu_mesh(w), v.make_params(0.8))
+    m.close()
+    s.step(5)
+    ref.step(5)
+    assert torch.equal(s.populations(), ref.populations())
+    s.close()
+    ref.close()
+
+
 def test_one_cell_periodic_axis_is_rejected():
     v = _vlbm()
     announce("one-cell periodic axis")
