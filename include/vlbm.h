@@ -91,7 +91,8 @@ int vlbm_lattice_info(int lattice, int32_t* Q, int32_t* d, int32_t* c, double* w
 /* Create a mesh from node coordinates (Sec. 2.1: the node set x(q) on a unit
  * index lattice).
  *  n        host int64[3]: real cells per axis (n[2] = 1 for a 2-D lattice).
- *  coords   host double [m_d]..[m_1][d], m_i = n_i + 2 G on non-periodic axes
+ *  coords   double [m_d]..[m_1][d] in device memory (e.g. a mesh generated
+ *           on the GPU) or host memory, m_i = n_i + 2 G on non-periodic axes
  *           (G ghost node layers per face: 2 for D2Q9 / D3Q19, 4 for D2Q21 /
  *           D3Q39, one more than the longest link), m_i = n_i on periodic axes.
  *  topo     host, faces and wrap translations.  D2Q21 / D3Q39 take walls on
@@ -99,7 +100,9 @@ int vlbm_lattice_info(int lattice, int32_t* Q, int32_t* d, int32_t* c, double* w
  *           straight path: halfway bounce-back from the mirrored source cell)
  *           and no far-field faces; every axis needs at least 3 cells.
  *  dx       the representative spacing of the tangent-vector formula (> 0).
- * The coordinates are copied to the device; nothing is computed yet.
+ * The coordinates are copied into the mesh (the runtime tells device from
+ * host memory by the pointer; the caller keeps its array); nothing is
+ * computed yet.  The FP64 geometry arrays are allocated here.
  * Errors: VLBM_ERR_ARG for bad sizes/faces, VLBM_ERR_UNSUPPORTED for faces a
  * lattice does not take, VLBM_ERR_NOMEM. */
 int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords,

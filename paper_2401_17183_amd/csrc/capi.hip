@@ -210,7 +210,8 @@ int vlbm_mesh_create(int lattice, const int64_t n[3], const double* coords, cons
     delete m;
     return rc;
   }
-  if (hipMemcpy(m->coords, coords, ncoord * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+  // device or host coordinates: the direction follows from the pointer
+  if (hipMemcpy(m->coords, coords, ncoord * sizeof(double), hipMemcpyDefault) != hipSuccess) {
     dev_free(m->coords);
     delete m;
     return fail(VLBM_ERR_DEVICE, "copy of coordinates failed");

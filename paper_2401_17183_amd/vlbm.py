@@ -196,6 +196,10 @@ def _dev(torch, a, shape=None):
     return t.to("cuda").contiguous()
 
 
+def _is_tensor(a):
+    return type(a).__module__.startswith("torch")
+
+
 def _ready(torch):
     """Finish torch's pending work on its current stream: buffers allocated or
     filled there are then safe to hand to a library call on another stream
@@ -220,10 +224,16 @@ class Mesh:
                 topo.face[i][f] = int(faces[i][f])
             for k in range(self.d):
                 topo.wrap[i][k] = float(wrap[i][k])
-        X = np.ascontiguousarray(coords, dtype=np.float64)
         h = _P()
-        vlbm_mesh_create(self.lattice, nn, X.ctypes.data_as(C.POINTER(C.c_double)), C.byref(topo), float(dx),
-                         C.byref(h))
+        torch = _torch() if _is_tensor(coords) else None
+        if torch is not None and coords.is_cuda:   # device coordinates stay on the device
+            X = coords.detach().to(torch.float64).contiguous()
+            _ready(torch)
+            ptr = C.cast(C.c_void_p(X.data_ptr()), C.POINTER(C.c_double))
+        else:
+            X = np.ascontiguousarray(coords.cpu().numpy() if torch is not None else coords, dtype=np.float64)
+            ptr = X.ctypes.data_as(C.POINTER(C.c_double))
+        vlbm_mesh_create(self.lattice, nn, ptr, C.byref(topo), float(dx), C.byref(h))
         self.h = h
         self.report = None
         if precompute:

@@ -65,6 +65,21 @@ def test_geometry_fp64_parity(w):
         assert abs(m.report[k] - v) <= tol * max(1.0, abs(v)), (k, m.report[k], v)
 
 
+@pytest.mark.parametrize("w", [W.tanh_channel_2d(12, 10), W.ogrid_3d(8, 12, 4)], ids=lambda w: w["name"])
+def test_mesh_from_device_coordinates(w):
+    """Node coordinates handed over in device memory (a torch CUDA tensor)
+    give the geometry of the same coordinates from host memory, bit for bit."""
+    v = _vlbm()
+    announce(f"mesh from device coordinates {w['name']}")
+    mh = gpu_mesh(w)
+    X = torch.as_tensor(w["coords"], dtype=torch.float64, device="cuda")
+    md = v.Mesh(w["lattice"], w["n"], X, w["faces"], w["wrap"], w["dx"])
+    assert md.report == mh.report
+    fh, fd = mh.fields(), md.fields()
+    for k in fh:
+        assert torch.equal(fh[k], fd[k]), k
+
+
 def test_degenerate_meshes_are_rejected():
     v = _vlbm()
     w = W.tanh_channel_2d(8, 6)
