@@ -395,7 +395,7 @@ def run_train(args, torch, vlbm):
                    "flop_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(tf / 2500.0, 5), "traffic": None,
-                     "kernel": "k_conv_gemm / k_wgrad (forward, input and weight gradients)"},
+                     "kernel": "k_conv_tile / k_wgrad_tile (forward, input and weight gradients)"},
     }
 
 
@@ -481,7 +481,7 @@ def run_surrogate(args, torch, vlbm):
                    "warm_vs_cold_final_u_rel_l2_max": float(np.max(agree))},
         "roofline": {"bound": "mfma", "achieved": round(flops / train_wall / 1e12, 2), "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": round(flops / train_wall / 1e12 / 2500.0, 5), "traffic": None,
-                     "kernel": "k_conv_gemm / k_wgrad (whole training loop, BF16 MFMA)"},
+                     "kernel": "k_conv_tile / k_wgrad_tile (whole training loop, BF16 MFMA)"},
     }
     net.close()
     return out

@@ -33,9 +33,14 @@ const char* check(const Conv& c);
 
 hipError_t conv_forward(const Conv& c, const uint16_t* x, const uint16_t* skip, const uint16_t* w,
                         const float* bias, uint16_t* y16, float* y32, hipStream_t st);
-// gx (primary input, stored resolution) and gskip accumulate (+=); either may be null
+// gx (primary input, stored resolution) and gskip accumulate (+=); either may be null.
+// With g16 (and gx), the contribution to gx is taken to be its last: g16 = bf16(gx (act > 0))
+// with act_relu, bf16(gx) without, the ReLU gradient of the layer whose output is the
+// primary input (act, g16 in gx's layout), as relu_grad would form it.  assign_gx /
+// assign_gskip: store the product instead of adding it (the tensor's first contribution).
 hipError_t conv_backward_data(const Conv& c, const uint16_t* gy, const uint16_t* wt, float* gx, float* gskip,
-                              hipStream_t st);
+                              hipStream_t st, const uint16_t* act = nullptr, int act_relu = 0,
+                              uint16_t* g16 = nullptr, int assign_gx = 0, int assign_gskip = 0);
 // gw [C_out][9][C_in + C_skip] and gb [C_out] accumulate (+=).  With a device
 // workspace of at least conv_backward_weight_workspace(c) floats the partial
 // sums are added in a fixed order (bit-reproducible); without one, with FP32
@@ -45,6 +50,11 @@ hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t
                                 int64_t work_floats = 0);
 int64_t conv_backward_weight_workspace(const Conv& c);
 hipError_t pack_weights(const Conv& c, const float* w, uint16_t* w16, uint16_t* wt16, hipStream_t st);
+// pack_weights for nlayers <= kMaxPackLayers layers in one launch; layer l's
+// weights start at w_off[l] in params, w16 and wt16
+constexpr int kMaxPackLayers = 32;
+hipError_t pack_weights_all(int nlayers, const Conv* convs, const int64_t* w_off, const float* params, uint16_t* w16,
+                            uint16_t* wt16, hipStream_t st);
 hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                 float c1, float c2, hipStream_t st);
 hipError_t fill(float* p, int64_t n, float v, hipStream_t st);

@@ -2,10 +2,12 @@
 // gradient, weight gradient, weight packing), Adam, and the whole 5-level
 // encoder-decoder as one object that owns its parameters, moments,
 // activations and gradients in device memory.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "nn.hpp"
@@ -83,6 +85,7 @@ struct Net {
   float* out32 = nullptr;    // head output [pixels][kOut]
   float* gout = nullptr;
   uint16_t* gy16 = nullptr;
+  uint16_t* gy16b = nullptr;  // the next layer's BF16 output gradient, formed by this layer's input gradient
   double* loss = nullptr;
   double* lossp = nullptr;   // per-block loss partials (ordered reduction)
   float* wwork = nullptr;    // partial weight-gradient tiles (ordered reduction)
@@ -154,7 +157,7 @@ void free_net(Net* n) {
   if (!n) return;
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   void* ptrs[] = {n->params, n->grads, n->m, n->v, n->w16, n->wt16, n->in16, n->act, n->gact, n->out32,
-                  n->gout, n->gy16, n->loss, n->lossp, n->wwork};
+                  n->gout, n->gy16, n->gy16b, n->loss, n->lossp, n->wwork};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete n;
@@ -173,8 +176,14 @@ const uint16_t* input_of(const Net* n, int idx) {
 float* grad_of(const Net* n, int idx) { return idx < 0 ? nullptr : n->gact + n->layers[idx].act_off; }
 
 int pack_all(Net* n) {
-  for (const Layer& L : n->layers)
-    NN_TRY(vlbm::nn::pack_weights(L.c, n->params + L.w_off, n->w16 + L.w_off, n->wt16 + L.w_off, n->stream));
+  std::vector<Conv> convs;
+  std::vector<int64_t> offs;
+  for (const Layer& L : n->layers) {
+    convs.push_back(L.c);
+    offs.push_back(L.w_off);
+  }
+  NN_TRY(vlbm::nn::pack_weights_all((int)convs.size(), convs.data(), offs.data(), n->params, n->w16, n->wt16,
+                                    n->stream));
   return VLBM_OK;
 }
 
@@ -200,20 +209,45 @@ int gradient(Net* n, const float* x, const float* t, int batch) {
   if (rc) return rc;
   const int64_t pixels = (int64_t)batch * n->H * n->W;
   NN_TRY(vlbm::nn::fill(n->grads, n->nparams, 0.f, n->stream));
-  NN_TRY(vlbm::nn::fill(n->gact, n->act_total, 0.f, n->stream));
+  // a layer output's gradient is stored by its first contribution in backward
+  // order (its highest-numbered consumer) and added to by the others, so it
+  // needs no clearing
+  std::vector<int> first(n->layers.size(), -1);
+  for (int i = 0; i < (int)n->layers.size(); ++i) {
+    const Layer& L = n->layers[i];
+    if (L.src >= 0) first[L.src] = std::max(first[L.src], i);
+    if (L.skip >= 0) first[L.skip] = std::max(first[L.skip], i);
+  }
   NN_TRY(vlbm::nn::mse(n->out32, t, n->gout, n->loss, pixels, kOut, kTargets, n->lossp, n->stream));
   const int last = (int)n->layers.size() - 1;
+  // Layer i's output gradient is complete once layer i + 1, its last consumer
+  // in backward order, has added its input gradient (a decoder reading it as
+  // skip runs earlier); that input gradient then also forms the BF16 ReLU
+  // gradient layer i starts from, into the second buffer.
+  uint16_t* gcur = n->gy16;
+  uint16_t* gnext = n->gy16b;
+  bool ready = false;
   for (int i = last; i >= 0; --i) {
     const Layer& L = n->layers[i];
     const int64_t nout = L.out_per_sample * batch;
-    const float* g = i == last ? n->gout : n->gact + L.act_off;
-    NN_TRY(vlbm::nn::relu_grad(g, i == last ? nullptr : n->act + L.act_off, n->gy16, nout, L.c.relu, n->stream));
+    if (!ready) {
+      const float* g = i == last ? n->gout : n->gact + L.act_off;
+      NN_TRY(vlbm::nn::relu_grad(g, i == last ? nullptr : n->act + L.act_off, gcur, nout, L.c.relu, n->stream));
+    }
     const uint16_t* skip = L.skip >= 0 ? input_of(n, L.skip) : nullptr;
-    NN_TRY(vlbm::nn::conv_backward_weight(L.c, input_of(n, L.src), skip, n->gy16, n->grads + L.w_off,
+    NN_TRY(vlbm::nn::conv_backward_weight(L.c, input_of(n, L.src), skip, gcur, n->grads + L.w_off,
                                           n->grads + L.b_off, n->stream, n->wwork, n->wwork_n));
-    if (L.src >= 0)
-      NN_TRY(vlbm::nn::conv_backward_data(L.c, n->gy16, n->wt16 + L.w_off, grad_of(n, L.src),
-                                          L.skip >= 0 ? grad_of(n, L.skip) : nullptr, n->stream));
+    ready = false;
+    if (L.src >= 0) {
+      const Layer& S = n->layers[L.src];
+      const bool fuse = L.src == i - 1;
+      NN_TRY(vlbm::nn::conv_backward_data(L.c, gcur, n->wt16 + L.w_off, grad_of(n, L.src),
+                                          L.skip >= 0 ? grad_of(n, L.skip) : nullptr, n->stream,
+                                          fuse ? n->act + S.act_off : nullptr, S.c.relu, fuse ? gnext : nullptr,
+                                          first[L.src] == i, L.skip >= 0 && first[L.skip] == i));
+      ready = fuse;
+    }
+    std::swap(gcur, gnext);
   }
   return VLBM_OK;
 }
@@ -328,6 +362,7 @@ int vlbm_surrogate_create(int height, int width, int max_batch, const float* par
   A(alloc(&n->out32, pixels * kOut));
   A(alloc(&n->gout, pixels * kOut));
   A(alloc(&n->gy16, n->max_out * max_batch));
+  A(alloc(&n->gy16b, n->max_out * max_batch));
   A(alloc(&n->loss, 1));
   A(alloc(&n->lossp, vlbm::nn::kMseBlocks));
   // the weight gradients add their split partial sums in a fixed order, so

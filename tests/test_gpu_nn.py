@@ -38,6 +38,9 @@ CONVS = [  # (N, H, W, c_in, c_skip, up, stride, c_out, relu)
     (1, 8, 12, 24, 16, True, 1, 40, True),
     (3, 8, 8, 256, 0, False, 1, 64, False),
     (2, 6, 10, 64, 0, False, 2, 72, True),
+    (2, 20, 36, 64, 32, True, 1, 64, True),   # several spatial tiles, ragged, two 32-channel sources
+    (3, 19, 37, 32, 0, False, 1, 96, False),  # ragged tiles in both directions, two column tiles
+    (3, 17, 35, 32, 0, False, 2, 64, True),   # stride 2 over several tiles, odd sizes (uneven parity classes)
 ]
 
 

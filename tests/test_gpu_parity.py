@@ -169,6 +169,55 @@ def test_long_axes_stream_only_is_bit_exact(lattice, n):
     assert np.array_equal(cpu(s.populations()), os_.N.reshape(os_.lat.Q, -1))
 
 
+def _poiseuille_gpu(n2, steps, audit_every=0):
+    w = W.tanh_channel_2d(64, n2)
+    rho, u = W.poiseuille_fields(w)
+    s, m = gpu_sim(w, rho=rho.ravel(), u=u.reshape(2, -1), audit_every=audit_every)
+    if audit_every:
+        s.audit_now()
+    s.step(steps)
+    ux = cpu(s.moments()["u"])[0].reshape(n2, 64)
+    return s, m, ux, u[0]
+
+
+def test_poiseuille_2000_steps_against_analytic_oracle_and_mass():
+    """D2Q9 plane Poiseuille on the 64x32 tanh(2) channel, FP64, tau 0.8,
+    G 1e-6, started at the analytic parabola (Sec. 3, nu = (tau - 1/2) T0):
+    after 2000 steps the profile is x-invariant, equals the oracle's (a 4-wide
+    copy of the same channel: the flow does not depend on x) to 1e-12, stays
+    within 3e-3 (rel-L2) of the parabola, and the FP64 mass drifts by at most
+    1e-13; the departure falls at second order under wall-normal refinement
+    (16, 32, 64 cells)."""
+    announce("poiseuille 64x32 fp64 x2000")
+    s, m, ux, ua = _poiseuille_gpu(32, 2000, audit_every=100)
+    assert np.max(np.abs(ux - ux[:, :1])) <= 1e-14
+    wo = W.tanh_channel_2d(4, 32)
+    o = sim_of(wo)
+    o.init(*W.poiseuille_fields(wo))
+    o.step(2000)
+    uo = o.moments()["u"][0]
+    assert np.max(np.abs(ux[:, :4] - uo)) <= 1e-12 * np.max(np.abs(uo)), np.max(np.abs(ux[:, :4] - uo))
+    err = np.linalg.norm(ux - ua) / np.linalg.norm(ua)
+    print("poiseuille 64x32 rel-L2 departure after 2000 steps", err)
+    assert err < 3e-3
+    aud = s.audits()
+    assert aud[0]["step"] == 0 and aud[-1]["step"] == 2000 and len(aud) >= 21
+    drift = max(abs(a["mass"] / aud[0]["mass"] - 1) for a in aud)
+    print("poiseuille FP64 mass drift", drift)
+    assert drift <= 1e-13
+    s.close()
+    m.close()
+    e = []
+    for n2 in (16, 32, 64):
+        announce(f"poiseuille 64x{n2} fp64 x2000 (refinement)")
+        s, m, ux, ua = _poiseuille_gpu(n2, 2000)
+        e.append(np.linalg.norm(ux - ua) / np.linalg.norm(ua))
+        s.close()
+        m.close()
+    print("poiseuille departures under refinement", e)
+    assert e[0] / e[1] > 3.5 and e[1] / e[2] > 3.5, e
+
+
 @pytest.mark.parametrize("w,steps", [(W.tanh_channel_2d(64, 32), 100), (W.wavy_channel_3d(16, 12, 8), 100),
                                      (W.ogrid_3d(8, 96, 4, rmax=1.5, dx_factor=1.3), 50)],
                          ids=lambda x: str(x) if isinstance(x, int) else x["name"])
