@@ -398,15 +398,15 @@ __global__ void k_sum_slices(const float* __restrict__ src, float* dst, int64_t 
 }
 
 // gw[e] += sum over z of part[z][e] (e < n), gb[e - n] likewise (n <= e < m),
-// in slice order.
+// in slice order; with assign, = instead of +=.
 __global__ void k_wgrad_reduce(const float* __restrict__ part, float* gw, float* gb, int64_t n, int64_t m,
-                               int slices) {
+                               int slices, int assign) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     float acc = 0.f;
 #pragma unroll 8
     for (int z = 0; z < slices; ++z) acc += part[z * m + e];
-    if (e < n) gw[e] += acc;
-    else gb[e - n] += acc;
+    if (e < n) gw[e] = assign ? acc : gw[e] + acc;
+    else gb[e - n] = assign ? acc : gb[e - n] + acc;
   }
 }
 
@@ -523,6 +523,7 @@ __global__ __launch_bounds__(kThreads) void k_mse(const float* __restrict__ out,
 __global__ __launch_bounds__(64) void k_loss_sum(const double* __restrict__ part, int nblocks, double inv_count,
                                                  double* loss) {
   double s = 0.0;
+#pragma unroll 16
   for (int i = threadIdx.x; i < nblocks; i += 64) s += part[i];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (threadIdx.x == 0) *loss = s * inv_count;
@@ -1117,7 +1118,7 @@ int64_t conv_backward_weight_workspace(const Conv& c) {
 }
 
 hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t* skip, const uint16_t* gy,
-                                float* gw, float* gb, hipStream_t st, float* work, int64_t work_floats) {
+                                float* gw, float* gb, hipStream_t st, float* work, int64_t work_floats, int assign) {
   const WgradShape w = wgrad_shape(c);
   WgradTile t{};
   t.x = x;
@@ -1144,6 +1145,11 @@ hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t
   const int64_t n = (int64_t)c.cout * 9 * t.ct, m = n + c.cout;
   const bool ordered = work && work_floats >= reduce_workspace(splits, m);
   t.part = ordered ? work : nullptr;
+  if (assign && !ordered) {   // the atomic path adds
+    hipError_t e = fill(gw, n, 0.f, st);
+    if (e == hipSuccess) e = fill(gb, c.cout, 0.f, st);
+    if (e != hipSuccess) return e;
+  }
   t.slice = m;
   t.gw = gw;
   t.gb = gb;
@@ -1169,7 +1175,7 @@ hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t
       src = dst;
       slices = groups;
     }
-    k_wgrad_reduce<<<grid_for(m), kThreads, 0, st>>>(src, gw, gb, n, m, (int)slices);
+    k_wgrad_reduce<<<grid_for(m), kThreads, 0, st>>>(src, gw, gb, n, m, (int)slices, assign);
   }
   return hipGetLastError();
 }

@@ -41,13 +41,13 @@ hipError_t conv_forward(const Conv& c, const uint16_t* x, const uint16_t* skip, 
 hipError_t conv_backward_data(const Conv& c, const uint16_t* gy, const uint16_t* wt, float* gx, float* gskip,
                               hipStream_t st, const uint16_t* act = nullptr, int act_relu = 0,
                               uint16_t* g16 = nullptr, int assign_gx = 0, int assign_gskip = 0);
-// gw [C_out][9][C_in + C_skip] and gb [C_out] accumulate (+=).  With a device
+// gw [C_out][9][C_in + C_skip] and gb [C_out] accumulate (+=), or are stored with assign.  With a device
 // workspace of at least conv_backward_weight_workspace(c) floats the partial
 // sums are added in a fixed order (bit-reproducible); without one, with FP32
 // atomics.
 hipError_t conv_backward_weight(const Conv& c, const uint16_t* x, const uint16_t* skip, const uint16_t* gy,
                                 float* gw, float* gb, hipStream_t st, float* work = nullptr,
-                                int64_t work_floats = 0);
+                                int64_t work_floats = 0, int assign = 0);
 int64_t conv_backward_weight_workspace(const Conv& c);
 hipError_t pack_weights(const Conv& c, const float* w, uint16_t* w16, uint16_t* wt16, hipStream_t st);
 // pack_weights for nlayers <= kMaxPackLayers layers in one launch; layer l's

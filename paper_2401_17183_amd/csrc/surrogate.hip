@@ -208,7 +208,6 @@ int gradient(Net* n, const float* x, const float* t, int batch) {
   int rc = forward(n, x, batch);
   if (rc) return rc;
   const int64_t pixels = (int64_t)batch * n->H * n->W;
-  NN_TRY(vlbm::nn::fill(n->grads, n->nparams, 0.f, n->stream));
   // a layer output's gradient is stored by its first contribution in backward
   // order (its highest-numbered consumer) and added to by the others, so it
   // needs no clearing
@@ -235,8 +234,9 @@ int gradient(Net* n, const float* x, const float* t, int batch) {
       NN_TRY(vlbm::nn::relu_grad(g, i == last ? nullptr : n->act + L.act_off, gcur, nout, L.c.relu, n->stream));
     }
     const uint16_t* skip = L.skip >= 0 ? input_of(n, L.skip) : nullptr;
+    // each layer's weight and bias gradients are formed once: stored, not added
     NN_TRY(vlbm::nn::conv_backward_weight(L.c, input_of(n, L.src), skip, gcur, n->grads + L.w_off,
-                                          n->grads + L.b_off, n->stream, n->wwork, n->wwork_n));
+                                          n->grads + L.b_off, n->stream, n->wwork, n->wwork_n, 1));
     ready = false;
     if (L.src >= 0) {
       const Layer& S = n->layers[L.src];

