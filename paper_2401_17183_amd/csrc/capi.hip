@@ -422,9 +422,9 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   if ((rc = dev_alloc(&s->audit_partial, sizeof(double) * s->audit_blocks * audit_words()))) return bail(rc);
   if ((rc = dev_alloc(&s->u_prev, sizeof(double) * nc * d))) return bail(rc);
   if ((rc = dev_alloc(&s->flags, sizeof(int) * 4))) return bail(rc);
-  if ((rc = dev_alloc(&s->stats, sizeof(unsigned long long) * 4))) return bail(rc);
+  if ((rc = dev_alloc(&s->stats, sizeof(unsigned long long) * 4 * kStatSlots))) return bail(rc);
   hipError_t e = hipMemsetAsync(s->flags, 0, sizeof(int) * 4, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * 4, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * 4 * kStatSlots, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->fcache, 0, nc * d * fcache_elem(s->p.precision), s->stream);
@@ -622,11 +622,14 @@ int vlbm_step_stats(vlbm_sim sh, int enable, uint64_t* out) {
   SimObj* s = reinterpret_cast<SimObj*>(sh);
   if (!s) return fail(VLBM_ERR_ARG, "null sim");
   if (out) {
-    unsigned long long h[4];
+    unsigned long long h[4 * kStatSlots];
     HIP_TRY(hipMemcpyAsync(h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(hipMemsetAsync(s->stats, 0, sizeof(h), s->stream));
-    for (int k = 0; k < 4; ++k) out[k] = h[k];
+    for (int k = 0; k < 4; ++k) {
+      out[k] = 0;
+      for (int q = 0; q < kStatSlots; ++q) out[k] += h[4 * q + k];
+    }
   }
   s->stats_on = enable ? 1 : 0;
   return ok();

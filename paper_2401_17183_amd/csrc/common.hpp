@@ -464,7 +464,7 @@ struct SimObj {
   int have_u_prev = 0;
   int* flags = nullptr;         // device int[4]: 0 = unconverged cells of a dry run (init, moments),
                                 //                2 = unconverged cell-steps of the step kernel
-  unsigned long long* stats = nullptr;   // device [4]: fixed-point statistics of the steps (when stats_on)
+  unsigned long long* stats = nullptr;   // device [kStatSlots][4]: fixed-point statistics of the steps (when stats_on)
   int stats_on = 0;
   // moving mesh (vlbm_step_moving): g_i boxes of the times t - 1, t, t + 1,
   // the real-cell geometry of t + 1, the incoming coefficients of the current
@@ -511,6 +511,8 @@ inline float pop_scale(int precision, double max_J) {
 inline size_t fcache_elem(int precision) { return precision == VLBM_FP64 ? 8 : 4; }
 // Re-basing period of the references (steps; vlbm_params.rebase_every: 0 =
 // default, < 0 = never).
+// copies of the fixed-point statistics counters (by block), summed on the host
+constexpr int kStatSlots = 64;
 constexpr int kDefaultRebase = 10;
 inline int rebase_period(const vlbm_params& p) { return p.rebase_every == 0 ? kDefaultRebase : p.rebase_every; }
 

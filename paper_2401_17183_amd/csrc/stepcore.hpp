@@ -58,10 +58,13 @@ __device__ __forceinline__ void add_iteration_stats(unsigned long long* stats, i
   }
   const int lane = (int)(threadIdx.x & 63);
   if (lane == __ffsll((long long)act) - 1) {
-    atomicAdd(&stats[0], sum);
-    atomicAdd(&stats[1], (unsigned long long)mx);
-    atomicAdd(&stats[2], (unsigned long long)__popcll(act));
-    atomicAdd(&stats[3], 1ull);
+    // kStatSlots copies of the four counters, chosen by block: one address
+    // shared by every wave of a launch serialises their atomics
+    unsigned long long* q = stats + 4 * (blockIdx.x & (kStatSlots - 1));
+    atomicAdd(&q[0], sum);
+    atomicAdd(&q[1], (unsigned long long)mx);
+    atomicAdd(&q[2], (unsigned long long)__popcll(act));
+    atomicAdd(&q[3], 1ull);
   }
 }
 

@@ -170,10 +170,10 @@ def bump_channel_2d(n1, n2, bump, stretch, tau, G=1e-6, H=1.0, max_slope=0.15):
     }
 
 
-def batch_meshes(count=256, seed=SEED):
+def batch_meshes(count=256, seed=SEED, max_slope=0.15):
     """The uneven batch: n1 ~ U{32..256}, n2 ~ U{16..128}, bump ~ U[0, 0.3] H
-    (then capped by the wall-slope limit of bump_channel_2d), stretch ~ U[1, 3],
-    tau ~ U[0.55, 1.0]."""
+    (then capped by the wall-slope limit max_slope of bump_channel_2d; None:
+    uncapped), stretch ~ U[1, 3], tau ~ U[0.55, 1.0]."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
@@ -182,7 +182,7 @@ def batch_meshes(count=256, seed=SEED):
         bump = float(rng.uniform(0.0, 0.3))
         s = float(rng.uniform(1.0, 3.0))
         tau = float(rng.uniform(0.55, 1.0))
-        out.append(bump_channel_2d(n1, n2, bump, s, tau))
+        out.append(bump_channel_2d(n1, n2, bump, s, tau, max_slope=np.inf if max_slope is None else max_slope))
     return out
 
 
