@@ -327,6 +327,17 @@ struct LinkPlan {
   unsigned wall_lo, wall_hi, far_lo, far_hi;
 };
 
+// the cell lies on a far-field face (so some of its links come from beyond it)
+template <class L>
+__device__ __forceinline__ bool on_farfield_face(const Box& b, int x, int y, int z) {
+  const int q[3] = {x, y, z};
+  bool f = false;
+#pragma unroll
+  for (int i = 0; i < L::D; ++i)
+    f = f || (q[i] == 0 && b.face[i][0] == VLBM_FARFIELD) || (q[i] == b.n[i] - 1 && b.face[i][1] == VLBM_FARFIELD);
+  return f;
+}
+
 template <class L>
 __device__ __forceinline__ LinkPlan link_plan(const Box& b, int x, int y, int z) {
   const int q[3] = {x, y, z};

@@ -240,7 +240,16 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   __shared__ S sA[ST ? (L::MOVING ? 2 : 1) * (Q - 1) * D * BLOCK : 1];
   NR N[Q];
   CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
-  gather<L, P, S, T, NR, ST, FF>(a, g, x, y, z, cell, N);
+  // a wavefront without a far-field cell takes the gather compiled without the
+  // far-field fill: with the fill in the same code, the compiler issues each
+  // direction's loads only after the previous direction's data arrived
+  // (measured on the O-grid, where three wavefronts in four have no far-field
+  // cell: the FP32 step waited five times longer per wavefront than on the
+  // channel)
+  bool ffwave = false;
+  if constexpr (FF == 2 && L::SPEED == 1) ffwave = a.has_ff && __ballot(on_farfield_face<L>(a.box, x, y, z)) != 0ull;
+  if (ffwave) gather<L, P, S, T, NR, ST, FF>(a, g, x, y, z, cell, N);
+  else gather<L, P, S, T, NR, ST, (FF == 2 ? 0 : FF)>(a, g, x, y, z, cell, N);
   if (a.stream_only) {
 #pragma unroll
     for (int al = 0; al < Q; ++al) store_slot<L>(a, al, cell, N[al]);
@@ -275,7 +284,8 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
     pin(yr);
     pin(zr);
     pin(cr);
-    gather<L, P, S, T, NR, ST, FF>(a, g, xr, yr, zr, cr, N);
+    if (ffwave) gather<L, P, S, T, NR, ST, FF>(a, g, xr, yr, zr, cr, N);
+    else gather<L, P, S, T, NR, ST, (FF == 2 ? 0 : FF)>(a, g, xr, yr, zr, cr, N);
   }
   T Np[Q];
   if constexpr (PopCodec<P>::shifted) {
