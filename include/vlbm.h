@@ -100,6 +100,8 @@ int vlbm_lattice_info(int lattice, int32_t* Q, int32_t* d, int32_t* c, double* w
  *           straight path: halfway bounce-back from the mirrored source cell)
  *           and no far-field faces; every axis needs at least 3 cells.
  *  dx       the representative spacing of the tangent-vector formula (> 0).
+ * The ghost layer count is the lattice's (it is not an argument: fewer
+ * layers cannot feed the longest link's tangent vectors, more are unused).
  * The coordinates are copied into the mesh (the runtime tells device from
  * host memory by the pointer; the caller keeps its array); nothing is
  * computed yet.  The FP64 geometry arrays are allocated here.
@@ -123,8 +125,12 @@ typedef struct {
  * ghost layer, then the link coefficients
  *   A^i_a(q) = sum_j c_a^j Theta^i_j(q + c_a, q) = [e_a(q + c_a) - e_a(q)] . g^i(q)
  * (eqs. (lattice), (gamma)) on real cells.  Synchronises the stream and fills
- * rep (host, may be NULL).  Errors: VLBM_ERR_MESH when some |D_i - D_-i| = 0 or
- * J <= 0 (reorder axes for a positive handedness), VLBM_ERR_DEVICE. */
+ * rep (host, may be NULL).  The coefficients A are always precomputed and
+ * stored (there is no variant that forms them from g_i inside the step: from
+ * FP32 g_i their difference of nearly equal tangent vectors would lose to
+ * cancellation what the stored FP64-formed A keeps).
+ * Errors: VLBM_ERR_MESH when some |D_i - D_-i| = 0 or J <= 0 (reorder axes
+ * for a positive handedness), VLBM_ERR_DEVICE. */
 int vlbm_geometry_precompute(vlbm_mesh m, void* stream, vlbm_geom_report* rep);
 
 /* vlbm_geometry_precompute for callers that cannot allocate device memory
