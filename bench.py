@@ -38,12 +38,14 @@ def algorithmic_bytes_per_cell(Q, d, precision, has_force, has_farfield=False):
     once and written once, the packed per-cell geometry words (J, g^{ij} upper,
     A^i_a for a >= 1, a_ext when a body force acts, U_inf when there is a far
     field; FP64 words for FP64 storage, FP32 otherwise, with a second FP32
-    word per g^{ij} for FP32 storage, whose arithmetic is FP64), and for the deviation
+    word per g^{ij} for FP32 storage, whose arithmetic is FP64, and a_ext
+    always there: it also cancels the FP32 rounding of A), and for the deviation
     storage modes the Q 16-bit references of the slots (each read by its
     writer and, at the offset of the population, by its reader: one array)."""
     sb = STORAGE_BYTES[precision]
     gb = 8 if precision == "fp64" else 4
-    words = 1 + d * (d + 1) // 2 + (Q - 1) * d + (d if has_force else 0) + (d if has_farfield else 0)
+    aext = has_force or precision == "fp32"
+    words = 1 + d * (d + 1) // 2 + (Q - 1) * d + (d if aext else 0) + (d if has_farfield else 0)
     if precision == "fp32":   # FP64 arithmetic on FP32 words: g^{ij} as a hi + lo pair
         words += d * (d + 1) // 2
     refs = Q * 2 if precision in SHIFTED else 0

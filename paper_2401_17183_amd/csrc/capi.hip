@@ -398,6 +398,7 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   const int d = m->d;
   for (int k = 0; k < d; ++k)
     if (p->body_force[k] != 0.0) s->has_force = 1;
+  s->comp_A = s->p.precision == VLBM_FP32;
   for (int i = 0; i < d; ++i)
     for (int f = 0; f < 2; ++f)
       if (m->box.face[i][f] == VLBM_FARFIELD) s->has_farfield = 1;

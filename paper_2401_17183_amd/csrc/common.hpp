@@ -465,6 +465,7 @@ struct SimObj {
   void* fcache = nullptr;   // [d][cells]: converged inertial force of the last step (fixed-point start),
                             // FP64 with FP64 storage, FP32 otherwise
   int has_force = 0, has_farfield = 0;
+  int comp_A = 0;   // FP32 words, FP64 arithmetic: the a_ext words also cancel the rounding of A
   // audits
   void* audit_ring = nullptr;   // device vlbm_audit[cap]
   int audit_cap = 0;

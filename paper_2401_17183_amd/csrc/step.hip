@@ -33,10 +33,20 @@ template <class L, class S, class T> constexpr int block_for() {
 
 // Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
 // a_ext^i = G . g^i, U_inf^i = u_inf . g^i.
+//
+// comp (FP32 words, FP64 arithmetic): a_ext also cancels the rounding of A.
+// With dA = fl32(A) - A, eq. (compo-constr) applied to a fluid at rest
+// (N = N' = J rho f^eq(rho = 1, U = Ut = 0)) gives the extra force rho kappa,
+//   kappa^i = -1/2 sum_a (dA^i_a + dA^i_opp(a)) f_a = -1/2 sum_a dA^i_a (f_a + f_opp(a)).
+// The velocity-linear part of f^eq does not reach that sum (dA_a + dA_opp(a)
+// is even in c_a, c_a . U odd), and the force enters every step as
+// F + rho a_ext, so storing a_ext - kappa cancels the rounding up to second
+// order in the velocity.  Without it the rounding of A acts as a spurious
+// body force on strongly stretched meshes (a 20:1 O-grid).
 template <class L, class S>
 __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const double* gup, const double* gco,
                                                  const double* A, double G0, double G1, double G2, double u0,
-                                                 double u1, double u2, int has_force, int has_ff, S* geo) {
+                                                 double u1, double u2, int has_force, int comp, int has_ff, S* geo) {
   constexpr int D = L::D;
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   if (cell >= box.ncells) return;
@@ -51,6 +61,23 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
     }
   for (int al = 1; al < L::Q; ++al)
     for (int i = 0; i < D; ++i) geo[pack_index<L>(Pack<L>::A + (al - 1) * D + i, cell)] = S(A[(al * D + i) * nc + cell]);
+  double kappa[D] = {};
+  if constexpr (sizeof(S) < sizeof(double)) {
+    if (comp) {
+      CellGeo<L, double> g;
+      for (int k = 0; k < nup<D>(); ++k) g.gup[k] = 0;
+      for (int i = 0; i < D; ++i)
+        for (int j = i; j < D; ++j) g.gup[up<D>(i, j)] = gup[(i * D + j) * nc + cell];
+      const double rest[D] = {};
+      double f[L::Q];
+      feq_all<L, double, double, 0>(g, eq_coef<L, double, double, 0>(g, 1.0, rest, rest), f);
+      for (int al = 1; al < L::Q; ++al)
+        for (int i = 0; i < D; ++i) {
+          const double a = A[(al * D + i) * nc + cell];
+          kappa[i] -= 0.5 * (double(S(a)) - a) * (f[al] + f[opp(al)]);
+        }
+    }
+  }
   const double G[3] = {G0, G1, G2};
   const double ui[3] = {u0, u1, u2};
   for (int i = 0; i < D; ++i) {
@@ -59,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
       ae += G[k] * gco[(i * D + k) * nc + cell];
       uc += ui[k] * gco[(i * D + k) * nc + cell];
     }
-    if (has_force) geo[pack_index<L>(Pack<L>::AEXT + i, cell)] = S(ae);
+    if (has_force || comp) geo[pack_index<L>(Pack<L>::AEXT + i, cell)] = S(ae - kappa[i]);
     if (has_ff) geo[pack_index<L>(Pack<L>::UINF + i, cell)] = S(uc);
   }
 }
@@ -98,7 +125,7 @@ hipError_t pack_typed(SimObj* s) {
   const int nb = (m->box.ncells + kBlock - 1) / kBlock;
   k_pack<L, S><<<nb, kBlock, 0, s->stream>>>(m->box, m->J, m->gup, m->gco, m->A, s->p.body_force[0],
                                               s->p.body_force[1], s->p.body_force[2], s->p.u_inf[0],
-                                              s->p.u_inf[1], s->p.u_inf[2], s->has_force, s->has_farfield,
+                                              s->p.u_inf[1], s->p.u_inf[2], s->has_force, s->comp_A, s->has_farfield,
                                               static_cast<S*>(s->geo));
   return hipGetLastError();
 }

@@ -326,7 +326,7 @@ inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   // roundoff: take at least two iterations there.
   a.min_iter = sizeof(T) == 4 ? 2 : 1;
   a.stream_only = s->p.stream_only;
-  a.has_force = s->has_force;
+  a.has_force = s->has_force || s->comp_A;   // the step reads the a_ext words
   a.has_ff = s->has_farfield;
   a.flags = s->flags + 2;   // the step kernel's own count of unconverged cell-steps
   a.stats = s->stats_on ? s->stats : nullptr;

@@ -708,12 +708,7 @@ def test_fp16s_range_follows_cell_volume():
     assert ratio <= 1.0, ratio
 
 
-@pytest.mark.parametrize("precision,bound", [
-    pytest.param("fp32", 1e-5, marks=pytest.mark.xfail(
-        strict=True, reason="measured 6.3e-6 / 1.26e-5 after 50 / 100 steps: the FP32 rounding of the link "
-                            "coefficients A (an emulation with only A rounded gives the same 6.3e-6) acts as a "
-                            "spurious inertial force on this mesh")),
-    ("fp16s", 1e-3), ("bf16s", None)])
+@pytest.mark.parametrize("precision,bound", [("fp32", 1e-5), ("fp16s", 1e-3), ("bf16s", None)])
 def test_ogrid_precision_study_against_stored_oracle(precision, bound):
     """Storage precisions on the O-grid, against the FP64 oracle: a radially
     faithful 256x128x2 replica of the 256x512x64 O-grid workload (the same
