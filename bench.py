@@ -258,6 +258,26 @@ def _copy_ref(torch, out, vlbm):
     out["config"]["copy_ref_grid"] = grid
 
 
+# Seconds of load before each measured run of steps: the GPU lowers its clocks
+# within about 10 ms of idling (the host-side state copies of this script idle
+# it for much longer) and needs some 40 ms of sustained load to raise them
+# again; a 20-step window of the channel started from idle ran at 0.59 ms per
+# step against 0.48 ms right after other work.
+DEVICE_WARMUP_S = 0.3
+
+
+def _device_warmup(torch, sim, seconds=DEVICE_WARMUP_S):
+    """Keep the device busy for about `seconds` with `sim`, a separate copy of
+    the workload (its state is never measured), and return the steps it ran."""
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        sim.step(20)
+        torch.cuda.synchronize()
+        n += 20
+    return n
+
+
 def collision_name(tau_g):
     if tau_g is None:
         return "BGK"
@@ -277,12 +297,17 @@ def run_single(args, torch, vlbm):
     u = w.get("u")
     sim = vlbm.Sim(mesh, p, rho=None if rho is None else rho.ravel(),
                    u=None if u is None else u.reshape(mesh.d, -1))
+    # a second copy of the workload, stepped only to load the device before
+    # each measured run (see DEVICE_WARMUP_S)
+    heat = vlbm.Sim(mesh, p, rho=None if rho is None else rho.ravel(),
+                    u=None if u is None else u.reshape(mesh.d, -1))
     cells = mesh.ncells
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()   # the Sim launches on torch's current stream
     blob = sim.save()                      # the state the timed steps start from
+    heat_steps = _device_warmup(torch, heat)
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ms = _timed(torch, stream, sim.step, args.steps)
@@ -300,6 +325,7 @@ def run_single(args, torch, vlbm):
     # HIP events around its launches, then the fixed point's iteration counts
     print("[bench] kernel durations and fixed-point statistics of the same steps", file=sys.stderr, flush=True)
     sim.restore(blob)
+    _device_warmup(torch, heat)
     sim.kernel_timing(True)
     sim.step(args.steps)
     kt = sim.kernel_timing(False)
@@ -308,6 +334,7 @@ def run_single(args, torch, vlbm):
     sim.step(args.steps)
     st = sim.step_stats(False)
     del blob
+    heat.close()
     k_ms = kt["step_ms"] / max(kt["step_launches"], 1)
     rb_ms = kt["rebase_ms"] / kt["rebase_launches"] if kt["rebase_launches"] else None
     has_force = any(v != 0 for v in w.get("body_force", (0, 0, 0)))
@@ -332,7 +359,9 @@ def run_single(args, torch, vlbm):
                    "fp_iters_per_cell_step": round(st["iters_per_cell"], 3),
                    "fp_wave_max_iters_per_step": round(st["wave_max_iters"], 3),
                    "k_step_ms": round(k_ms, 5), "k_rebase_ms": None if rb_ms is None else round(rb_ms, 5),
-                   "rebase_every": REBASE_EVERY if args.precision in SHIFTED else None},
+                   "rebase_every": REBASE_EVERY if args.precision in SHIFTED else None,
+                   "device_warmup": f"{DEVICE_WARMUP_S:g} s ({heat_steps} steps) of a separate copy of the "
+                                    "workload between the warm-up and the timed steps"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
