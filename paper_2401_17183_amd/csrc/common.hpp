@@ -415,7 +415,9 @@ struct MeshObj {
 template <class L> struct Pack {
   static constexpr int J = 0;
   static constexpr int GUP = 1;
-  static constexpr int A = GUP + nup<L::D>();                 // A^i_a for a >= 1 (outgoing)
+  // a >= 1: static meshes S^i = A^i_a + A^i_(a+1) (odd a) and D^i = A^i_(a-1) - A^i_a
+  // (even a), the pair form; moving meshes the outgoing A^i_a
+  static constexpr int A = GUP + nup<L::D>();
   static constexpr int AIN = A + (L::Q - 1) * L::D;           // moving meshes: incoming coefficients
   static constexpr int AEXT = AIN + (L::MOVING ? (L::Q - 1) * L::D : 0);   // present if force
   static constexpr int UINF = AEXT + L::D;                    // present if far field

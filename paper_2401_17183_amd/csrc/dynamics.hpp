@@ -11,8 +11,15 @@ namespace vlbm {
 
 // Per-cell geometry as the collision needs it, held in registers of type AT
 // (the storage type) and converted to the arithmetic type T at each use.  The
-// link coefficients A live either in registers (STRIDE = 0) or in LDS, word
+// link coefficients live either in registers (STRIDE = 0) or in LDS, word
 // (a - 1) * D + i at lds[word * STRIDE] (STRIDE = threads per block).
+//
+// Static meshes hold them in pair form: every direction a >= 1 has its
+// opposite at a + 1 (odd a), and slot a holds S_a = A_a + A_(a+1), slot a + 1
+// D_a = A_a - A_(a+1).  Every sum of the collision over directions pairs the
+// coefficients that way (the incoming coefficient of a is A_opp(a)), so the
+// pair form saves the sums and differences in each fixed-point iteration.
+// Moving meshes hold the outgoing coefficients A_a and the incoming ones.
 template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   // g^{ij} carries a low word when the words are narrower than the arithmetic
   static constexpr bool LO = sizeof(AT) < sizeof(T);
@@ -27,19 +34,26 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   int lofs;                // added to every LDS index (0); re-defined per fixed-point iteration
   __device__ __forceinline__ T j() const { return T(J); }
   __device__ __forceinline__ T ae(int i) const { return T(aext[i]); }
-  // outgoing link coefficient A^i_al (eq. (gamma) contracted with c_al)
+  // coefficient slot al: on a moving mesh the outgoing link coefficient A^i_al
+  // (eq. (gamma) contracted with c_al), on a static one S or D of its pair
   __device__ __forceinline__ AT a(int al, int i) const {
     if constexpr (STRIDE == 0) return Areg[al][i];
     else return al == 0 ? AT(0) : lds[lofs + ((al - 1) * L::D + i) * STRIDE];
   }
-  // incoming one: on a static mesh the opposite direction's outgoing one
-  // (c_opp = -c), on a moving mesh a coefficient of its own
+  // moving meshes: the incoming coefficient of al
   __device__ __forceinline__ AT ain(int al, int i) const {
-    if constexpr (!L::MOVING) return a(opp(al), i);
-    else if constexpr (STRIDE == 0) return Ainreg[al][i];
+    static_assert(L::MOVING, "a static mesh takes the opposite outgoing coefficient (pair form)");
+    if constexpr (STRIDE == 0) return Ainreg[al][i];
     else return al == 0 ? AT(0) : lds[lofs + ((L::Q - 1) * L::D + (al - 1) * L::D + i) * STRIDE];
   }
 };
+
+// Pair form of the outgoing coefficients A_a, A_(a+1) of an opposite pair.
+template <class T>
+__host__ __device__ __forceinline__ void pair_form(T ap, T am, T& s, T& d) {
+  s = ap + am;
+  d = ap - am;
+}
 
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ T gval(const CellGeo<L, T, AT, ST>& g, int i, int j) {
@@ -95,6 +109,13 @@ __device__ __forceinline__ void a_pair(const CellGeo<L, T, AT, ST>& g, int p, in
       aq[i] = widen<T>(g.a(q, i));
     }
   }
+}
+
+// S and D of the opposite pair (p, p + 1) of a static mesh in the arithmetic type.
+template <class L, class T, class AT, int ST>
+__device__ __forceinline__ void sd_pair(const CellGeo<L, T, AT, ST>& g, int p, T* s, T* d) {
+  static_assert(!L::MOVING, "moving meshes keep outgoing and incoming coefficients");
+  a_pair<L, T, AT, ST>(g, p, p + 1, s, d);
 }
 
 // Incoming coefficients of the pair (p, q) in the arithmetic type (moving
@@ -311,30 +332,34 @@ __device__ __forceinline__ T delta_n_dir(T J, const T* Ft, const T* dpi, T trdpi
 //   X^i  = sum_a A^i_a f^eq_a,   Xo^i = sum_a A^i_opp(a) f^eq_a (if wanted),
 //   M^{ij} = sum_a c^i_a S^j_a f^eq_a,  S_a = A_a + A_opp(a),
 // accumulated over opposite pairs (S_a = S_opp(a), c_opp(a) = -c_a) without
-// storing f^eq.
+// storing f^eq.  With f^eq = even +- odd over the pair, a static mesh's pair
+// adds S even + D odd to X, S even - D odd to Xo and 2 c S odd to M; M is
+// returned halved (the factor 2 sits in finish_dpi).
 template <class L, class T, class AT, int ST, bool WITH_XO, int p = 1>
 __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const EqCoef<L, T>& e, T* X, T* Xo,
                                          T (*M)[L::D]) {
   if constexpr (p < L::Q) {
-    T ap[L::D], am[L::D];
-    a_pair<L, T, AT, ST>(g, p, p + 1, ap, am);
     T even, odd;
     feq_parts<L, T, AT, ST, p>(g, e, even, odd);
-    const T fp = even + odd, fm = even - odd, df = T(2) * odd;
     if constexpr (!L::MOVING) {
+      T sp[L::D], dp[L::D];
+      sd_pair<L, T, AT, ST>(g, p, sp, dp);
 #pragma unroll
       for (int i = 0; i < L::D; ++i) {
-        X[i] += ap[i] * fp + am[i] * fm;
-        if constexpr (WITH_XO) Xo[i] += am[i] * fp + ap[i] * fm;
+        X[i] += sp[i] * even + dp[i] * odd;
+        if constexpr (WITH_XO) Xo[i] += sp[i] * even - dp[i] * odd;
       }
 #pragma unroll
       for (int i = 0; i < L::D; ++i) {
         const int ci = L::c(p, i);
         if (ci == 0) continue;
 #pragma unroll
-        for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * (ap[j] + am[j]) * df;
+        for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * sp[j] * odd;
       }
     } else {
+      T ap[L::D], am[L::D];
+      a_pair<L, T, AT, ST>(g, p, p + 1, ap, am);
+      const T fp = even + odd, fm = even - odd;
       // S_a = A_a + Ain_a differs between the two members of the pair
       T ip[L::D], im[L::D];
       ain_pair<L, T, AT, ST>(g, p, p + 1, ip, im);
@@ -348,7 +373,7 @@ __device__ __forceinline__ void pass_feq(const CellGeo<L, T, AT, ST>& g, const E
         const int ci = L::c(p, i);
         if (ci == 0) continue;
 #pragma unroll
-        for (int j = 0; j < L::D; ++j) M[i][j] += T(ci) * ((ap[j] + ip[j]) * fp - (am[j] + im[j]) * fm);
+        for (int j = 0; j < L::D; ++j) M[i][j] += T(0.5 * ci) * ((ap[j] + ip[j]) * fp - (am[j] + im[j]) * fm);
       }
     }
     pass_feq<L, T, AT, ST, WITH_XO, p + 2>(g, e, X, Xo, M);
@@ -380,18 +405,26 @@ __device__ __forceinline__ void delta_n_parts(T J, const T* Ft, const T* dpi, T 
   odd = wJ * (T(L::INV_T0) * cF);
 }
 
-// Pass 2: Y^i = sum_a A^i_a dN_a, dN with the volume J.
+// Pass 2: Y^i = sum_a A^i_a dN_a, dN with the volume J (a static mesh's pair
+// adds S even + D odd).
 template <class L, class T, class AT, int ST, int a = 1>
 __device__ __forceinline__ void pass_dn_j(const CellGeo<L, T, AT, ST>& g, T J, const T* Ft, const T* dpi, T trdpi,
                                           T* Y) {
   if constexpr (a < L::Q) {
-    T ap[L::D], am[L::D];
-    a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
     T even, odd;
     delta_n_parts<L, T, a>(J, Ft, dpi, trdpi, even, odd);
-    const T dp = even + odd, dm = even - odd;
+    if constexpr (!L::MOVING) {
+      T sp[L::D], dp[L::D];
+      sd_pair<L, T, AT, ST>(g, a, sp, dp);
 #pragma unroll
-    for (int i = 0; i < L::D; ++i) Y[i] += ap[i] * dp + am[i] * dm;
+      for (int i = 0; i < L::D; ++i) Y[i] += sp[i] * even + dp[i] * odd;
+    } else {
+      T ap[L::D], am[L::D];
+      a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
+      const T dp = even + odd, dm = even - odd;
+#pragma unroll
+      for (int i = 0; i < L::D; ++i) Y[i] += ap[i] * dp + am[i] * dm;
+    }
     pass_dn_j<L, T, AT, ST, a + 2>(g, J, Ft, dpi, trdpi, Y);
   }
 }
@@ -421,8 +454,9 @@ __device__ __forceinline__ void pass_out(const CellGeo<L, T, AT, ST>& g, const E
   }
 }
 
-// Symmetrised dPi of eq. (delta-flux) from M of pass 1, plus the body-force
-// reading 1/2 k (Ut^i rho a^j + rho a^i Ut^j), k = 1 - 1/(2 tau).  Returns tr dPi.
+// Symmetrised dPi of eq. (delta-flux) from M of pass 1 (halved), plus the
+// body-force reading 1/2 k (Ut^i rho a^j + rho a^i Ut^j), k = 1 - 1/(2 tau).
+// Returns tr dPi.
 template <class L, class T, class AT, int ST>
 __device__ __forceinline__ T finish_dpi(const CellGeo<L, T, AT, ST>& g, T (*M)[L::D], const T* Ut, T rho, T k, T* dpi) {
   constexpr int D = L::D;
@@ -431,7 +465,7 @@ __device__ __forceinline__ T finish_dpi(const CellGeo<L, T, AT, ST>& g, T (*M)[L
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = i; j < D; ++j) {
-      const T v = T(-0.25) * k * (M[i][j] + M[j][i]) + T(0.5) * k * rho * (Ut[i] * g.ae(j) + g.ae(i) * Ut[j]);
+      const T v = T(-0.5) * k * (M[i][j] + M[j][i]) + T(0.5) * k * rho * (Ut[i] * g.ae(j) + g.ae(i) * Ut[j]);
       dpi[up<D>(i, j)] = v;
       if (i == j) tr += v;
     }
@@ -461,15 +495,15 @@ template <class L, class T, class MT = T> struct CollState {
 template <class L> constexpr int lm_words() { return L::D + nup<L::D>() + 1; }
 
 // Adds the opposite pair (a, a + 1) to the link moments m[i][word]: with
-// c_(a+1) = -c_a, P takes A_a - A_(a+1) and Q, R take A_a + A_(a+1).
+// c_(a+1) = -c_a, P takes D = A_a - A_(a+1) and Q, R take S = A_a + A_(a+1).
 template <class L, class T, int a>
-__device__ __forceinline__ void add_link_moments(const T* ap, const T* am, T (*m)[lm_words<L>()]) {
+__device__ __forceinline__ void add_link_moments(const T* sp, const T* dp, T (*m)[lm_words<L>()]) {
   constexpr int D = L::D;
   constexpr int NU = nup<D>();
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    const T dif = ap[i] - am[i];
-    const T sum = ap[i] + am[i];
+    const T dif = dp[i];
+    const T sum = sp[i];
 #pragma unroll
     for (int k = 0; k < D; ++k)
       if (L::c(a, k) != 0) m[i][k] += T(L::w(a) * L::c(a, k)) * dif;
@@ -501,36 +535,49 @@ __device__ __forceinline__ void dn_from_moments(const MT* lm, T J, const T* Ft, 
   }
 }
 
-// The sums of phase 1 over the opposite pairs (a, a + 1), each pair's A read
-// and widened once: rho J, J rho U, C, B and (ST > 0) the link moments.
+// The sums of phase 1 over the opposite pairs (a, a + 1), each pair's
+// coefficients read and widened once: rho J, J rho U, C, B and (ST > 0) the
+// link moments.  A static mesh's pair (sigma = N_a + N_(a+1), delta = N_a -
+// N_(a+1)) adds (S sigma + D delta) / 2 to C and -(S sigma - D delta) / 4 to
+// B; C and B collect sum S sigma and sum D delta, and collide_prepare forms
+// C and B from them.
 template <class L, class T, class AT, int ST, class NS, int a = 1>
 __device__ __forceinline__ void prepare_pairs(const CellGeo<L, T, AT, ST>& g, const NS* N, T& rhoJ, T* mom, T* C, T* B,
                                               T (*m)[lm_words<L>()]) {
   if constexpr (a < L::Q) {
     constexpr int D = L::D;
     static_assert(opposite_pair<L>(a), "prepare_pairs walks opposite pairs (a, a + 1)");
-    T ap[D], am[D];
-    a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
     const T np = T(N[a]), nm = T(N[a + 1]);
-    rhoJ += np + nm;
-    const T dn = np - nm;
-    T ip[D], im[D];   // incoming coefficients of the pair
-    if constexpr (L::MOVING) {
-      ain_pair<L, T, AT, ST>(g, a, a + 1, ip, im);
-    } else {
+    const T sn = np + nm, dn = np - nm;
+    rhoJ += sn;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * dn;
+    if constexpr (!L::MOVING) {
+      T sp[D], dp[D];
+      sd_pair<L, T, AT, ST>(g, a, sp, dp);
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        ip[i] = am[i];
-        im[i] = ap[i];
+        C[i] += sp[i] * sn;
+        B[i] += dp[i] * dn;
+      }
+      if constexpr (ST != 0) add_link_moments<L, T, a>(sp, dp, m);
+    } else {
+      T ap[D], am[D], ip[D], im[D];   // outgoing and incoming coefficients of the pair
+      a_pair<L, T, AT, ST>(g, a, a + 1, ap, am);
+      ain_pair<L, T, AT, ST>(g, a, a + 1, ip, im);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        C[i] += ap[i] * np + am[i] * nm;
+        B[i] -= T(0.5) * (ip[i] * np + im[i] * nm);
+      }
+      if constexpr (ST != 0) {
+        T sp[D], dp[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) pair_form(ap[i], am[i], sp[i], dp[i]);
+        add_link_moments<L, T, a>(sp, dp, m);
       }
     }
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      if (L::c(a, i) != 0) mom[i] += T(L::c(a, i)) * dn;
-      C[i] += ap[i] * np + am[i] * nm;
-      B[i] -= T(0.5) * (ip[i] * np + im[i] * nm);
-    }
-    if constexpr (ST != 0) add_link_moments<L, T, a>(ap, am, m);
     prepare_pairs<L, T, AT, ST, NS, a + 2>(g, N, rhoJ, mom, C, B, m);
   }
 }
@@ -556,6 +603,13 @@ __device__ __forceinline__ void collide_prepare(const CellGeo<L, T, AT, ST>& g, 
 #pragma unroll
       for (int k = 0; k < W; ++k) m[i][k] = 0;
   prepare_pairs<L, T, AT, ST, NS>(g, N, rhoJ, mom, C, B, m);
+  if constexpr (!L::MOVING)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {   // C, B from sum S sigma (in C) and sum D delta (in B)
+      const T ss = C[i], dd = B[i];
+      C[i] = T(0.5) * (ss + dd);
+      B[i] = T(-0.25) * (ss - dd);
+    }
   // two divisions: 1/J and 1/(rho J)
   const T inv_rhoJ = T(1) / rhoJ;
   st.invJ = T(1) / g.j();
@@ -607,6 +661,7 @@ __device__ __forceinline__ void collide_iterate(CellGeo<L, T, AT, ST>& gl, const
   int it = 1;
   int done = 0;
   T& rho_l = st.rho;
+  T prev = T(0);
   for (; it <= max_iter; ++it) {
     // Re-define the per-cell scalars each iteration (empty register
     // constraints, in place: the values do not change): quantities derived from
@@ -659,6 +714,18 @@ __device__ __forceinline__ void collide_iterate(CellGeo<L, T, AT, ST>& gl, const
       done = 1;
       break;
     }
+    // FP32 arithmetic: on coarse, strongly stretched meshes the change can
+    // stall at the rounding level of the sums (the terms of eq.
+    // (compo-constr) are far larger than F) just above the tolerance; an
+    // iterate whose change no longer decreases and lies within 16 tolerances
+    // is as close as this precision gets
+    if constexpr (sizeof(T) == 4) {
+      if (it > min_iter && change >= prev && change <= T(16) * tol * rho_l) {
+        done = 1;
+        break;
+      }
+    }
+    prev = change;
   }
   st.iters = done ? it : max_iter + 1;
 }

@@ -49,10 +49,14 @@ __device__ inline CellGeo<L, double> load_fp64(const StateArgs<S>& a, int cell, 
   g.J = a.J[cell];
   for (int i = 0; i < D; ++i)
     for (int j = i; j < D; ++j) g.gup[up<D>(i, j)] = a.gup[(i * D + j) * nc + cell];
+  // the collision takes the coefficients in pair form
 #pragma unroll
-  for (int al = 0; al < L::Q; ++al)
+  for (int i = 0; i < D; ++i) g.Areg[0][i] = 0;
 #pragma unroll
-    for (int i = 0; i < D; ++i) g.Areg[al][i] = a.A[(al * D + i) * nc + cell];
+  for (int al = 1; al < L::Q; al += 2)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      pair_form(a.A[(al * D + i) * nc + cell], a.A[((al + 1) * D + i) * nc + cell], g.Areg[al][i], g.Areg[al + 1][i]);
   for (int i = 0; i < D; ++i) {
     double ae = 0, uc = 0;
     for (int k = 0; k < D; ++k) {
@@ -267,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
       for (int i = 0; i < D; ++i) {
         const double ci = L::c(al, i);
         // incoming coefficient: the opposite outgoing one on a static mesh
-        const double Ao = a.Ain ? a.Ain[(al * D + i) * nc + cell] : g.a(opp(al), i);
+        const double Ao = a.Ain ? a.Ain[(al * D + i) * nc + cell] : a.A[(opp(al) * D + i) * nc + cell];
         inner[i] += (ci - 0.5 * Ao) * n;
         if ((wm >> al) & 1) wall[i] += (2.0 * ci - Ao) * n;
       }
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(StateArgs<S> a) {
 #pragma unroll
           for (int i = 0; i < D; ++i) {
             const double ci = L::c(al, i);
-            const double ah = g.a(opp(al), i);
+            const double ah = a.A[(opp(al) * D + i) * nc + cell];
             const double as = a.A[(opp(al) * D + i) * nc + src];
             wall[i] -= (ci - 0.5 * ah) * n;   // keep this cell's half only
 #pragma unroll

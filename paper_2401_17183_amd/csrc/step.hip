@@ -31,18 +31,22 @@ template <class L, class S, class T> constexpr int block_for() {
   return L::Q > 21 ? ((sizeof(S) == 4 && sizeof(T) == 8) ? 128 : 64) : kBlock;
 }
 
-// Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), A (a >= 1),
-// a_ext^i = G . g^i, U_inf^i = u_inf . g^i.
+// Pack FP64 geometry into the kernel precision: J, g^{ij} (upper), the link
+// coefficients in pair form (S = A_a + A_(a+1) in slot a, D = A_a - A_(a+1)
+// in slot a + 1, odd a), a_ext^i = G . g^i, U_inf^i = u_inf . g^i.
 //
-// comp (FP32 words, FP64 arithmetic): a_ext also cancels the rounding of A.
-// With dA = fl32(A) - A, eq. (compo-constr) applied to a fluid at rest
+// comp (FP32 words, FP64 arithmetic): a_ext also cancels the rounding of the
+// coefficients.  The kernel's A_a is (fl32(S) + fl32(D)) / 2; with dA its
+// difference from A, eq. (compo-constr) applied to a fluid at rest
 // (N = N' = J rho f^eq(rho = 1, U = Ut = 0)) gives the extra force rho kappa,
-//   kappa^i = -1/2 sum_a (dA^i_a + dA^i_opp(a)) f_a = -1/2 sum_a dA^i_a (f_a + f_opp(a)).
+//   kappa^i = -1/2 sum_a (dA^i_a + dA^i_opp(a)) f_a,
+// and dA_a + dA_(a+1) = fl32(S) - S over each pair (f_a = f_(a+1) at rest), so
+//   kappa^i = -sum_pairs (fl32(S^i) - S^i) f_a.
 // The velocity-linear part of f^eq does not reach that sum (dA_a + dA_opp(a)
 // is even in c_a, c_a . U odd), and the force enters every step as
 // F + rho a_ext, so storing a_ext - kappa cancels the rounding up to second
-// order in the velocity.  Without it the rounding of A acts as a spurious
-// body force on strongly stretched meshes (a 20:1 O-grid).
+// order in the velocity.  Without it the rounding acts as a spurious body
+// force on strongly stretched meshes (a 20:1 O-grid).
 template <class L, class S>
 __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const double* gup, const double* gco,
                                                  const double* A, double G0, double G1, double G2, double u0,
@@ -59,8 +63,13 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
       geo[pack_index<L>(Pack<L>::GUP + up<D>(i, j), cell)] = hi;
       geo[pack_index<L>(Pack<L>::GUPLO + up<D>(i, j), cell)] = S(v - double(hi));
     }
-  for (int al = 1; al < L::Q; ++al)
-    for (int i = 0; i < D; ++i) geo[pack_index<L>(Pack<L>::A + (al - 1) * D + i, cell)] = S(A[(al * D + i) * nc + cell]);
+  for (int al = 1; al < L::Q; al += 2)
+    for (int i = 0; i < D; ++i) {
+      double sv, dv;
+      pair_form(A[(al * D + i) * nc + cell], A[((al + 1) * D + i) * nc + cell], sv, dv);
+      geo[pack_index<L>(Pack<L>::A + (al - 1) * D + i, cell)] = S(sv);
+      geo[pack_index<L>(Pack<L>::A + al * D + i, cell)] = S(dv);
+    }
   double kappa[D] = {};
   if constexpr (sizeof(S) < sizeof(double)) {
     if (comp) {
@@ -71,10 +80,11 @@ __global__ __launch_bounds__(kBlock) void k_pack(Box box, const double* J, const
       const double rest[D] = {};
       double f[L::Q];
       feq_all<L, double, double, 0>(g, eq_coef<L, double, double, 0>(g, 1.0, rest, rest), f);
-      for (int al = 1; al < L::Q; ++al)
+      for (int al = 1; al < L::Q; al += 2)
         for (int i = 0; i < D; ++i) {
-          const double a = A[(al * D + i) * nc + cell];
-          kappa[i] -= 0.5 * (double(S(a)) - a) * (f[al] + f[opp(al)]);
+          double sv, dv;
+          pair_form(A[(al * D + i) * nc + cell], A[((al + 1) * D + i) * nc + cell], sv, dv);
+          kappa[i] -= 0.5 * (double(S(sv)) - sv) * (f[al] + f[al + 1]);
         }
     }
   }
