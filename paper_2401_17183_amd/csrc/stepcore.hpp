@@ -29,6 +29,9 @@ template <class P, class S, class T> struct StepArgs {
   float scale, inv_scale;
   const S* __restrict__ geo;
   T tau, tau_g, tol, rho_inf;
+  // relaxation rates from the host (kernel arguments, so no lane divides):
+  // 1/tau, s = 1/tau_g and c1 = (s - 1/tau) / 2 (tau_g = tau for BGK)
+  T inv_tau, relax_s, relax_c1;
   int general;                  // collision matrix other than BGK (tau_g != tau)
   int max_iter, min_iter;
   int stream_only;
@@ -259,7 +262,11 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
 #pragma unroll
   for (int i = 0; i < D; ++i) F[i] = load_stream(word(a.fcache, i, nc) + cell);
   CollState<L, T, S> st;
-  const Relax<T> rx = make_relax<T>(a.tau, a.tau_g, GEN ? 1 : 0);
+  Relax<T> rx;
+  rx.tau = a.tau;
+  rx.general = GEN ? 1 : 0;
+  rx.s = GEN ? a.relax_s : a.inv_tau;
+  rx.c1 = GEN ? a.relax_c1 : T(0);
   collide_prepare<L, T, S, ST, NR>(g, N, rx, st);
   collide_iterate<L, T, S, ST>(g, rx, a.tol, a.max_iter, F, st, a.min_iter);
   if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
@@ -319,6 +326,9 @@ inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   a.tau = T(s->p.tau);
   a.general = general_collision(s->p);
   a.tau_g = T(a.general ? s->p.tau_g : s->p.tau);
+  a.inv_tau = T(1) / a.tau;
+  a.relax_s = T(1) / a.tau_g;
+  a.relax_c1 = T(0.5) * (a.relax_s - a.inv_tau);
   a.tol = T(s->p.fp_tol);
   a.rho_inf = T(s->p.rho_inf);
   a.max_iter = s->p.fp_max_iter;
