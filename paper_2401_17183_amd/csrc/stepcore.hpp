@@ -282,7 +282,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   // registers, and so do the populations of the other BGK variants (FP64 ones
   // in accumulation registers: that kernel runs one wave per SIMD either way).
   constexpr bool regather =
-      std::is_same<P, F32Dev>::value || (!PopCodec<P>::shifted && sizeof(T) == 8 && GEN);
+      (std::is_same<P, F32Dev>::value && (L::Q <= 21 || GEN)) || (!PopCodec<P>::shifted && sizeof(T) == 8 && GEN);
   if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
     // here instead of being kept (or spilled) across the fixed point
