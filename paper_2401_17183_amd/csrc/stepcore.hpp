@@ -276,13 +276,16 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
 #pragma unroll
   for (int i = 0; i < D; ++i) store_stream(word(a.fcache, i, nc) + cell, FC(F[i]));
   // gather again (cache hits) rather than keeping N live across the fixed point
-  // where registers are short: FP32 deviations (decoded into FP64 registers;
-  // they re-read their references with them) and the general collision
-  // variant with FP64 arithmetic.  Decoded 16-bit populations stay in
-  // registers, and so do the populations of the other BGK variants (FP64 ones
-  // in accumulation registers: that kernel runs one wave per SIMD either way).
+  // where registers are short: D3Q19 FP32 deviations (decoded into FP64
+  // registers, 38 VGPRs that would cost its second wavefront per SIMD; they
+  // re-read their references with them) and the general collision variants
+  // with FP64 arithmetic.  Everywhere else the populations stay in registers:
+  // D2Q9 FP32 deviations (three wavefronts per SIMD either way, measured 8 %
+  // faster on the bump-channel batch), D2Q21 (two either way, 6 %), D3Q39
+  // (one either way, 11 %), decoded 16-bit populations, and the FP64 ones in
+  // accumulation registers (that kernel runs one wave per SIMD either way).
   constexpr bool regather =
-      (std::is_same<P, F32Dev>::value && (L::Q <= 21 || GEN)) || (!PopCodec<P>::shifted && sizeof(T) == 8 && GEN);
+      (std::is_same<P, F32Dev>::value && (L::Q == 19 || GEN)) || (!PopCodec<P>::shifted && sizeof(T) == 8 && GEN);
   if constexpr (regather) {
     // opaque copies of the coordinates: the source addresses are recomputed
     // here instead of being kept (or spilled) across the fixed point
