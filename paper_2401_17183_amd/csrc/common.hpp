@@ -464,7 +464,7 @@ struct SimObj {
   void* geo = nullptr;    // precision pack
   void* rown = nullptr;     // shifted modes: [Q][cells] 16-bit reference of each slot (read by the slot's
                             // writer and, at the same offset as the population, by its reader)
-  void* fcache = nullptr;   // [d][cells]: converged inertial force of the last step (fixed-point start),
+  void* fcache = nullptr;   // [d][cells]: converged inertial force per unit density of the last step (fixed-point start),
                             // FP64 with FP64 storage, FP32 otherwise
   int has_force = 0, has_farfield = 0;
   int comp_A = 0;   // FP32 words, FP64 arithmetic: the a_ext words also cancel the rounding of A

@@ -140,9 +140,10 @@ __global__ __launch_bounds__(kBlock) void k_init(StateArgs<S> a) {
   double N[L::Q], F[D];
   if (!consistent_equilibrium<L, double>(g, rho, Ut, a.tau, a.tol, a.max_iter, N, F)) atomicAdd(a.flag, 1);
   unstream_store<L, S>(a, cell, x, y, z, N);
+  // the step's force cache holds F per unit density
   for (int i = 0; i < D; ++i) {
-    if (a.fc64) static_cast<double*>(a.fcache)[i * nc + cell] = F[i];
-    else static_cast<float*>(a.fcache)[i * nc + cell] = (float)F[i];
+    if (a.fc64) static_cast<double*>(a.fcache)[i * nc + cell] = F[i] / rho;
+    else static_cast<float*>(a.fcache)[i * nc + cell] = (float)(F[i] / rho);
   }
 }
 

@@ -36,8 +36,11 @@ template <class P, class S, class T> struct StepArgs {
   int max_iter, min_iter;
   int stream_only;
   int has_force, has_ff;
-  // [D][cells] starting guess in, converged F out: FP64 with FP64 storage,
-  // FP32 otherwise (a starting guess only)
+  // [D][cells] the converged F per unit density F / rho of the last step in
+  // (the starting guess is rho F / rho_prev: most of a step's change of F is
+  // the density's, through the metric part of the equilibrium stress), that
+  // of this step out: FP64 with FP64 storage, FP32 otherwise (a starting guess
+  // only; the converged F does not depend on it)
   typename std::conditional<std::is_same<S, double>::value, double, float>::type* __restrict__ fcache;
   int* flags;
   // optional fixed-point statistics (null: off): [0] sum over cells of the
@@ -268,13 +271,15 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   rx.s = GEN ? a.relax_s : a.inv_tau;
   rx.c1 = GEN ? a.relax_c1 : T(0);
   collide_prepare<L, T, S, ST, NR>(g, N, rx, st);
+#pragma unroll
+  for (int i = 0; i < D; ++i) F[i] *= st.rho;
   collide_iterate<L, T, S, ST>(g, rx, a.tol, a.max_iter, F, st, a.min_iter);
   if (st.iters > a.max_iter) atomicAdd(&a.flags[0], 1);
   if (a.stats) add_iteration_stats(a.stats, st.iters);   // wave-uniform
   collide_refresh<L, T, S, ST>(g, F, st);
   using FC = typename std::remove_cv<typename std::remove_reference<decltype(*a.fcache)>::type>::type;
 #pragma unroll
-  for (int i = 0; i < D; ++i) store_stream(word(a.fcache, i, nc) + cell, FC(F[i]));
+  for (int i = 0; i < D; ++i) store_stream(word(a.fcache, i, nc) + cell, FC(T(2) * st.half_inv_rho * F[i]));
   // gather again (cache hits) rather than keeping N live across the fixed point
   // where registers are short: D3Q19 FP32 deviations (decoded into FP64
   // registers, 38 VGPRs that would cost its second wavefront per SIMD; they
