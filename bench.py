@@ -205,11 +205,10 @@ STEP_SOURCES = ["paper_2401_17183_amd/csrc/common.hpp", "paper_2401_17183_amd/cs
 BATCH_SOURCES = STEP_SOURCES[:3] + ["paper_2401_17183_amd/csrc/batch.hip"]
 
 
-def profiled_traffic(profile, sources, require=None):
-    """HBM bytes per launch from a committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None when
-    there is no summary, the kernel sources changed since it was taken, or one of
-    the `require` entries (e.g. the launch shape) differs from the summary's."""
+def profile_values(profile, sources, require=None):
+    """The `key = value` lines of a committed rocprofv3 summary, or None when
+    there is no summary, the kernel sources changed since it was taken, or one
+    of the `require` entries (e.g. the launch shape) differs from the summary's."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -224,11 +223,34 @@ def profiled_traffic(profile, sources, require=None):
             if " = " in line:
                 k, v = line.split(" = ", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_digest") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_digest") != h.hexdigest()[:16]:
         return None
     if any(vals.get(k) != str(v) for k, v in (require or {}).items()):
         return None
+    return vals
+
+
+def profiled_traffic(profile, sources, require=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
+    (see profile_values)."""
+    vals = profile_values(profile, sources, require)
+    if vals is None or "traffic_bytes_per_launch" not in vals:
+        return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def profiled_valu(profile, sources):
+    """The VALU evidence of a committed summary (SQ counters of the same
+    kernel): instructions per wavefront, the SIMD's VALU busy fraction while
+    its wavefronts are resident, and the graphics clock under the load."""
+    vals = profile_values(profile, sources)
+    keys = ("valu_insts_per_wave", "valu_busy_while_resident", "graphics_clock_GHz")
+    if vals is None or any(k not in vals for k in keys):
+        return None
+    return {"kind": "valu", "valu_insts_per_wave": float(vals[keys[0]]),
+            "valu_busy_while_resident": float(vals[keys[1]]), "graphics_clock_GHz": float(vals[keys[2]]),
+            "source": f"profiles/{profile}"}
 
 
 def _event_pair(torch, stream):
@@ -342,9 +364,11 @@ def run_single(args, torch, vlbm):
     bpc = algorithmic_bytes_per_cell(mesh.Q, mesh.d, args.precision, has_force, has_ff)
     achieved = bpc * cells / (k_ms / 1e3) / 1e9
     traffic = None
+    binding = None
     if args.workload in PROFILE_STEM:
         tag = ("" if args.tau is None else f"_tau{args.tau:g}") + ("" if args.tau_g is None else f"_taug{args.tau_g:g}")
         traffic = profiled_traffic(f"{PROFILE_STEM[args.workload]}_{args.precision}{tag}.md", STEP_SOURCES)
+        binding = profiled_valu(f"{PROFILE_STEM[args.workload]}_{args.precision}{tag}.md", STEP_SOURCES)
     print("[bench] STREAM-style ceiling", file=sys.stderr, flush=True)
     ceil = copy_ceiling(vlbm)
     return {
@@ -371,7 +395,10 @@ def run_single(args, torch, vlbm):
                      "kernel_ms": round(k_ms, 5),
                      "copy_ceiling_GBps": ceil["copy"], "read_ceiling_GBps": ceil["read"],
                      "write_ceiling_GBps": ceil["write"],
-                     "frac_of_copy_ceiling": round(achieved / ceil["copy"], 4) if ceil["copy"] else None},
+                     "frac_of_copy_ceiling": round(achieved / ceil["copy"], 4) if ceil["copy"] else None,
+                     # what limits the kernel short of the HBM roofline (SQ counters of the same
+                     # sources), or None where no counter summary covers it
+                     "binding_limit": binding},
     }
 
 
