@@ -1,0 +1,39 @@
+"""The bench's algorithmic byte model and its contract checks (CPU only)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("precision,expected", [("fp32", 470), ("fp32c", 408), ("fp16s", 370), ("bf16s", 370),
+                                                ("fp64", 816)])
+def test_channel_bytes_per_cell(precision, expected):
+    """D3Q19 channel with a body force: populations read and written once,
+    J, 6 g^{ij}, 54 coefficient words and 3 a_ext words; FP32 storage adds the
+    6 lo words of g^{ij} and the deviation modes 19 16-bit references."""
+    assert bench.algorithmic_bytes_per_cell(19, 3, precision, True) == expected
+
+
+def test_fp32_mode_always_reads_a_ext():
+    """Without a body force the FP32 mode still reads the a_ext words (they
+    carry the rest-state compensation of the coefficient rounding); the O-grid
+    adds the far-field U_inf words."""
+    assert bench.algorithmic_bytes_per_cell(19, 3, "fp32", False, True) == 152 + (1 + 6 + 54 + 3 + 3 + 6) * 4 + 38
+    assert bench.algorithmic_bytes_per_cell(19, 3, "fp32c", False, True) == 152 + (1 + 6 + 54 + 3) * 4
+
+
+def test_batch_bytes_per_cell():
+    """D2Q9 FP32 with deviation storage: 72 + 25 words x 4 + 18 = 190."""
+    assert bench.algorithmic_bytes_per_cell(9, 2, "fp32", True) == 190
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
