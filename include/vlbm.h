@@ -48,12 +48,16 @@ enum { VLBM_D2Q9 = 0, VLBM_D3Q19 = 1, VLBM_D2Q21 = 2, VLBM_D3Q39 = 3 };
 
 /* Storage / arithmetic precision of a simulation:
  *  FP64   populations and geometry stored in FP64, FP64 arithmetic;
- *  FP32   populations and geometry stored in FP32, FP64 arithmetic in registers
- *         (FP32 arithmetic loses the small velocity signal to cancellation);
+ *  FP32   each population stored as the FP32 difference from a per-slot FP16
+ *         reference (one reference array, re-based every rebase_every steps),
+ *         geometry in FP32 words (g^{ij} as a hi + lo pair; the a_ext words
+ *         also cancel the rest-state effect of rounding the link
+ *         coefficients), FP64 arithmetic in registers (FP32 arithmetic loses
+ *         the small velocity signal to cancellation);
  *  FP32C  FP32 storage and FP32 arithmetic (faster, less accurate);
- *  FP16S / BF16S  deviations from the per-cell rest equilibrium stored in 16
- *         bits (FP16: multiplied by the largest power of two up to 4096 that
- *         keeps deviations up to 4 max J inside FP16's range). */
+ *  FP16S / BF16S  the same per-slot deviations stored in 16 bits, FP32
+ *         arithmetic (FP16: multiplied by the largest power of two up to 4096
+ *         that keeps deviations up to 4 max J inside FP16's range). */
 enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP16S = 2, VLBM_BF16S = 3, VLBM_FP32C = 4 };
 
 enum { VLBM_PERIODIC = 0, VLBM_WALL = 1, VLBM_FARFIELD = 2 };
