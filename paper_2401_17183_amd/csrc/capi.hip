@@ -352,6 +352,7 @@ static void free_sim(SimObj* s) {
   dev_free(s->geo);
   dev_free(s->fcache);
   dev_free(s->rown);
+  dev_free(s->rown_spare);
   dev_free(s->audit_ring);
   dev_free(s->audit_partial);
   dev_free(s->u_prev);
@@ -416,6 +417,7 @@ static int create_sim(MeshObj* m, const vlbm_params* p, const double* rho, const
   if ((rc = dev_alloc(&s->geo, pack_elements(words, nc) * geometry_bytes(s->p.precision)))) return bail(rc);
   if (storage_shifted(s->p.precision))   // 16-bit references
     if ((rc = dev_alloc(&s->rown, nc * m->Q * 2))) return bail(rc);
+    if ((rc = dev_alloc(&s->rown_spare, nc * m->Q * 2))) return bail(rc);
   if ((rc = dev_alloc(&s->fcache, nc * d * fcache_elem(s->p.precision)))) return bail(rc);
   s->audit_cap = 4096;
   if ((rc = dev_alloc(&s->audit_ring, sizeof(vlbm_audit) * s->audit_cap))) return bail(rc);
@@ -501,12 +503,22 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
   const int rebase = rebase_period(s->p);
   EventPool* ep = s->timing_on ? static_cast<EventPool*>(s->timing) : nullptr;
   for (int64_t k = 0; k < nsteps; ++k) {
+    // the step that reaches a multiple of the re-basing period re-bases its
+    // own outputs (new references into the spare array, swapped in after it);
+    // a stream-only step, and a batch member (whose batch keeps its reference
+    // array in its step arguments), leave that to the re-basing kernel
+    const bool due = rebase > 0 && storage_shifted(s->p.precision) && (s->t + 1) % rebase == 0;
+    s->rebase_in_step = due && !s->p.stream_only && !s->batch_member;
     if (ep) HIP_TRY(ep->begin(s->stream, 0));
-    HIP_TRY(launch_step(s));
+    const hipError_t le = launch_step(s);
+    const bool fused = s->rebase_in_step;
+    s->rebase_in_step = 0;
+    HIP_TRY(le);
     if (ep) HIP_TRY(ep->end(s->stream));
+    if (fused) std::swap(s->rown, s->rown_spare);
     s->buf ^= 1;
     s->t++;
-    if (rebase > 0 && storage_shifted(s->p.precision) && s->t % rebase == 0) {
+    if (due && !fused) {
       if (ep) HIP_TRY(ep->begin(s->stream, 1));
       HIP_TRY(launch_rebase(s));
       if (ep) HIP_TRY(ep->end(s->stream));
@@ -825,6 +837,7 @@ int vlbm_batch_create(const vlbm_mesh* meshes, const vlbm_params* params, int co
     SimObj* s = nullptr;
     const int rc = create_sim(m, &params[i], nullptr, nullptr, b->stream, &s);
     if (rc) return bail(rc);
+    s->batch_member = 1;
     b->members.push_back(s);
     const int rb = storage_shifted(prec) ? rebase_period(s->p) : 0;
     if (i == 0) {

@@ -464,6 +464,10 @@ struct SimObj {
   void* geo = nullptr;    // precision pack
   void* rown = nullptr;     // shifted modes: [Q][cells] 16-bit reference of each slot (read by the slot's
                             // writer and, at the same offset as the population, by its reader)
+  void* rown_spare = nullptr;   // shifted modes: a second reference array; a re-basing step writes the new
+                                // references there and the two are swapped after it
+  int rebase_in_step = 0;       // the next step launch re-bases its outputs (into rown_spare)
+  int batch_member = 0;         // owned by a batch, whose step arguments hold its reference array
   void* fcache = nullptr;   // [d][cells]: converged inertial force per unit density of the last step (fixed-point start),
                             // FP64 with FP64 storage, FP32 otherwise
   int has_force = 0, has_farfield = 0;

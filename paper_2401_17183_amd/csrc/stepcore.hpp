@@ -26,6 +26,9 @@ template <class P, class S, class T> struct StepArgs {
   // shifted modes: the reference of every slot, [Q][cells]; the writer encodes
   // against its own slots, the reader decodes at the offset it gathers from
   const PopR<P>* __restrict__ rown;
+  // re-basing step (else null): the outputs are re-based as the re-basing
+  // kernel would re-base them after the step, the new references go here
+  PopR<P>* __restrict__ rown_new;
   float scale, inv_scale;
   const S* __restrict__ geo;
   T tau, tau_g, tol, rho_inf;
@@ -310,9 +313,20 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
 #pragma unroll
     for (int al = 0; al < Q; ++al) ref[al] = word(a.rown, al, nc)[cell];
     collide_output<L, T, S, ST, NR>(g, N, rx, st, Np);
+    using C = PopCodec<P>;
+    if (a.rown_new) {   // wave-uniform: the steps of rebase_cell on the written word
 #pragma unroll
-    for (int al = 0; al < Q; ++al)
-      store_stream(word(a.out, al, nc) + cell, PopCodec<P>::template encode<T>(T(Np[al]), ref[al], a.scale));
+      for (int al = 0; al < Q; ++al) {
+        const T n = C::template decode<T>(C::template encode<T>(T(Np[al]), ref[al], a.scale), ref[al], a.inv_scale);
+        const PopR<P> r = C::template reference<T>(n);
+        store_stream(word(a.rown_new, al, nc) + cell, r);
+        store_stream(word(a.out, al, nc) + cell, C::template encode<T>(n, r, a.scale));
+      }
+    } else {
+#pragma unroll
+      for (int al = 0; al < Q; ++al)
+        store_stream(word(a.out, al, nc) + cell, C::template encode<T>(T(Np[al]), ref[al], a.scale));
+    }
   } else {
     collide_output<L, T, S, ST, NR>(g, N, rx, st, Np);
 #pragma unroll
@@ -328,6 +342,7 @@ inline StepArgs<P, S, T> make_step_args(const SimObj* s) {
   a.in = static_cast<const PopE<P>*>(s->pop[s->buf]);
   a.out = static_cast<PopE<P>*>(s->pop[s->buf ^ 1]);
   a.rown = static_cast<const PopR<P>*>(s->rown);
+  a.rown_new = s->rebase_in_step ? static_cast<PopR<P>*>(s->rown_spare) : nullptr;
   a.scale = pop_scale(s->p.precision, s->mesh->report.max_J);
   a.inv_scale = 1.0f / a.scale;
   a.geo = static_cast<const S*>(s->geo);
