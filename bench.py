@@ -1,12 +1,16 @@
 """Benchmark: D3Q19 FP32 fused stream-collide-force update on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload channel|ogrid|batch]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload channel|ogrid|batch|moving|...]
                     [--precision fp32|fp32c|fp64|fp16s|bf16s] [--no-cpu]
 
 Prints ONE JSON line: MLUPS of the whole job (inputs resident in HBM), the
 roofline of the fused step kernel (algorithmic bytes per launch / average
 launch duration from HIP events on the stream the kernel runs on), and the FP64
 CPU oracle timed on a bounded sample of the same workload.
+
+--workload moving times a deforming D3Q19 periodic box of the same size in
+FP64: every step computes the geometry of the next node positions and then
+runs the fused step of a moving mesh.
 
 --workload batch times the 256-mesh uneven D2Q9 batch instead: one persistent
 launch per step replayed from captured graphs, with the launch shape chosen by
@@ -151,6 +155,41 @@ def cpu_baseline(workload="channel", seconds_target=12.0, tau_g=None, tau=None):
         one = {k: out[k] for k in ("value", "cores", "sample")}
         out.update(oracle_batch_pool())
         out["one_core"] = one
+    return out
+
+
+def cpu_baseline_moving(seconds_target=12.0, tau=None):
+    """The FP64 moving-mesh oracle, one BLAS thread, on a 16x16x8 replica of the
+    deforming box (same motion, waviness scaled with the size); the node
+    positions of one period are made before timing, the geometry of each new
+    position is computed inside the timed steps, as on the device."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lattice, moving
+    from paper_2401_17183_amd import workloads as W
+
+    w = W.wavy_periodic("D3Q19", (16, 16, 8), 0.25)
+    if tau is not None:
+        w["tau"] = tau
+    period = MOVING_MOTION["period"]
+    pos = [W.moving_coords(w, t, **MOVING_MOTION) for t in range(period)]
+    rng = np.random.default_rng(MOVING_SEED)
+    shape = tuple(reversed(w["n"]))
+    with threadpool_limits(limits=1):
+        o = moving.MovingSim(lattice.by_name("D3Q19"), w["n"], pos[0][0], pos[0][1], w["dx"], w["tau"])
+        o.init(1.0 + 0.01 * rng.standard_normal(shape), 0.01 * rng.standard_normal((3,) + shape))
+        o.step(*pos[1])
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < seconds_target:
+            o.step(*pos[(steps + 2) % period])
+            steps += 1
+        dt = time.perf_counter() - t0
+    cells = int(np.prod(w["n"]))
+    out = {"value": round(cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "sample": f"D3Q19 deforming wavy periodic 16x16x8, FP64 moving-mesh oracle, {steps} steps, "
+                     f"{dt:.1f} s, 1 thread"}
+    out.update(host_cpu())
     return out
 
 
@@ -402,6 +441,126 @@ def run_single(args, torch, vlbm):
     }
 
 
+# The deforming-mesh workload: a periodic wavy D3Q19 box of the benchmarked
+# channel's size whose node displacements from the uniform lattice breathe by
+# 30 % with a period of 40 steps (the node positions of one period are made
+# before timing and cycled).
+MOVING_MOTION = dict(breathe=0.3, period=40)
+MOVING_SEED = 7
+
+
+def moving_bytes_per_cell(Q, d, has_force):
+    """Bytes the fused step of a moving mesh moves per cell (FP64 only): the Q
+    populations read and written once, and the per-step FP64 words J,
+    g^{ij} upper, the outgoing and incoming A^i_a for a >= 1 (a_ext when a
+    body force acts)."""
+    words = 1 + d * (d + 1) // 2 + 2 * (Q - 1) * d + (d if has_force else 0)
+    return 2 * Q * 8 + words * 8
+
+
+def moving_geometry_bytes(Q, d, ncells, nbox, has_force):
+    """Bytes the two geometry kernels of a moving step move, per launch:
+    k_basis reads the d coordinates of each geometry-box node and writes g_i on
+    the box (d*d words) and J, g^i, g_i and g^{ij} (full d x d) on the real
+    cells; k_links_moving reads J, g^{ij} upper and g^i of the cell and g_i
+    on the boxes of three times (each box word once), and writes the pack of
+    the step (J, g^{ij} upper, outgoing and incoming A^i_a for a >= 1 and
+    a_ext, which it always writes)."""
+    nup = d * (d + 1) // 2
+    basis = 8 * (nbox * (d + d * d) + ncells * (1 + 3 * d * d))
+    links = 8 * ncells * ((1 + nup + d * d + 3 * d * d) + (1 + nup + 2 * (Q - 1) * d + d))
+    return basis, links
+
+
+def run_moving(args, torch, vlbm):
+    from paper_2401_17183_amd import workloads as W
+    if args.precision != "fp64":
+        raise SystemExit("--workload moving runs in FP64 (moving meshes are built for FP64 storage)")
+    w = W.wavy_periodic("D3Q19", (256, 128, 128), 2.0)
+    if args.tau is not None:
+        w["tau"] = args.tau
+    period = MOVING_MOTION["period"]
+    print(f"[bench] building {w['name']} and the node positions of one period ({period} steps)",
+          file=sys.stderr, flush=True)
+    coords, wraps = [], []
+    for t in range(period):
+        X, wr = W.moving_coords(w, t, **MOVING_MOTION)
+        if t == 0:
+            mesh = vlbm.Mesh(w["lattice"], w["n"], X, w["faces"], wr, w["dx"])
+        coords.append(torch.from_numpy(X.ravel()).to("cuda"))
+        wraps.append(wr)
+    del X
+    rng = np.random.default_rng(MOVING_SEED)
+    cells, d = mesh.ncells, mesh.d
+    rho = 1.0 + 0.01 * rng.standard_normal(cells)
+    u = 0.01 * rng.standard_normal((d, cells))
+    sim = vlbm.Sim(mesh, vlbm.make_params(w["tau"], precision="fp64", fp_tol=args.fp_tol), rho=rho, u=u)
+    del rho, u
+    t = [0]
+
+    def steps(n):
+        for _ in range(n):
+            t[0] += 1
+            k = t[0] % period
+            sim.step_moving(coords[k], wraps[k])
+
+    stream = torch.cuda.current_stream()   # the Sim launches on torch's current stream
+    print(f"[bench] warmup {args.warmup} + device warm-up", file=sys.stderr, flush=True)
+    steps(args.warmup)
+    torch.cuda.synchronize()
+    # the mesh state cannot be restored once it moved: the device is loaded by
+    # more untimed steps of the same run instead of a separate copy
+    t0 = time.perf_counter()
+    heat_steps = 0
+    while time.perf_counter() - t0 < DEVICE_WARMUP_S:
+        steps(10)
+        torch.cuda.synchronize()
+        heat_steps += 10
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ms = _timed(torch, stream, steps, args.steps)
+    wall = time.perf_counter() - t0
+    # the next steps of the same run, with HIP events around each kernel
+    sim.kernel_timing(True)
+    steps(args.steps)
+    kt = sim.kernel_timing(False)
+    sim.sync()
+    mo = sim.moments()
+    finite = bool(torch.isfinite(mo["u"]).all().item())
+    u_max = float(mo["u"].abs().max().item())
+    ms_per_step = ms / args.steps
+    nbox = int(np.prod([n + 2 for n in w["n"]]))   # one layer around the real cells (one-cell links)
+    basis_b, links_b = moving_geometry_bytes(mesh.Q, d, cells, nbox, False)
+    step_b = moving_bytes_per_cell(mesh.Q, d, False) * cells
+    kernels = {}
+    for key, name, nbytes in (("step", "k_step (moving mesh)", step_b), ("links", "k_links_moving", links_b),
+                              ("basis", "k_basis", basis_b)):
+        kms = kt[f"{key}_ms"] / max(kt[f"{key}_launches"], 1)
+        kernels[name] = {"ms": round(kms, 5), "algorithmic_bytes_per_launch": nbytes,
+                         "GBps": round(nbytes / (kms / 1e3) / 1e9, 1)}
+    dominant = max(kernels, key=lambda k: kernels[k]["ms"])
+    dk = kernels[dominant]
+    sim.close()
+    mesh.close()
+    return {
+        "metric": METRIC,
+        "value": round(cells * args.steps / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']} deforming (displacements breathe by 30 %, period {period} steps), "
+                               "FP64; per step the geometry of the next node positions and the fused step",
+                   "cells": cells, "lattice": w["lattice"], "tau": w["tau"], "storage": "f64",
+                   "wall_s": round(wall, 3), "finite": finite, "u_max": u_max,
+                   "kernels": kernels,
+                   "device_warmup": f"{heat_steps} more untimed steps of the same run (>= {DEVICE_WARMUP_S:g} s)"},
+        # the kernel of the step with the longest average duration
+        "roofline": {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": dk["algorithmic_bytes_per_launch"],
+                     "kernel": dominant, "kernel_ms": dk["ms"]},
+    }
+
+
 def run_batch(args, torch, vlbm):
     from paper_2401_17183_amd import workloads as W
     ws = W.batch_meshes(256)
@@ -605,8 +764,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="channel",
-                    choices=["channel", "ogrid", "d3q39", "d2q21", "batch", "surrogate", "train"])
-    ap.add_argument("--precision", default="fp32", choices=sorted(STORAGE_BYTES))
+                    choices=["channel", "ogrid", "d3q39", "d2q21", "batch", "surrogate", "train", "moving"])
+    ap.add_argument("--precision", default=None, choices=sorted(STORAGE_BYTES),
+                    help="storage precision (default: fp32; fp64 for --workload moving)")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file for --workload batch")
     ap.add_argument("--persistent-only", action="store_true",
                     help="--workload batch: time only the persistent graph-replayed mode (for counter runs)")
@@ -628,6 +788,8 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = "fp64" if args.workload == "moving" else "fp32"
     if args.gpus != 1:
         print("this build runs on one GPU only: --gpus must be 1 (the multi-GPU slab "
               "decomposition is a design, not code)", file=sys.stderr)
@@ -644,13 +806,16 @@ def main():
         out = run_surrogate(args, torch, vlbm)
     elif args.workload == "train":
         out = run_train(args, torch, vlbm)
+    elif args.workload == "moving":
+        out = run_moving(args, torch, vlbm)
     else:
         out = run_single(args, torch, vlbm)
     if args.copy_ref:
         _copy_ref(torch, out, vlbm)
     if not args.no_cpu and args.workload not in ("surrogate", "train"):
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, tau_g=args.tau_g, tau=args.tau)
+        out["cpu_baseline"] = (cpu_baseline_moving(tau=args.tau) if args.workload == "moving" else
+                               cpu_baseline(args.workload, tau_g=args.tau_g, tau=args.tau))
     print(json.dumps(out), flush=True)
 
 

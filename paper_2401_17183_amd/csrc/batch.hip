@@ -22,13 +22,8 @@ namespace {
 // FF = 0 when no member has far-field links, else 2 (per-member run-time test).
 // GEN: some member uses a general collision matrix; members stepped with
 // the BGK matrix then take the same arithmetic with tau_g = tau (c1 = 0).
-// Workgroups are dealt to the 8 XCDs in turn; with one block per tile the
-// tile order is regrouped so that consecutive tiles (which share halo rows)
-// run on one XCD and its L2.
-__device__ __forceinline__ int xcd_grouped(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
+// With one block per tile the tile order is regrouped (xcd_grouped) so that
+// consecutive tiles (which share halo rows) run on one XCD and its L2.
 
 template <class L, class P, class S, class T, int BLOCK, int FF, bool GEN>
 __global__ __launch_bounds__(BLOCK) VLBM_STEP_ATTR void k_batch(const StepArgs<P, S, T>* __restrict__ args,

@@ -87,7 +87,9 @@ struct CkptHeader {
 };
 
 // Event pairs recorded around kernel launches while a sim's timing is on:
-// kind 0 = step, 1 = re-basing.  Events are reused across reads.
+// kind 0 = step, 1 = re-basing, 2 = g_i of the next positions and 3 = link
+// coefficients of a moving step.  Events are reused across reads.
+constexpr int kTimingKinds = 4;
 struct EventPool {
   std::vector<hipEvent_t> ev;      // 2 per recorded launch
   std::vector<int> kind;
@@ -329,6 +331,10 @@ int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double
   if (!m->have_geometry) return fail(VLBM_ERR_STATE, "geometry not precomputed");
   const size_t nc = m->box.ncells;
   const int d = m->d;
+  if (m->mover) {   // a moved mesh: its coefficients of the current positions, on the mover's stream
+    HIP_TRY(refresh_moving_state(m->mover));
+    HIP_TRY(hipStreamSynchronize(m->mover->stream));
+  }
   if (J) HIP_TRY(hipMemcpy(J, m->J, nc * sizeof(double), hipMemcpyDeviceToDevice));
   if (gup) HIP_TRY(hipMemcpy(gup, m->gup, nc * d * d * sizeof(double), hipMemcpyDeviceToDevice));
   if (A) HIP_TRY(hipMemcpy(A, m->A, nc * m->Q * d * sizeof(double), hipMemcpyDeviceToDevice));
@@ -338,14 +344,18 @@ int vlbm_geometry_fields(vlbm_mesh mh, double* J, double* gup, double* A, double
 
 static void free_sim(SimObj* s) {
   MeshObj* mesh = s->mesh;
+  if (mesh && mesh->mover == s) {
+    // the mesh outlives the simulation that moved it: its outgoing coefficients
+    // of the current positions are made before the boxes they come from go
+    if (refresh_moving_state(s) == hipSuccess) (void)hipStreamSynchronize(s->stream);
+    mesh->mover = nullptr;
+  }
   for (double* b : s->mv_box) dev_free(b);
   dev_free(s->mv_J);
   dev_free(s->mv_gup);
   dev_free(s->mv_gco);
   dev_free(s->mv_g);
-  dev_free(s->mv_A);
   dev_free(s->Ain);
-  dev_free(s->mv_Ain);
   dev_free(s->mv_pack);
   dev_free(s->pop[0]);
   dev_free(s->pop[1]);
@@ -497,6 +507,7 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
   if (!s) return fail(VLBM_ERR_ARG, "null sim");
   if (nsteps < 0) return fail(VLBM_ERR_ARG, "nsteps < 0");
   if (s->geo_stale) {   // the mesh moved (vlbm_step_moving): re-pack its current geometry
+    HIP_TRY(refresh_moving_state(s));
     HIP_TRY(launch_pack(s));
     s->geo_stale = 0;
   }
@@ -518,6 +529,7 @@ int vlbm_step(vlbm_sim sh, int64_t nsteps) {
     if (fused) std::swap(s->rown, s->rown_spare);
     s->buf ^= 1;
     s->t++;
+    s->state_moving = 0;   // a static step: the state's incoming coefficients are the opposite outgoing ones
     if (due && !fused) {
       if (ep) HIP_TRY(ep->begin(s->stream, 1));
       HIP_TRY(launch_rebase(s));
@@ -583,8 +595,7 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
       if ((rc = dev_alloc(&b, sizeof(double) * d * d * nbox))) return rc;
     if ((rc = dev_alloc(&s->mv_J, nc * sizeof(double))) || (rc = dev_alloc(&s->mv_gup, nc * d * d * sizeof(double))) ||
         (rc = dev_alloc(&s->mv_gco, nc * d * d * sizeof(double))) || (rc = dev_alloc(&s->mv_g, nc * d * d * sizeof(double))) ||
-        (rc = dev_alloc(&s->mv_A, nc * m->Q * d * sizeof(double))) || (rc = dev_alloc(&s->Ain, nc * m->Q * d * sizeof(double))) ||
-        (rc = dev_alloc(&s->mv_Ain, nc * m->Q * d * sizeof(double))) ||
+        (rc = dev_alloc(&s->Ain, nc * m->Q * d * sizeof(double))) ||
         (rc = dev_alloc(&s->mv_pack, moving_pack_elements(m->lattice, nc) * sizeof(double))))
       return rc;
     HIP_TRY(hipMemsetAsync(s->flags + 1, 0, sizeof(int), s->stream));
@@ -595,17 +606,25 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
     HIP_TRY(hipMemcpyAsync(s->mv_box[0], s->mv_box[1], sizeof(double) * d * d * nbox, hipMemcpyDeviceToDevice,
                            s->stream));
     s->moving = 1;
+    m->mover = s;
   }
   double wrap[3][3];
   for (int i = 0; i < 3; ++i)
     for (int k = 0; k < 3; ++k) wrap[i][k] = (wrap_next && i < d && k < d) ? wrap_next[i * 3 + k] : m->wrap[i][k];
+  EventPool* ep = s->timing_on ? static_cast<EventPool*>(s->timing) : nullptr;
   // geometry of t + 1
+  if (ep) HIP_TRY(ep->begin(s->stream, 2));
   HIP_TRY(launch_basis_of(m, coords_next, wrap, s->mv_box[2], s->mv_J, s->mv_gup, s->mv_gco, s->mv_g, s->flags + 1,
                           s->stream));
-  // coefficients of the step at t, and of the state at t + 1
-  HIP_TRY(launch_links_moving(m, s->mv_box[0], s->mv_box[1], s->mv_box[2], m->J, m->gup, m->gco, s->mv_gco,
-                              s->p.body_force, s->has_force, s->mv_pack, s->mv_Ain, s->mv_A, s->stream));
+  if (ep) HIP_TRY(ep->end(s->stream));
+  // coefficients of the step at t
+  if (ep) HIP_TRY(ep->begin(s->stream, 3));
+  HIP_TRY(launch_links_moving(m, s->mv_box[0], s->mv_box[1], s->mv_box[2], m->J, m->gup, m->gco, s->p.body_force,
+                              s->has_force, s->mv_pack, s->stream));
+  if (ep) HIP_TRY(ep->end(s->stream));
+  if (ep) HIP_TRY(ep->begin(s->stream, 0));
   HIP_TRY(launch_step_moving(s, s->mv_pack));
+  if (ep) HIP_TRY(ep->end(s->stream));
   s->buf ^= 1;
   s->t++;
   // the mesh is now at t + 1: its coordinates, translations and geometry
@@ -617,13 +636,13 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
   std::swap(m->gup, s->mv_gup);
   std::swap(m->gco, s->mv_gco);
   std::swap(m->g, s->mv_g);
-  std::swap(m->A, s->mv_A);
-  std::swap(s->Ain, s->mv_Ain);
   double* oldest = s->mv_box[0];
   s->mv_box[0] = s->mv_box[1];
   s->mv_box[1] = s->mv_box[2];
   s->mv_box[2] = oldest;
   s->geo_stale = 1;
+  s->mv_state_stale = 1;   // Ain and mesh->A of t + 1: made when first needed
+  s->state_moving = 1;
   if (s->p.audit_every > 0 && s->t % s->p.audit_every == 0) {
     const int arc = vlbm_audit_now(sh);
     if (arc) return arc;
@@ -657,7 +676,7 @@ int vlbm_kernel_timing(vlbm_sim sh, int enable, double* out) {
   }
   EventPool* ep = static_cast<EventPool*>(s->timing);
   if (out) {
-    for (int k = 0; k < 4; ++k) out[k] = 0.0;
+    for (int k = 0; k < 2 * kTimingKinds; ++k) out[k] = 0.0;
     HIP_TRY(hipStreamSynchronize(s->stream));
     for (size_t i = 0; i < ep->used; ++i) {
       float ms = 0.f;

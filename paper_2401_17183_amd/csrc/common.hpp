@@ -124,6 +124,15 @@ template <class B> struct Moving : B {
 
 __host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
 
+// Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8), each
+// XCD with its own L2.  xcd_grouped(b, nb) renumbers the nb blocks of a grid
+// so that each XCD receives one contiguous run of the logical order (a
+// bijection of [0, nb)): neighbouring logical blocks share an L2.
+__device__ __forceinline__ int xcd_grouped(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // One bit per direction (64 bits once Q exceeds 32).
 template <class L> using DirMask = typename std::conditional<(L::Q > 32), unsigned long long, unsigned>::type;
 
@@ -385,8 +394,11 @@ __device__ __forceinline__ int link_at(const LinkPlan& p, int cell, int& src) {
 // ---------------------------------------------------------------------------
 // Host-side objects.
 // ---------------------------------------------------------------------------
+struct SimObj;
+
 struct MeshObj {
   int users = 0;                 // simulations that hold the mesh
+  SimObj* mover = nullptr;       // the simulation that moved the mesh (vlbm_step_moving), if any
   bool destroy_pending = false;  // vlbm_mesh_destroy was called while simulations held it
   int lattice;
   int d, Q;
@@ -401,7 +413,7 @@ struct MeshObj {
   double* gup = nullptr;      // [d*d][cells]
   double* gco = nullptr;      // [d][d][cells]  g^i components
   double* g = nullptr;        // [d][d][cells]  g_i components
-  double* A = nullptr;        // [Q][d][cells]
+  double* A = nullptr;        // [Q][d][cells]; after a moving step made on demand (refresh_moving_state)
   vlbm_geom_report report{};
 };
 
@@ -489,10 +501,14 @@ struct SimObj {
   // state (audits), and the step's pack; allocated at the first moving step
   int moving = 0;
   int geo_stale = 0;              // the static pack no longer matches the mesh
+  // the mesh moved in the last step: the state's incoming coefficients (Ain)
+  // and the mesh's outgoing ones of the new positions (mesh->A) are made from
+  // the g_i boxes of the last two times when first needed
+  int mv_state_stale = 0;
+  int state_moving = 0;           // the last step moved the mesh: the state reads Ain
   double* mv_box[3] = {nullptr, nullptr, nullptr};
-  double *mv_J = nullptr, *mv_gup = nullptr, *mv_gco = nullptr, *mv_g = nullptr, *mv_A = nullptr;
+  double *mv_J = nullptr, *mv_gup = nullptr, *mv_gco = nullptr, *mv_g = nullptr;
   double* Ain = nullptr;          // [Q][d][cells], null on a static mesh
-  double* mv_Ain = nullptr;
   double* mv_pack = nullptr;
   // kernel timing (vlbm_kernel_timing): event pairs around the step and the
   // re-basing launches, resolved when read
@@ -541,9 +557,11 @@ size_t geometry_box_cells(const MeshObj* m);
 hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double (*wrap)[3], double* gbox, double* J,
                            double* gup, double* gco, double* g, int* dflag, hipStream_t s);
 hipError_t launch_links_moving(const MeshObj* m, const double* gprev, const double* gcur, const double* gnext,
-                               const double* J, const double* gup, const double* gco, const double* gco_next,
-                               const double* G, int has_force, double* pack, double* Ain_next, double* A_next,
-                               hipStream_t s);
+                               const double* J, const double* gup, const double* gco, const double* G, int has_force,
+                               double* pack, hipStream_t s);
+// After a moving step: Ain of the state and mesh->A of the new positions, if
+// not made since (geometry.hip); enqueued on the sim's stream.
+hipError_t refresh_moving_state(SimObj* s);
 // Allocates the mesh's FP64 geometry arrays (J, g^{ij}, g^i, g_i, A).
 int alloc_mesh_geometry(MeshObj* m);
 // Report of a geometry pass (capi.hip): flag of degenerate cells and the

@@ -23,13 +23,23 @@ namespace vlbm {
 template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   // g^{ij} carries a low word when the words are narrower than the arithmetic
   static constexpr bool LO = sizeof(AT) < sizeof(T);
+  // a moving mesh staged in LDS keeps the incoming coefficients of its first
+  // KR directions in registers: for D3Q19 the other 78 words take 39,936 bytes
+  // per 64 threads, so four blocks (one wavefront per SIMD) share a CU's
+  // 160 KiB, where all 108 words in LDS left room for two
+  static constexpr int KR = (L::MOVING && STRIDE) ? 10 : 0;
+  static_assert(KR < L::Q, "more kept directions than the lattice has");
+  // LDS words per thread: the outgoing coefficients, then the incoming ones
+  // of the directions after the first KR
+  static constexpr int LDS_WORDS = (L::Q - 1) * L::D + (L::MOVING ? (L::Q - 1 - KR) * L::D : 0);
   AT J;
   AT gup[nup<L::D>()];     // g^{ij}, upper triangle
   AT gup_lo[LO ? nup<L::D>() : 1];   // g^{ij} - gup (FP32 words, FP64 arithmetic)
   AT aext[L::D];           // a_ext^i = G . g^i
   AT Areg[STRIDE ? 1 : L::Q][L::D];
   // moving meshes: the incoming coefficients, after the outgoing ones in LDS
-  AT Ainreg[(L::MOVING && !STRIDE) ? L::Q : 1][L::D];
+  // (with LDS staging, row al - 1 holds direction al <= KR)
+  AT Ainreg[(L::MOVING && !STRIDE) ? L::Q : (KR ? KR : 1)][L::D];
   const AT* lds;
   int lofs;                // added to every LDS index (0); re-defined per fixed-point iteration
   __device__ __forceinline__ T j() const { return T(J); }
@@ -44,7 +54,9 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   __device__ __forceinline__ AT ain(int al, int i) const {
     static_assert(L::MOVING, "a static mesh takes the opposite outgoing coefficient (pair form)");
     if constexpr (STRIDE == 0) return Ainreg[al][i];
-    else return al == 0 ? AT(0) : lds[lofs + ((L::Q - 1) * L::D + (al - 1) * L::D + i) * STRIDE];
+    else if (al == 0) return AT(0);
+    else if (al <= KR) return Ainreg[al - 1][i];
+    else return lds[lofs + ((L::Q - 1) * L::D + (al - 1 - KR) * L::D + i) * STRIDE];
   }
 };
 

@@ -310,95 +310,216 @@ namespace {
 // cell, from g_i on the geometry boxes of the times t - 1, t and t + 1:
 //   outgoing  A+^i_a(q, t) = [e_a(q + c_a, t + 1) - e_a(q, t)] . g^i(q, t)
 //   incoming  A-^i_a(q, t) = [e_a(q, t) - e_a(q - c_a, t - 1)] . g^i(q, t)
-// packed with J(t), g^{ij}(t) and a_ext(t) = G . g^i(t) for the step kernel;
-// and for the state at t + 1 (audits, output mapping) its incoming
-// coefficients A-(t + 1) and its static outgoing ones (the mesh taken as
-// momentarily at rest).
+// packed with J(t), g^{ij}(t) and a_ext(t) = G . g^i(t) for the step kernel.
 struct MovingLinkArgs {
   Box box;
   int nb[3], nbox, layers;
   const double *gprev, *gcur, *gnext;      // [d][d][nbox]
   const double *J, *gup, *gco;             // time t, real cells
-  const double* gco_next;                  // time t + 1, real cells
   double G[3];
   int has_force;
   double* pack;                            // moving-mesh step words (FP64)
-  double* Ain_next;                        // [Q][d][cells]
-  double* A_next;                          // [Q][d][cells]
 };
+
+// e_a = c_a^j g_j at box cell b, from g on a box ([d][d][nbox], word j * D + k
+// holds component k of g_j); only the axes the link moves along are read.
+template <class L>
+__device__ __forceinline__ void e_at(const double* __restrict__ gb, int al, long b, int nbox, double* e) {
+#pragma unroll
+  for (int k = 0; k < L::D; ++k) {
+    double v = 0;
+#pragma unroll
+    for (int j = 0; j < L::D; ++j) {
+      const int cj = L::c(al, j);
+      if (cj != 0) v += cj * gb[(long)(j * L::D + k) * nbox + b];
+    }
+    e[k] = v;
+  }
+}
+
+// r^i = v . g^i with g^i in registers (gi[i * D + k] = component k of g^i).
+template <int D>
+__device__ __forceinline__ void project(const double* gi, const double* v, double* r) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) s += v[k] * gi[i * D + k];
+    r[i] = s;
+  }
+}
+
+template <class L>
+__device__ __forceinline__ long box_index(const int* nb, int layers, int cell, const Box& box, int s0, int s1, int s2) {
+  const int x = cell % box.n[0];
+  const int y = (cell / box.n[0]) % box.n[1];
+  const int z = cell / (box.n[0] * box.n[1]);
+  const int b0 = x + layers + s0, b1 = y + (L::D > 1 ? layers : 0) + s1, b2 = z + (L::D > 2 ? layers : 0) + s2;
+  return b0 + (long)nb[0] * (b1 + (long)nb[1] * b2);
+}
+
+// Block order of k_links_moving: one block per (x-chunk of kBlock cells, row),
+// blocks dealt to the XCDs in contiguous runs (xcd_grouped), and the rows of a
+// run taken in y-bands of kLinkBand rows that sweep z.  A cell reads g_i of
+// its 18 neighbours on two boxes; rows dealt to the XCDs in turn left those
+// reads to other XCDs' L2s and fetched 3.2x the algorithmic reads from HBM,
+// this order 1.5x (measured, D3Q19 256x128x128).
+constexpr int kLinkBand = 16;
+
+__device__ __forceinline__ int links_cell(const Box& box, int blk) {
+  const int nxc = (box.n[0] + kBlock - 1) / kBlock;
+  const int xc = blk % nxc, r = blk / nxc;
+  const int n1 = box.n[1], n2 = box.n[2];
+  const int band = r / (kLinkBand * n2), rem = r - band * kLinkBand * n2;
+  const int hb = min(kLinkBand, n1 - band * kLinkBand);   // the last band may be narrower
+  const int z = rem / hb, y = band * kLinkBand + rem % hb;
+  const int x = xc * kBlock + threadIdx.x;
+  return x < box.n[0] ? x + box.n[0] * (y + n1 * z) : -1;
+}
+
+// The pack is written once and read by the next kernel from HBM: stores that
+// do not keep it in the caches (5 % off the geometry of a step, measured).
+__device__ __forceinline__ void pstore(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
 template <class L>
 __global__ __launch_bounds__(kBlock) void k_links_moving(MovingLinkArgs a) {
   constexpr int D = L::D;
   using LM = Moving<L>;
+  const int cell = links_cell(a.box, xcd_grouped(blockIdx.x, gridDim.x));
+  if (cell < 0) return;
+  const long nc = a.box.ncells;
+  const double* __restrict__ gprev = a.gprev;
+  const double* __restrict__ gcur = a.gcur;
+  const double* __restrict__ gnext = a.gnext;
+  const double* __restrict__ gco = a.gco;
+  double* __restrict__ pk = a.pack;
+  const long b0 = box_index<L>(a.nb, a.layers, cell, a.box, 0, 0, 0);
+  // g_j(q, t) and g^i(q, t) of this cell, read once for all links
+  double gq[D * D], gi[D * D];
+#pragma unroll
+  for (int w = 0; w < D * D; ++w) {
+    gq[w] = gcur[(long)w * a.nbox + b0];
+    gi[w] = gco[w * nc + cell];
+  }
+  pstore(&pk[pack_index<LM>(Pack<LM>::J, cell)], a.J[cell]);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j)
+      pstore(&pk[pack_index<LM>(Pack<LM>::GUP + up<D>(i, j), cell)], a.gup[(i * D + j) * nc + cell]);
+#pragma unroll
+  for (int al = 1; al < L::Q; ++al) {
+    const int c0 = L::c(al, 0), c1 = D > 1 ? L::c(al, 1) : 0, c2 = D > 2 ? L::c(al, 2) : 0;
+    // the box strides of the link, from the cell's own box index
+    const long st = c0 + (long)a.nb[0] * (c1 + (long)a.nb[1] * c2);
+    double e_cur[3], e_there[3], e_back[3], v[3], r[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int cj = L::c(al, j);
+        if (cj != 0) s += cj * gq[j * D + k];
+      }
+      e_cur[k] = s;
+    }
+    e_at<L>(gnext, al, b0 + st, a.nbox, e_there);   // e_a(q + c_a, t + 1)
+    e_at<L>(gprev, al, b0 - st, a.nbox, e_back);    // e_a(q - c_a, t - 1)
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = e_there[k] - e_cur[k];
+    project<D>(gi, v, r);
+#pragma unroll
+    for (int i = 0; i < D; ++i) pstore(&pk[pack_index<LM>(Pack<LM>::A + (al - 1) * D + i, cell)], r[i]);
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = e_cur[k] - e_back[k];
+    project<D>(gi, v, r);
+#pragma unroll
+    for (int i = 0; i < D; ++i) pstore(&pk[pack_index<LM>(Pack<LM>::AIN + (al - 1) * D + i, cell)], r[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double ae = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) ae += a.G[k] * gi[i * D + k];
+    pstore(&pk[pack_index<LM>(Pack<LM>::AEXT + i, cell)], a.has_force ? ae : 0.0);
+  }
+}
+
+// The coefficients of the state at time T on a mesh that moved into it, for
+// the audits, the output mapping and a static step that follows (the mesh
+// taken as momentarily at rest), from g_i on the boxes of T - 1 and T:
+//   incoming  Ain^i_a(q) = [e_a(q, T) - e_a(q - c_a, T - 1)] . g^i(q, T)
+//   outgoing  A^i_a(q)   = [e_a(q + c_a, T) - e_a(q, T)] . g^i(q, T)
+struct StateLinkArgs {
+  Box box;
+  int nb[3], nbox, layers;
+  const double *gprev, *gcur;              // [d][d][nbox], times T - 1 and T
+  const double* gco;                       // g^i(T), real cells
+  double* Ain;                             // [Q][d][cells]
+  double* A;                               // [Q][d][cells]
+};
+
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_links_state(StateLinkArgs a) {
+  constexpr int D = L::D;
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   if (cell >= a.box.ncells) return;
   const long nc = a.box.ncells;
-  const int x = cell % a.box.n[0];
-  const int y = (cell / a.box.n[0]) % a.box.n[1];
-  const int z = cell / (a.box.n[0] * a.box.n[1]);
-  const int ly = a.layers;
-  const int bq[3] = {x + ly, y + (D > 1 ? ly : 0), z + (D > 2 ? ly : 0)};
-  auto bidx = [&](int s0, int s1, int s2) { return bq[0] + s0 + a.nb[0] * (bq[1] + s1 + a.nb[1] * (bq[2] + s2)); };
-  // e_a at a box cell from g on a box: c^j g_j
-  auto eat = [&](const double* gb, int al, long b, double* e) {
-    for (int k = 0; k < D; ++k) {
-      double v = 0;
-      for (int j = 0; j < D; ++j) {
-        const int cj = L::c(al, j);
-        if (cj != 0) v += cj * gb[(long)(j * D + k) * a.nbox + b];
-      }
-      e[k] = v;
-    }
-  };
-  auto proj = [&](const double* gco, const double* v, double* out) {
-    for (int i = 0; i < D; ++i) {
-      double s = 0;
-      for (int k = 0; k < D; ++k) s += v[k] * gco[(i * D + k) * nc + cell];
-      out[i] = s;
-    }
-  };
-  double* pk = a.pack;
-  pk[pack_index<LM>(Pack<LM>::J, cell)] = a.J[cell];
-  for (int i = 0; i < D; ++i)
-    for (int j = i; j < D; ++j) {
-      pk[pack_index<LM>(Pack<LM>::GUP + up<D>(i, j), cell)] = a.gup[(i * D + j) * nc + cell];
-      pk[pack_index<LM>(Pack<LM>::GUPLO + up<D>(i, j), cell)] = 0.0;
-    }
-  for (int i = 0; i < D; ++i) {
-    a.Ain_next[(0 * D + i) * nc + cell] = 0.0;
-    a.A_next[(0 * D + i) * nc + cell] = 0.0;
+  const double* __restrict__ gprev = a.gprev;
+  const double* __restrict__ gcur = a.gcur;
+  const double* __restrict__ gco = a.gco;
+  double* __restrict__ Ain = a.Ain;
+  double* __restrict__ A = a.A;
+  const long b0 = box_index<L>(a.nb, a.layers, cell, a.box, 0, 0, 0);
+  double gq[D * D], gi[D * D];
+#pragma unroll
+  for (int w = 0; w < D * D; ++w) {
+    gq[w] = gcur[(long)w * a.nbox + b0];
+    gi[w] = gco[w * nc + cell];
   }
-  const long b0 = bidx(0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    Ain[i * nc + cell] = 0.0;
+    A[i * nc + cell] = 0.0;
+  }
+#pragma unroll
   for (int al = 1; al < L::Q; ++al) {
     const int c0 = L::c(al, 0), c1 = D > 1 ? L::c(al, 1) : 0, c2 = D > 2 ? L::c(al, 2) : 0;
-    const long bp = bidx(c0, c1, c2), bm = bidx(-c0, -c1, -c2);
-    double e_cur[3], e_next_there[3], e_prev_back[3], e_next[3], e_cur_back[3], v[3], r[3];
-    eat(a.gcur, al, b0, e_cur);
-    eat(a.gnext, al, bp, e_next_there);
-    eat(a.gprev, al, bm, e_prev_back);
-    eat(a.gnext, al, b0, e_next);
-    eat(a.gcur, al, bm, e_cur_back);
-    for (int k = 0; k < D; ++k) v[k] = e_next_there[k] - e_cur[k];
-    proj(a.gco, v, r);
-    for (int i = 0; i < D; ++i) pk[pack_index<LM>(Pack<LM>::A + (al - 1) * D + i, cell)] = r[i];
-    for (int k = 0; k < D; ++k) v[k] = e_cur[k] - e_prev_back[k];
-    proj(a.gco, v, r);
-    for (int i = 0; i < D; ++i) pk[pack_index<LM>(Pack<LM>::AIN + (al - 1) * D + i, cell)] = r[i];
-    // the state at t + 1
-    for (int k = 0; k < D; ++k) v[k] = e_next[k] - e_cur_back[k];
-    proj(a.gco_next, v, r);
-    for (int i = 0; i < D; ++i) a.Ain_next[(al * D + i) * nc + cell] = r[i];
-    double e_static_there[3];
-    eat(a.gnext, al, bp, e_static_there);
-    for (int k = 0; k < D; ++k) v[k] = e_static_there[k] - e_next[k];
-    proj(a.gco_next, v, r);
-    for (int i = 0; i < D; ++i) a.A_next[(al * D + i) * nc + cell] = r[i];
+    const long st = c0 + (long)a.nb[0] * (c1 + (long)a.nb[1] * c2);
+    double e_cur[3], e_there[3], e_back[3], v[3], r[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int cj = L::c(al, j);
+        if (cj != 0) s += cj * gq[j * D + k];
+      }
+      e_cur[k] = s;
+    }
+    e_at<L>(gprev, al, b0 - st, a.nbox, e_back);    // e_a(q - c_a, T - 1)
+    e_at<L>(gcur, al, b0 + st, a.nbox, e_there);    // e_a(q + c_a, T)
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = e_cur[k] - e_back[k];
+    project<D>(gi, v, r);
+#pragma unroll
+    for (int i = 0; i < D; ++i) Ain[(al * D + i) * nc + cell] = r[i];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = e_there[k] - e_cur[k];
+    project<D>(gi, v, r);
+#pragma unroll
+    for (int i = 0; i < D; ++i) A[(al * D + i) * nc + cell] = r[i];
   }
-  for (int i = 0; i < D; ++i) {
-    double ae = 0;
-    for (int k = 0; k < D; ++k) ae += a.G[k] * a.gco[(i * D + k) * nc + cell];
-    pk[pack_index<LM>(Pack<LM>::AEXT + i, cell)] = a.has_force ? ae : 0.0;
+}
+
+template <class Args>
+void box_shape(const MeshObj* m, Args& a) {
+  a.box = m->box;
+  a.layers = lattice_speed(m->lattice);
+  a.nbox = 1;
+  for (int i = 0; i < 3; ++i) {
+    a.nb[i] = i < m->d ? m->box.n[i] + 2 * a.layers : 1;
+    a.nbox *= a.nb[i];
   }
 }
 
@@ -438,36 +559,48 @@ hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double 
 
 // The link coefficients of a step on a moving mesh (k_links_moving).
 hipError_t launch_links_moving(const MeshObj* m, const double* gprev, const double* gcur, const double* gnext,
-                               const double* J, const double* gup, const double* gco, const double* gco_next,
-                               const double* G, int has_force, double* pack, double* Ain_next, double* A_next,
-                               hipStream_t s) {
+                               const double* J, const double* gup, const double* gco, const double* G, int has_force,
+                               double* pack, hipStream_t s) {
   MovingLinkArgs a;
-  a.box = m->box;
-  a.layers = lattice_speed(m->lattice);
-  a.nbox = 1;
-  for (int i = 0; i < 3; ++i) {
-    a.nb[i] = i < m->d ? m->box.n[i] + 2 * a.layers : 1;
-    a.nbox *= a.nb[i];
-    a.G[i] = G[i];
-  }
+  box_shape(m, a);
+  for (int i = 0; i < 3; ++i) a.G[i] = G[i];
   a.gprev = gprev;
   a.gcur = gcur;
   a.gnext = gnext;
   a.J = J;
   a.gup = gup;
   a.gco = gco;
-  a.gco_next = gco_next;
   a.has_force = has_force;
   a.pack = pack;
-  a.Ain_next = Ain_next;
-  a.A_next = A_next;
-  const int nb = (m->box.ncells + kBlock - 1) / kBlock;
+  const int nb = (m->box.n[0] + kBlock - 1) / kBlock * m->box.n[1] * m->box.n[2];   // links_cell
   switch (m->lattice) {
     case VLBM_D2Q9: k_links_moving<D2Q9><<<nb, kBlock, 0, s>>>(a); break;
     case VLBM_D3Q19: k_links_moving<D3Q19><<<nb, kBlock, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;   // rejected by the caller
   }
   return hipGetLastError();
+}
+
+hipError_t refresh_moving_state(SimObj* sim) {
+  if (!sim->mv_state_stale) return hipSuccess;
+  const MeshObj* m = sim->mesh;
+  StateLinkArgs a;
+  box_shape(m, a);
+  // after a moving step the boxes rotate: [0] holds the previous time, [1] the current
+  a.gprev = sim->mv_box[0];
+  a.gcur = sim->mv_box[1];
+  a.gco = m->gco;
+  a.Ain = sim->Ain;
+  a.A = m->A;
+  const int nb = (m->box.ncells + kBlock - 1) / kBlock;
+  switch (m->lattice) {
+    case VLBM_D2Q9: k_links_state<D2Q9><<<nb, kBlock, 0, sim->stream>>>(a); break;
+    case VLBM_D3Q19: k_links_state<D3Q19><<<nb, kBlock, 0, sim->stream>>>(a); break;
+    default: return hipErrorInvalidValue;   // moving meshes are D2Q9 and D3Q19
+  }
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) sim->mv_state_stale = 0;
+  return e;
 }
 
 namespace {

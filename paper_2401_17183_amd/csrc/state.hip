@@ -410,7 +410,7 @@ StateArgs<S> make_args(SimObj* s) {
   a.flag = s->flags;
   a.fcache = s->fcache;
   a.fc64 = fcache_elem(s->p.precision) == 8;
-  a.Ain = s->Ain;
+  a.Ain = s->state_moving ? s->Ain : nullptr;
   return a;
 }
 
@@ -485,6 +485,8 @@ hipError_t dispatch_lattice(SimObj* s, int what, const double* r_in, const doubl
 
 hipError_t dispatch_any(SimObj* s, int what, const double* r_in, const double* u_in, double* r_out, double* u_out,
                         double* U_out, double* N_out, const double* N_in, int slot) {
+  const hipError_t e = refresh_moving_state(s);   // the coefficients of a state the mesh moved into
+  if (e != hipSuccess) return e;
   switch (s->mesh->lattice) {
     case VLBM_D2Q9: return dispatch_lattice<D2Q9>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);
     case VLBM_D3Q19: return dispatch_lattice<D3Q19>(s, what, r_in, u_in, r_out, u_out, U_out, N_out, N_in, slot);

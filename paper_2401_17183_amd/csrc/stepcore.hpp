@@ -147,7 +147,8 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
       for (int i = 0; i < L::D; ++i) {
         const S v = load_stream(gw + (Pack<L>::AIN + (a - 1) * L::D + i) * kGeoTile);
         if constexpr (ST == 0) g.Ainreg[a][i] = v;
-        else lds[((L::Q - 1) * L::D + (a - 1) * L::D + i) * ST] = v;
+        else if (a <= CellGeo<L, T, S, ST>::KR) g.Ainreg[a - 1][i] = v;
+        else lds[((L::Q - 1) * L::D + (a - 1 - CellGeo<L, T, S, ST>::KR) * L::D + i) * ST] = v;
       }
     if constexpr (ST == 0)
 #pragma unroll
@@ -244,9 +245,10 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   cell_coords(a.box, cell, x, y, z);
   // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19); so
   // do D3Q39 in FP64 (its 114 A words cannot live in registers) and a moving
-  // 3-D mesh in FP64 (outgoing and incoming coefficients, 108 words)
+  // 3-D mesh in FP64 (outgoing and incoming coefficients, 108 words, 30 of
+  // them kept in registers)
   constexpr int ST = (sizeof(S) == 4 || L::Q > 21 || (L::MOVING && D == 3)) ? BLOCK : 0;
-  __shared__ S sA[ST ? (L::MOVING ? 2 : 1) * (Q - 1) * D * BLOCK : 1];
+  __shared__ S sA[ST ? CellGeo<L, T, S, ST>::LDS_WORDS * BLOCK : 1];
   NR N[Q];
   CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
   // a wavefront without a far-field cell takes the gather compiled without the

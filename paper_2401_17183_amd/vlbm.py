@@ -310,6 +310,7 @@ class Sim:
         vlbm_init(mesh.h, C.byref(params), _P(r.data_ptr()) if r is not None else None,
                   _P(v.data_ptr()) if v is not None else None, _stream_ptr(torch), C.byref(h))
         self.h = h
+        self._stream = torch.cuda.current_stream().cuda_stream   # the stream the sim launches on
 
     def step(self, n=1):
         vlbm_step(self.h, int(n))
@@ -325,7 +326,8 @@ class Sim:
             a = np.asarray(wrap_next, dtype=np.float64)
             w[: a.shape[0], : a.shape[1]] = a
             wr = (C.c_double * 9)(*w.ravel())
-        _ready(torch)
+        if torch.cuda.current_stream().cuda_stream != self._stream:
+            _ready(torch)   # coords_next may still be in flight on another stream
         vlbm_step_moving(self.h, _P(X.data_ptr()), wr)
         self._keep = X   # the call is asynchronous: keep the input alive until the next call
 
@@ -337,11 +339,14 @@ class Sim:
     def kernel_timing(self, enable=False):
         """Kernel durations recorded since the last read (then cleared), and
         turn the recording on or off for the following steps:
-        {step_ms, step_launches, rebase_ms, rebase_launches}."""
-        out = (C.c_double * 4)()
+        {step_ms, step_launches, rebase_ms, rebase_launches, basis_ms,
+        basis_launches, links_ms, links_launches} (the last four: the geometry
+        kernels of moving steps)."""
+        out = (C.c_double * 8)()
         vlbm_kernel_timing(self.h, int(bool(enable)), out)
         return {"step_ms": out[0], "step_launches": int(out[1]), "rebase_ms": out[2],
-                "rebase_launches": int(out[3])}
+                "rebase_launches": int(out[3]), "basis_ms": out[4], "basis_launches": int(out[5]),
+                "links_ms": out[6], "links_launches": int(out[7])}
 
     def set_fixed_point(self, max_iter=0, tol=-1.0):
         vlbm_set_fixed_point(self.h, int(max_iter), float(tol))
@@ -437,6 +442,7 @@ class _Member(Sim):
         self.mesh = mesh
         self.params = params
         self.h = h
+        self._stream = None   # members run on the batch's own stream
 
     def close(self):
         self.h = None

@@ -27,7 +27,7 @@ CASES = [("D2Q9", (12, 10), 0.2, None), ("D2Q9", (12, 10), 0.2, (2e-4, -1e-4)),
          ("D3Q19", (7, 6, 5), 0.1, None), ("D3Q19", (7, 6, 5), 0.1, (2e-4, -1e-4, 5e-5))]
 
 
-def _setup(name, n, amp, G, motion, seed=3):
+def _setup(name, n, amp, G, motion, seed=3, audit_every=1):
     v = _vlbm()
     w = W.wavy_periodic(name, n, amp)
     w["tau"] = 0.7
@@ -42,7 +42,7 @@ def _setup(name, n, amp, G, motion, seed=3):
     o = moving.MovingSim(lat, n, X0, wr0, w["dx"], w["tau"], body_force=G)
     o.init(rho, u)
     m = v.Mesh(name, n, X0, w["faces"], wr0, w["dx"])
-    s = v.Sim(m, v.make_params(w["tau"], body_force=G, precision="fp64", audit_every=1),
+    s = v.Sim(m, v.make_params(w["tau"], body_force=G, precision="fp64", audit_every=audit_every),
               rho=rho.ravel(), u=u.reshape(d, -1))
     return w, o, s, m
 
@@ -74,6 +74,52 @@ def test_moving_mesh_fp64_parity_and_balance(name, n, amp, G):
             bal = a["mom_I"] - aud[k - 1]["mom_I"] - aud[k - 1]["force_impulse"]
             assert np.max(np.abs(bal)) <= 1e-12 * mass0, (k, bal)
     s.close()
+    m.close()
+
+
+@pytest.mark.parametrize("name,n,amp", [("D2Q9", (12, 10), 0.2), ("D3Q19", (7, 6, 5), 0.1)], ids=str)
+def test_state_coefficients_made_when_read(name, n, amp):
+    """Moving steps without audits leave the coefficients of the state the
+    mesh moved into (its incoming ones, and the mesh's outgoing ones of the
+    new positions) to be made when first read: after 6 steps the mid-link
+    momentum of an audit matches the oracle's, the moments match the oracle's
+    output mapping (the mesh momentarily at rest), and the mesh's A matches the
+    static geometry of the final positions; static steps then continue on the
+    re-packed mesh, conserving mass."""
+    announce(f"moving mesh {name} {n}: state coefficients made when read")
+    w, o, s, m = _setup(name, n, amp, None, MOTION, audit_every=0)
+    Q, d = lattice.by_name(name).Q, len(n)
+    for t in range(6):
+        X, wr = W.moving_coords(w, t + 1, **MOTION)
+        s.step_moving(X, wr)
+        o.step(X, wr)
+    s.sync()
+    mass0 = o.mass()
+    s.audit_now()
+    a = s.audits()[-1]
+    assert np.allclose(a["mom_I"][:d], o.momentum_I(), rtol=0, atol=1e-12 * mass0), (a["mom_I"], o.momentum_I())
+    mg, mo = s.moments(), o.moments()
+    assert float(np.max(np.abs(mg["rho"].cpu().numpy() - mo["rho"].ravel()))) <= 1e-12
+    assert float(np.max(np.abs(mg["u"].cpu().numpy() - mo["u"].reshape(d, -1)))) <= 1e-12
+    A = m.fields()["A"].cpu().numpy()
+    A_o = o._static_geo().A.reshape(Q, d, -1)
+    assert float(np.max(np.abs(A - A_o))) <= 1e-12
+    s.step(3)
+    s.audit_now()
+    s.sync()
+    assert abs(s.audits()[-1]["mass"] / mass0 - 1) <= 1e-13
+    s.close()
+    m.close()
+    # a mesh outliving the simulation that moved it keeps the coefficients of
+    # its final positions
+    w, o, s, m = _setup(name, n, amp, None, MOTION, audit_every=0)
+    for t in range(3):
+        X, wr = W.moving_coords(w, t + 1, **MOTION)
+        s.step_moving(X, wr)
+        o.step(X, wr)
+    s.close()
+    A = m.fields()["A"].cpu().numpy()
+    assert float(np.max(np.abs(A - o._static_geo().A.reshape(Q, d, -1)))) <= 1e-12
     m.close()
 
 
