@@ -246,12 +246,12 @@ int vlbm_step_stats(vlbm_sim s, int enable, uint64_t* out);
 
 /* Durations of the kernels launched by vlbm_step and vlbm_step_moving while
  * enabled, from HIP events recorded on the sim's stream around each launch
- * (off by default).  out (host [8], may be NULL) receives, since the previous
+ * (off by default).  out (host [6], may be NULL) receives, since the previous
  * read: [0] total milliseconds and [1] count of the fused step launches, [2]
  * and [3] the same for the re-basing launches of the deviation storage, [4]
- * and [5] for the g_i of the next node positions and [6] and [7] for the link
- * coefficients that a moving step computes before its fused step; the record
- * is then cleared.  Synchronises when out is not NULL. */
+ * and [5] for the geometry (g_i, J, g^i, g^{ij}) of the next node positions
+ * that a moving step computes before its fused step; the record is then
+ * cleared.  Synchronises when out is not NULL. */
 int vlbm_kernel_timing(vlbm_sim s, int enable, double* out);
 
 /* Change the fixed point's cap and tolerance for the following steps (the

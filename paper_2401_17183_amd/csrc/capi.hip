@@ -87,9 +87,9 @@ struct CkptHeader {
 };
 
 // Event pairs recorded around kernel launches while a sim's timing is on:
-// kind 0 = step, 1 = re-basing, 2 = g_i of the next positions and 3 = link
-// coefficients of a moving step.  Events are reused across reads.
-constexpr int kTimingKinds = 4;
+// kind 0 = step, 1 = re-basing, 2 = g_i of the next node positions (moving
+// steps).  Events are reused across reads.
+constexpr int kTimingKinds = 3;
 struct EventPool {
   std::vector<hipEvent_t> ev;      // 2 per recorded launch
   std::vector<int> kind;
@@ -356,7 +356,6 @@ static void free_sim(SimObj* s) {
   dev_free(s->mv_gco);
   dev_free(s->mv_g);
   dev_free(s->Ain);
-  dev_free(s->mv_pack);
   dev_free(s->pop[0]);
   dev_free(s->pop[1]);
   dev_free(s->geo);
@@ -595,8 +594,7 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
       if ((rc = dev_alloc(&b, sizeof(double) * d * d * nbox))) return rc;
     if ((rc = dev_alloc(&s->mv_J, nc * sizeof(double))) || (rc = dev_alloc(&s->mv_gup, nc * d * d * sizeof(double))) ||
         (rc = dev_alloc(&s->mv_gco, nc * d * d * sizeof(double))) || (rc = dev_alloc(&s->mv_g, nc * d * d * sizeof(double))) ||
-        (rc = dev_alloc(&s->Ain, nc * m->Q * d * sizeof(double))) ||
-        (rc = dev_alloc(&s->mv_pack, moving_pack_elements(m->lattice, nc) * sizeof(double))))
+        (rc = dev_alloc(&s->Ain, nc * m->Q * d * sizeof(double))))
       return rc;
     HIP_TRY(hipMemsetAsync(s->flags + 1, 0, sizeof(int), s->stream));
     // g_i of the current mesh on its box (into the t box; the real-cell arrays
@@ -617,13 +615,9 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
   HIP_TRY(launch_basis_of(m, coords_next, wrap, s->mv_box[2], s->mv_J, s->mv_gup, s->mv_gco, s->mv_g, s->flags + 1,
                           s->stream));
   if (ep) HIP_TRY(ep->end(s->stream));
-  // coefficients of the step at t
-  if (ep) HIP_TRY(ep->begin(s->stream, 3));
-  HIP_TRY(launch_links_moving(m, s->mv_box[0], s->mv_box[1], s->mv_box[2], m->J, m->gup, m->gco, s->p.body_force,
-                              s->has_force, s->mv_pack, s->stream));
-  if (ep) HIP_TRY(ep->end(s->stream));
+  // the step at t, its link coefficients computed from the boxes of t - 1, t, t + 1
   if (ep) HIP_TRY(ep->begin(s->stream, 0));
-  HIP_TRY(launch_step_moving(s, s->mv_pack));
+  HIP_TRY(launch_step_moving(s, s->mv_box[0], s->mv_box[1], s->mv_box[2]));
   if (ep) HIP_TRY(ep->end(s->stream));
   s->buf ^= 1;
   s->t++;

@@ -427,11 +427,11 @@ struct MeshObj {
 template <class L> struct Pack {
   static constexpr int J = 0;
   static constexpr int GUP = 1;
-  // a >= 1: static meshes S^i = A^i_a + A^i_(a+1) (odd a) and D^i = A^i_(a-1) - A^i_a
-  // (even a), the pair form; moving meshes the outgoing A^i_a
+  // a >= 1: S^i = A^i_a + A^i_(a+1) (odd a) and D^i = A^i_(a-1) - A^i_a (even
+  // a), the pair form (moving meshes have no pack: their step computes the
+  // coefficients from g_i)
   static constexpr int A = GUP + nup<L::D>();
-  static constexpr int AIN = A + (L::Q - 1) * L::D;           // moving meshes: incoming coefficients
-  static constexpr int AEXT = AIN + (L::MOVING ? (L::Q - 1) * L::D : 0);   // present if force
+  static constexpr int AEXT = A + (L::Q - 1) * L::D;          // present if force
   static constexpr int UINF = AEXT + L::D;                    // present if far field
   static constexpr int GUPLO = UINF + L::D;                   // low words of g^{ij}
   static constexpr int WORDS = GUPLO + nup<L::D>();
@@ -450,10 +450,6 @@ __host__ __device__ __forceinline__ size_t pack_index(int word, int cell) {
 // Elements of a packed geometry of nc cells (the last tile is whole).
 inline size_t pack_elements(int words, size_t nc) {
   return (nc + kGeoTile - 1) / kGeoTile * kGeoTile * (size_t)words;
-}
-
-inline size_t moving_pack_elements(int lattice, size_t nc) {
-  return pack_elements(lattice == VLBM_D2Q9 ? Pack<Moving<D2Q9>>::WORDS : Pack<Moving<D3Q19>>::WORDS, nc);
 }
 
 inline int pack_words(int lattice) {
@@ -497,8 +493,8 @@ struct SimObj {
   unsigned long long* stats = nullptr;   // device [kStatSlots][4]: fixed-point statistics of the steps (when stats_on)
   int stats_on = 0;
   // moving mesh (vlbm_step_moving): g_i boxes of the times t - 1, t, t + 1,
-  // the real-cell geometry of t + 1, the incoming coefficients of the current
-  // state (audits), and the step's pack; allocated at the first moving step
+  // the real-cell geometry of t + 1 and the incoming coefficients of the
+  // current state (audits); allocated at the first moving step
   int moving = 0;
   int geo_stale = 0;              // the static pack no longer matches the mesh
   // the mesh moved in the last step: the state's incoming coefficients (Ain)
@@ -509,7 +505,6 @@ struct SimObj {
   double* mv_box[3] = {nullptr, nullptr, nullptr};
   double *mv_J = nullptr, *mv_gup = nullptr, *mv_gco = nullptr, *mv_g = nullptr;
   double* Ain = nullptr;          // [Q][d][cells], null on a static mesh
-  double* mv_pack = nullptr;
   // kernel timing (vlbm_kernel_timing): event pairs around the step and the
   // re-basing launches, resolved when read
   int timing_on = 0;
@@ -556,9 +551,6 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
 size_t geometry_box_cells(const MeshObj* m);
 hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double (*wrap)[3], double* gbox, double* J,
                            double* gup, double* gco, double* g, int* dflag, hipStream_t s);
-hipError_t launch_links_moving(const MeshObj* m, const double* gprev, const double* gcur, const double* gnext,
-                               const double* J, const double* gup, const double* gco, const double* G, int has_force,
-                               double* pack, hipStream_t s);
 // After a moving step: Ain of the state and mesh->A of the new positions, if
 // not made since (geometry.hip); enqueued on the sim's stream.
 hipError_t refresh_moving_state(SimObj* s);
@@ -571,8 +563,9 @@ int set_error(int code, const char* fmt, ...);
 hipError_t launch_pack(SimObj* s);
 hipError_t launch_init(SimObj* s, const double* rho, const double* u, int* dflag);
 hipError_t launch_step(SimObj* s);
-// one step on a moving mesh with the given FP64 moving-mesh pack (step.hip)
-hipError_t launch_step_moving(SimObj* s, const double* pack);
+// one step on a moving mesh from g_i on the geometry boxes of the times
+// t - 1, t and t + 1 and the mesh's real-cell geometry of t (step.hip)
+hipError_t launch_step_moving(SimObj* s, const double* gprev, const double* gcur, const double* gnext);
 hipError_t launch_moments(SimObj* s, double* rho, double* u, double* U, int* dflag);
 hipError_t launch_get_pop(SimObj* s, double* N);
 hipError_t launch_set_pop(SimObj* s, const double* N);

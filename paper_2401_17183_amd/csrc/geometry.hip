@@ -306,21 +306,6 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
 
 namespace {
 
-// Link coefficients of a step on a moving mesh (time t to t + 1), per real
-// cell, from g_i on the geometry boxes of the times t - 1, t and t + 1:
-//   outgoing  A+^i_a(q, t) = [e_a(q + c_a, t + 1) - e_a(q, t)] . g^i(q, t)
-//   incoming  A-^i_a(q, t) = [e_a(q, t) - e_a(q - c_a, t - 1)] . g^i(q, t)
-// packed with J(t), g^{ij}(t) and a_ext(t) = G . g^i(t) for the step kernel.
-struct MovingLinkArgs {
-  Box box;
-  int nb[3], nbox, layers;
-  const double *gprev, *gcur, *gnext;      // [d][d][nbox]
-  const double *J, *gup, *gco;             // time t, real cells
-  double G[3];
-  int has_force;
-  double* pack;                            // moving-mesh step words (FP64)
-};
-
 // e_a = c_a^j g_j at box cell b, from g on a box ([d][d][nbox], word j * D + k
 // holds component k of g_j); only the axes the link moves along are read.
 template <class L>
@@ -356,93 +341,6 @@ __device__ __forceinline__ long box_index(const int* nb, int layers, int cell, c
   const int z = cell / (box.n[0] * box.n[1]);
   const int b0 = x + layers + s0, b1 = y + (L::D > 1 ? layers : 0) + s1, b2 = z + (L::D > 2 ? layers : 0) + s2;
   return b0 + (long)nb[0] * (b1 + (long)nb[1] * b2);
-}
-
-// Block order of k_links_moving: one block per (x-chunk of kBlock cells, row),
-// blocks dealt to the XCDs in contiguous runs (xcd_grouped), and the rows of a
-// run taken in y-bands of kLinkBand rows that sweep z.  A cell reads g_i of
-// its 18 neighbours on two boxes; rows dealt to the XCDs in turn left those
-// reads to other XCDs' L2s and fetched 3.2x the algorithmic reads from HBM,
-// this order 1.5x (measured, D3Q19 256x128x128).
-constexpr int kLinkBand = 16;
-
-__device__ __forceinline__ int links_cell(const Box& box, int blk) {
-  const int nxc = (box.n[0] + kBlock - 1) / kBlock;
-  const int xc = blk % nxc, r = blk / nxc;
-  const int n1 = box.n[1], n2 = box.n[2];
-  const int band = r / (kLinkBand * n2), rem = r - band * kLinkBand * n2;
-  const int hb = min(kLinkBand, n1 - band * kLinkBand);   // the last band may be narrower
-  const int z = rem / hb, y = band * kLinkBand + rem % hb;
-  const int x = xc * kBlock + threadIdx.x;
-  return x < box.n[0] ? x + box.n[0] * (y + n1 * z) : -1;
-}
-
-// The pack is written once and read by the next kernel from HBM: stores that
-// do not keep it in the caches (5 % off the geometry of a step, measured).
-__device__ __forceinline__ void pstore(double* p, double v) { __builtin_nontemporal_store(v, p); }
-
-template <class L>
-__global__ __launch_bounds__(kBlock) void k_links_moving(MovingLinkArgs a) {
-  constexpr int D = L::D;
-  using LM = Moving<L>;
-  const int cell = links_cell(a.box, xcd_grouped(blockIdx.x, gridDim.x));
-  if (cell < 0) return;
-  const long nc = a.box.ncells;
-  const double* __restrict__ gprev = a.gprev;
-  const double* __restrict__ gcur = a.gcur;
-  const double* __restrict__ gnext = a.gnext;
-  const double* __restrict__ gco = a.gco;
-  double* __restrict__ pk = a.pack;
-  const long b0 = box_index<L>(a.nb, a.layers, cell, a.box, 0, 0, 0);
-  // g_j(q, t) and g^i(q, t) of this cell, read once for all links
-  double gq[D * D], gi[D * D];
-#pragma unroll
-  for (int w = 0; w < D * D; ++w) {
-    gq[w] = gcur[(long)w * a.nbox + b0];
-    gi[w] = gco[w * nc + cell];
-  }
-  pstore(&pk[pack_index<LM>(Pack<LM>::J, cell)], a.J[cell]);
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j)
-      pstore(&pk[pack_index<LM>(Pack<LM>::GUP + up<D>(i, j), cell)], a.gup[(i * D + j) * nc + cell]);
-#pragma unroll
-  for (int al = 1; al < L::Q; ++al) {
-    const int c0 = L::c(al, 0), c1 = D > 1 ? L::c(al, 1) : 0, c2 = D > 2 ? L::c(al, 2) : 0;
-    // the box strides of the link, from the cell's own box index
-    const long st = c0 + (long)a.nb[0] * (c1 + (long)a.nb[1] * c2);
-    double e_cur[3], e_there[3], e_back[3], v[3], r[3];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double s = 0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const int cj = L::c(al, j);
-        if (cj != 0) s += cj * gq[j * D + k];
-      }
-      e_cur[k] = s;
-    }
-    e_at<L>(gnext, al, b0 + st, a.nbox, e_there);   // e_a(q + c_a, t + 1)
-    e_at<L>(gprev, al, b0 - st, a.nbox, e_back);    // e_a(q - c_a, t - 1)
-#pragma unroll
-    for (int k = 0; k < D; ++k) v[k] = e_there[k] - e_cur[k];
-    project<D>(gi, v, r);
-#pragma unroll
-    for (int i = 0; i < D; ++i) pstore(&pk[pack_index<LM>(Pack<LM>::A + (al - 1) * D + i, cell)], r[i]);
-#pragma unroll
-    for (int k = 0; k < D; ++k) v[k] = e_cur[k] - e_back[k];
-    project<D>(gi, v, r);
-#pragma unroll
-    for (int i = 0; i < D; ++i) pstore(&pk[pack_index<LM>(Pack<LM>::AIN + (al - 1) * D + i, cell)], r[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    double ae = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) ae += a.G[k] * gi[i * D + k];
-    pstore(&pk[pack_index<LM>(Pack<LM>::AEXT + i, cell)], a.has_force ? ae : 0.0);
-  }
 }
 
 // The coefficients of the state at time T on a mesh that moved into it, for
@@ -554,30 +452,6 @@ hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double 
   a.partial = nullptr;
   a.gbox = gbox;
   k_basis<<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
-  return hipGetLastError();
-}
-
-// The link coefficients of a step on a moving mesh (k_links_moving).
-hipError_t launch_links_moving(const MeshObj* m, const double* gprev, const double* gcur, const double* gnext,
-                               const double* J, const double* gup, const double* gco, const double* G, int has_force,
-                               double* pack, hipStream_t s) {
-  MovingLinkArgs a;
-  box_shape(m, a);
-  for (int i = 0; i < 3; ++i) a.G[i] = G[i];
-  a.gprev = gprev;
-  a.gcur = gcur;
-  a.gnext = gnext;
-  a.J = J;
-  a.gup = gup;
-  a.gco = gco;
-  a.has_force = has_force;
-  a.pack = pack;
-  const int nb = (m->box.n[0] + kBlock - 1) / kBlock * m->box.n[1] * m->box.n[2];   // links_cell
-  switch (m->lattice) {
-    case VLBM_D2Q9: k_links_moving<D2Q9><<<nb, kBlock, 0, s>>>(a); break;
-    case VLBM_D3Q19: k_links_moving<D3Q19><<<nb, kBlock, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;   // rejected by the caller
-  }
   return hipGetLastError();
 }
 

@@ -117,12 +117,40 @@ __device__ __forceinline__ X* word(X* __restrict__ base, int w, int nc) {
   return base + (size_t)w * (size_t)nc;
 }
 
-// Packed geometry of one cell.  With ST > 0 the link coefficients are staged
-// in LDS (this thread's column of lds, stride ST) instead of registers; only
-// this thread reads its column.
+// Placement of a cell's coefficient of slot a >= 1, component i: the outgoing
+// one (put_a) in registers or in this thread's LDS column (stride ST), the
+// incoming one of a moving mesh (put_ain) in registers for the first KR
+// directions when staged, after the outgoing ones in LDS otherwise.
+template <class L, class S, class T, int ST>
+__device__ __forceinline__ void put_a(CellGeo<L, T, S, ST>& g, S* lds, int a, int i, S v) {
+  if constexpr (ST == 0) g.Areg[a][i] = v;
+  else lds[((a - 1) * L::D + i) * ST] = v;
+}
+template <class L, class S, class T, int ST>
+__device__ __forceinline__ void put_ain(CellGeo<L, T, S, ST>& g, S* lds, int a, int i, S v) {
+  if constexpr (ST == 0) g.Ainreg[a][i] = v;
+  else if (a <= CellGeo<L, T, S, ST>::KR) g.Ainreg[a - 1][i] = v;
+  else lds[((L::Q - 1) * L::D + (a - 1 - CellGeo<L, T, S, ST>::KR) * L::D + i) * ST] = v;
+}
+// The zero coefficients of the rest direction (registers only).
+template <class L, class S, class T, int ST>
+__device__ __forceinline__ void zero_rest(CellGeo<L, T, S, ST>& g) {
+  if constexpr (ST == 0) {
+#pragma unroll
+    for (int i = 0; i < L::D; ++i) {
+      g.Areg[0][i] = S(0);
+      if constexpr (L::MOVING) g.Ainreg[0][i] = S(0);
+    }
+  }
+}
+
+// Packed geometry of one cell (static meshes).  With ST > 0 the link
+// coefficients are staged in LDS (this thread's column of lds, stride ST)
+// instead of registers; only this thread reads its column.
 template <class L, class S, class T, int ST>
 __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ geo, int nc, int cell, int has_force,
                                                           S* lds) {
+  static_assert(!L::MOVING, "a moving mesh computes its coefficients (MovingGeo)");
   CellGeo<L, T, S, ST> g;
   // this cell's element of word 0 of its tile; word w is w * kGeoTile further
   const S* __restrict__ gw = geo + pack_index<L>(0, cell);
@@ -140,20 +168,6 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
       if constexpr (ST == 0) g.Areg[a][i] = v;
       else lds[((a - 1) * L::D + i) * ST] = v;
     }
-  if constexpr (L::MOVING) {
-#pragma unroll
-    for (int a = 1; a < L::Q; ++a)
-#pragma unroll
-      for (int i = 0; i < L::D; ++i) {
-        const S v = load_stream(gw + (Pack<L>::AIN + (a - 1) * L::D + i) * kGeoTile);
-        if constexpr (ST == 0) g.Ainreg[a][i] = v;
-        else if (a <= CellGeo<L, T, S, ST>::KR) g.Ainreg[a - 1][i] = v;
-        else lds[((L::Q - 1) * L::D + (a - 1 - CellGeo<L, T, S, ST>::KR) * L::D + i) * ST] = v;
-      }
-    if constexpr (ST == 0)
-#pragma unroll
-      for (int i = 0; i < L::D; ++i) g.Ainreg[0][i] = S(0);
-  }
   if constexpr (ST == 0)
 #pragma unroll
     for (int i = 0; i < L::D; ++i) g.Areg[0][i] = S(0);
@@ -229,11 +243,108 @@ __device__ __forceinline__ void store_slot(const StepArgs<P, S, T>& a, int al, i
   else store_stream(word(a.out, al, nc) + cell, PopE<P>(v));
 }
 
+// Geometry source of a static mesh: the packed words (load_pack).
+struct PackGeo {};
+
+// Geometry source of a step on a moving mesh (time t to t + 1, FP64): each
+// cell computes its link coefficients from g_i on the geometry boxes of the
+// times t - 1, t and t + 1,
+//   outgoing  A+^i_a(q, t) = [e_a(q + c_a, t + 1) - e_a(q, t)] . g^i(q, t)
+//   incoming  A-^i_a(q, t) = [e_a(q, t) - e_a(q - c_a, t - 1)] . g^i(q, t)
+// with e_a = c_a^j g_j, and takes J, g^{ij} and a_ext = G . g^i of time t from
+// the real-cell arrays: no coefficient words go through HBM.
+struct MovingGeo {
+  const double* gprev;   // [d][d][nbox], word j * d + k: component k of g_j
+  const double* gcur;
+  const double* gnext;
+  const double* J;       // time t, real cells: [cells], [d][d][cells], [d][d][cells]
+  const double* gup;
+  const double* gco;
+  int nb[3], nbox, layers;
+  double G[3];
+
+  template <class L, class P, class S, class T, int ST>
+  __device__ __forceinline__ CellGeo<L, T, S, ST> load(const StepArgs<P, S, T>& a, int x, int y, int z, int cell,
+                                                       S* lds) const {
+    static_assert(L::MOVING && std::is_same<S, double>::value, "moving meshes step in FP64");
+    constexpr int D = L::D;
+    const int nc = a.box.ncells;
+    const double* __restrict__ gp = gprev;
+    const double* __restrict__ gc = gcur;
+    const double* __restrict__ gn = gnext;
+    const double* __restrict__ gi_w = gco;
+    CellGeo<L, T, S, ST> g;
+    g.J = J[cell];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i; j < D; ++j) g.gup[up<D>(i, j)] = gup[(i * D + j) * nc + cell];
+    const int b0 = (x + layers) + nb[0] * ((D > 1 ? y + layers : 0) + nb[1] * (D > 2 ? z + layers : 0));
+    // g_j(q, t) and g^i(q, t) of this cell, read once for all links
+    double gq[D * D], gi[D * D];
+#pragma unroll
+    for (int w = 0; w < D * D; ++w) {
+      gq[w] = gc[(size_t)w * nbox + b0];
+      gi[w] = gi_w[(size_t)w * nc + cell];
+    }
+#pragma unroll
+    for (int al = 1; al < L::Q; ++al) {
+      const int st = L::c(al, 0) + nb[0] * ((D > 1 ? L::c(al, 1) : 0) + nb[1] * (D > 2 ? L::c(al, 2) : 0));
+      double e_cur[D], e_there[D], e_back[D], v[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double sc = 0, sn = 0, sp = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const int cj = L::c(al, j);
+          if (cj != 0) {
+            sc += cj * gq[j * D + k];
+            sn += cj * gn[(size_t)(j * D + k) * nbox + (b0 + st)];   // e_a(q + c_a, t + 1)
+            sp += cj * gp[(size_t)(j * D + k) * nbox + (b0 - st)];   // e_a(q - c_a, t - 1)
+          }
+        }
+        e_cur[k] = sc;
+        e_there[k] = sn;
+        e_back[k] = sp;
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) v[k] = e_there[k] - e_cur[k];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double r = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) r += v[k] * gi[i * D + k];
+        put_a<L, S, T, ST>(g, lds, al, i, r);
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) v[k] = e_cur[k] - e_back[k];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double r = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) r += v[k] * gi[i * D + k];
+        put_ain<L, S, T, ST>(g, lds, al, i, r);
+      }
+    }
+    zero_rest<L, S, T, ST>(g);
+    g.lds = lds;
+    g.lofs = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double ae = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) ae += G[k] * gi[i * D + k];
+      g.aext[i] = a.has_force ? ae : 0.0;
+    }
+    return g;
+  }
+};
+
 // One cell of one mesh; BLOCK threads per workgroup share the LDS staging.
 // GEN: general collision matrix (compiled separately, so that the BGK kernels
-// carry none of its registers).
-template <class L, class P, class S, class T, int BLOCK, int FF = 2, bool GEN = false>
-__device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) {
+// carry none of its registers).  Src supplies the cell's geometry.
+template <class L, class P, class S, class T, int BLOCK, int FF = 2, bool GEN = false, class Src = PackGeo>
+__device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell, const Src& src = Src()) {
   constexpr int Q = L::Q;
   constexpr int D = L::D;
   // registers hold populations in the storage type, decoded deviations in the
@@ -250,7 +361,12 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell) 
   constexpr int ST = (sizeof(S) == 4 || L::Q > 21 || (L::MOVING && D == 3)) ? BLOCK : 0;
   __shared__ S sA[ST ? CellGeo<L, T, S, ST>::LDS_WORDS * BLOCK : 1];
   NR N[Q];
-  CellGeo<L, T, S, ST> g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
+  // (the static path calls load_pack here directly: a wrapper around it was
+  // measured to change the register allocation of the static kernels)
+  CellGeo<L, T, S, ST> g;
+  if constexpr (std::is_same<Src, PackGeo>::value)
+    g = load_pack<L, S, T, ST>(a.geo, nc, cell, a.has_force, sA + (ST ? threadIdx.x : 0));
+  else g = src.template load<L, P, S, T, ST>(a, x, y, z, cell, sA + (ST ? threadIdx.x : 0));
   // a wavefront without a far-field cell takes the gather compiled without the
   // far-field fill: with the fill in the same code, the compiler issues each
   // direction's loads only after the previous direction's data arrived

@@ -340,13 +340,11 @@ class Sim:
         """Kernel durations recorded since the last read (then cleared), and
         turn the recording on or off for the following steps:
         {step_ms, step_launches, rebase_ms, rebase_launches, basis_ms,
-        basis_launches, links_ms, links_launches} (the last four: the geometry
-        kernels of moving steps)."""
-        out = (C.c_double * 8)()
+        basis_launches} (the last two: the geometry kernel of moving steps)."""
+        out = (C.c_double * 6)()
         vlbm_kernel_timing(self.h, int(bool(enable)), out)
         return {"step_ms": out[0], "step_launches": int(out[1]), "rebase_ms": out[2],
-                "rebase_launches": int(out[3]), "basis_ms": out[4], "basis_launches": int(out[5]),
-                "links_ms": out[6], "links_launches": int(out[7])}
+                "rebase_launches": int(out[3]), "basis_ms": out[4], "basis_launches": int(out[5])}
 
     def set_fixed_point(self, max_iter=0, tol=-1.0):
         vlbm_set_fixed_point(self.h, int(max_iter), float(tol))

@@ -34,18 +34,16 @@ def test_batch_bytes_per_cell():
 
 def test_moving_bytes_per_cell():
     """Moving D3Q19 mesh, FP64: 19 populations read and written (304 bytes),
-    J, 6 g^{ij} and 2 x 54 outgoing and incoming coefficient words (920)."""
-    assert bench.moving_bytes_per_cell(19, 3, False) == 1224
-    assert bench.moving_bytes_per_cell(9, 2, True) == 144 + (1 + 3 + 32 + 2) * 8
+    J, 6 g^{ij}, 9 g^i and 27 box words of g_i (344 bytes); D2Q9: 144 + (1 +
+    3 + 4 + 12) x 8."""
+    assert bench.moving_bytes_per_cell(19, 3) == 648
+    assert bench.moving_bytes_per_cell(9, 2) == 304
 
 
-def test_moving_geometry_bytes():
-    """D3Q19 on a 4x3x2 mesh (box 6x5x4 = 120 nodes): k_basis reads 3 and
-    writes 9 words per box node and writes 1 + 27 words per cell; k_links_moving
-    reads 1 + 6 + 9 + 27 and writes 1 + 6 + 108 + 3 words per cell."""
-    basis, links = bench.moving_geometry_bytes(19, 3, 24, 120, False)
-    assert basis == 8 * (120 * 12 + 24 * 28)
-    assert links == 8 * 24 * (43 + 118)
+def test_moving_basis_bytes():
+    """D3Q19 on a 4x3x2 mesh (box 6x5x4 = 120 nodes): 3 words read and 9
+    written per box node, 1 + 27 words written per cell."""
+    assert bench.moving_basis_bytes(3, 24, 120) == 8 * (120 * 12 + 24 * 28)
 
 
 def test_more_than_one_gpu_is_refused():
