@@ -242,6 +242,8 @@ PROFILE_STEM = {"channel": "k_step_d3q19_channel_256x128x128", "d3q39": "k_step_
 STEP_SOURCES = ["paper_2401_17183_amd/csrc/common.hpp", "paper_2401_17183_amd/csrc/dynamics.hpp",
                 "paper_2401_17183_amd/csrc/stepcore.hpp", "paper_2401_17183_amd/csrc/step.hip"]
 BATCH_SOURCES = STEP_SOURCES[:3] + ["paper_2401_17183_amd/csrc/batch.hip"]
+MOVING_SOURCES = STEP_SOURCES[:3] + ["paper_2401_17183_amd/csrc/moving.hip"]
+MOVING_PROFILE = "k_step_moving_d3q19_wavy_256x128x128_fp64.md"
 
 
 def profile_values(profile, sources, require=None):
@@ -459,10 +461,11 @@ def moving_bytes_per_cell(Q, d):
 
 
 def moving_basis_bytes(d, ncells, nbox):
-    """Bytes of k_basis per launch: the d coordinates of each geometry-box node
-    read, g_i written on the box (d*d words) and J, g^i, g_i and g^{ij} (full
-    d x d) on the real cells."""
-    return 8 * (nbox * (d + d * d) + ncells * (1 + 3 * d * d))
+    """Bytes of k_basis per launch of a moving step: the d coordinates of each
+    geometry-box node read, g_i written on the box (d*d words) and J, g^i and
+    g^{ij} (full d x d) on the real cells (the real-cell g_i are made on
+    demand from the box)."""
+    return 8 * (nbox * (d + d * d) + ncells * (1 + 2 * d * d))
 
 
 def run_moving(args, torch, vlbm):
@@ -533,6 +536,10 @@ def run_moving(args, torch, vlbm):
                          "GBps": round(nbytes / (kms / 1e3) / 1e9, 1)}
     dominant = max(kernels, key=lambda k: kernels[k]["ms"])
     dk = kernels[dominant]
+    traffic = binding = None
+    if dominant == "k_step_moving" and args.tau is None:
+        traffic = profiled_traffic(MOVING_PROFILE, MOVING_SOURCES)
+        binding = profiled_valu(MOVING_PROFILE, MOVING_SOURCES)
     sim.close()
     mesh.close()
     return {
@@ -548,9 +555,14 @@ def run_moving(args, torch, vlbm):
                    "device_warmup": f"{heat_steps} more untimed steps of the same run (>= {DEVICE_WARMUP_S:g} s)"},
         # the kernel of the step with the longest average duration
         "roofline": {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "algorithmic_bytes_per_launch": dk["algorithmic_bytes_per_launch"],
-                     "kernel": dominant, "kernel_ms": dk["ms"]},
+                     "kernel": dominant, "kernel_ms": dk["ms"],
+                     # what limits the kernel short of the HBM roofline (SQ counters of the same
+                     # sources), or None where no counter summary covers it
+                     "binding_limit": binding},
     }
 
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvlbm.so")
 
-SOURCES = ["capi.hip", "geometry.hip", "step.hip", "state.hip", "batch.hip", "nn.hip", "surrogate.hip",
+SOURCES = ["capi.hip", "geometry.hip", "step.hip", "moving.hip", "state.hip", "batch.hip", "nn.hip", "surrogate.hip",
            "membench.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

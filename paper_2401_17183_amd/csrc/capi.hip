@@ -354,7 +354,6 @@ static void free_sim(SimObj* s) {
   dev_free(s->mv_J);
   dev_free(s->mv_gup);
   dev_free(s->mv_gco);
-  dev_free(s->mv_g);
   dev_free(s->Ain);
   dev_free(s->pop[0]);
   dev_free(s->pop[1]);
@@ -593,13 +592,13 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
     for (double*& b : s->mv_box)
       if ((rc = dev_alloc(&b, sizeof(double) * d * d * nbox))) return rc;
     if ((rc = dev_alloc(&s->mv_J, nc * sizeof(double))) || (rc = dev_alloc(&s->mv_gup, nc * d * d * sizeof(double))) ||
-        (rc = dev_alloc(&s->mv_gco, nc * d * d * sizeof(double))) || (rc = dev_alloc(&s->mv_g, nc * d * d * sizeof(double))) ||
+        (rc = dev_alloc(&s->mv_gco, nc * d * d * sizeof(double))) ||
         (rc = dev_alloc(&s->Ain, nc * m->Q * d * sizeof(double))))
       return rc;
     HIP_TRY(hipMemsetAsync(s->flags + 1, 0, sizeof(int), s->stream));
     // g_i of the current mesh on its box (into the t box; the real-cell arrays
     // it also writes are the next-time scratch), then t - 1 = t
-    HIP_TRY(launch_basis_of(m, m->coords, m->wrap, s->mv_box[1], s->mv_J, s->mv_gup, s->mv_gco, s->mv_g,
+    HIP_TRY(launch_basis_of(m, m->coords, m->wrap, s->mv_box[1], s->mv_J, s->mv_gup, s->mv_gco, nullptr,
                             s->flags + 1, s->stream));
     HIP_TRY(hipMemcpyAsync(s->mv_box[0], s->mv_box[1], sizeof(double) * d * d * nbox, hipMemcpyDeviceToDevice,
                            s->stream));
@@ -612,7 +611,7 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
   EventPool* ep = s->timing_on ? static_cast<EventPool*>(s->timing) : nullptr;
   // geometry of t + 1
   if (ep) HIP_TRY(ep->begin(s->stream, 2));
-  HIP_TRY(launch_basis_of(m, coords_next, wrap, s->mv_box[2], s->mv_J, s->mv_gup, s->mv_gco, s->mv_g, s->flags + 1,
+  HIP_TRY(launch_basis_of(m, coords_next, wrap, s->mv_box[2], s->mv_J, s->mv_gup, s->mv_gco, nullptr, s->flags + 1,
                           s->stream));
   if (ep) HIP_TRY(ep->end(s->stream));
   // the step at t, its link coefficients computed from the boxes of t - 1, t, t + 1
@@ -629,7 +628,6 @@ int vlbm_step_moving(vlbm_sim sh, const double* coords_next, const double* wrap_
   std::swap(m->J, s->mv_J);
   std::swap(m->gup, s->mv_gup);
   std::swap(m->gco, s->mv_gco);
-  std::swap(m->g, s->mv_g);
   double* oldest = s->mv_box[0];
   s->mv_box[0] = s->mv_box[1];
   s->mv_box[1] = s->mv_box[2];

@@ -497,13 +497,14 @@ struct SimObj {
   // current state (audits); allocated at the first moving step
   int moving = 0;
   int geo_stale = 0;              // the static pack no longer matches the mesh
-  // the mesh moved in the last step: the state's incoming coefficients (Ain)
-  // and the mesh's outgoing ones of the new positions (mesh->A) are made from
-  // the g_i boxes of the last two times when first needed
+  // the mesh moved in the last step: the state's incoming coefficients (Ain),
+  // the mesh's outgoing ones of the new positions (mesh->A) and its real-cell
+  // g_i (mesh->g) are made from the g_i boxes of the last two times when
+  // first needed
   int mv_state_stale = 0;
   int state_moving = 0;           // the last step moved the mesh: the state reads Ain
   double* mv_box[3] = {nullptr, nullptr, nullptr};
-  double *mv_J = nullptr, *mv_gup = nullptr, *mv_gco = nullptr, *mv_g = nullptr;
+  double *mv_J = nullptr, *mv_gup = nullptr, *mv_gco = nullptr;
   double* Ain = nullptr;          // [Q][d][cells], null on a static mesh
   // kernel timing (vlbm_kernel_timing): event pairs around the step and the
   // re-basing launches, resolved when read

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
   for (int i = 0; i < d; ++i)
     for (int k = 0; k < d; ++k) {
       a.gco[(i * d + k) * nc + cell] = gc[i][k];
-      a.g[(i * d + k) * nc + cell] = gv[i][k];
+      if (a.g) a.g[(i * d + k) * nc + cell] = gv[i][k];   // null: left to the caller (moving steps)
     }
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j) {
@@ -345,7 +345,8 @@ __device__ __forceinline__ long box_index(const int* nb, int layers, int cell, c
 
 // The coefficients of the state at time T on a mesh that moved into it, for
 // the audits, the output mapping and a static step that follows (the mesh
-// taken as momentarily at rest), from g_i on the boxes of T - 1 and T:
+// taken as momentarily at rest), from g_i on the boxes of T - 1 and T (and
+// g_i(T) on the real cells, which the moving step's k_basis leaves out):
 //   incoming  Ain^i_a(q) = [e_a(q, T) - e_a(q - c_a, T - 1)] . g^i(q, T)
 //   outgoing  A^i_a(q)   = [e_a(q + c_a, T) - e_a(q, T)] . g^i(q, T)
 struct StateLinkArgs {
@@ -355,6 +356,7 @@ struct StateLinkArgs {
   const double* gco;                       // g^i(T), real cells
   double* Ain;                             // [Q][d][cells]
   double* A;                               // [Q][d][cells]
+  double* g;                               // g_i(T) on the real cells, [d][d][cells]
 };
 
 template <class L>
@@ -374,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_links_state(StateLinkArgs a) {
   for (int w = 0; w < D * D; ++w) {
     gq[w] = gcur[(long)w * a.nbox + b0];
     gi[w] = gco[w * nc + cell];
+    a.g[w * nc + cell] = gq[w];
   }
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -425,8 +428,8 @@ void box_shape(const MeshObj* m, Args& a) {
 
 // g_i on the geometry box and J, g^{ij}, g^i, g_i on the real cells of the
 // node positions `coords` (mesh layout) with periodic translations `wrap`,
-// into the given arrays (pass 1 of the precompute); degenerate cells set bits
-// of *dflag.
+// into the given arrays (pass 1 of the precompute; g may be null: the real-cell
+// g_i are then not written); degenerate cells set bits of *dflag.
 hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double (*wrap)[3], double* gbox, double* J,
                            double* gup, double* gco, double* g, int* dflag, hipStream_t s) {
   GeoArgs a;
@@ -466,6 +469,7 @@ hipError_t refresh_moving_state(SimObj* sim) {
   a.gco = m->gco;
   a.Ain = sim->Ain;
   a.A = m->A;
+  a.g = m->g;
   const int nb = (m->box.ncells + kBlock - 1) / kBlock;
   switch (m->lattice) {
     case VLBM_D2Q9: k_links_state<D2Q9><<<nb, kBlock, 0, sim->stream>>>(a); break;

@@ -155,48 +155,8 @@ hipError_t step_lattice(SimObj* s) {
   }
 }
 
-// One step on a moving mesh (FP64; periodic meshes): every cell computes the
-// outgoing and incoming link coefficients of time t from g_i on the geometry
-// boxes of t - 1, t and t + 1 (MovingGeo).
-template <class L, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_step_moving(StepArgs<double, double, double> a, MovingGeo mg) {
-  step_cell<Moving<L>, double, double, double, BLOCK, 0, false>(a, blockIdx.x * BLOCK + threadIdx.x, mg);
-}
-
-template <class L, int B>
-hipError_t step_moving_typed(SimObj* s, const MovingGeo& mg) {
-  StepArgs<double, double, double> a = make_step_args<double, double, double>(s);
-  a.geo = nullptr;
-  const int nb = (a.box.ncells + B - 1) / B;
-  k_step_moving<L, B><<<nb, B, 0, s->stream>>>(a, mg);
-  return hipGetLastError();
-}
-
 }  // namespace
 
-hipError_t launch_step_moving(SimObj* s, const double* gprev, const double* gcur, const double* gnext) {
-  const MeshObj* m = s->mesh;
-  MovingGeo mg;
-  mg.gprev = gprev;
-  mg.gcur = gcur;
-  mg.gnext = gnext;
-  mg.J = m->J;
-  mg.gup = m->gup;
-  mg.gco = m->gco;
-  mg.layers = lattice_speed(m->lattice);
-  mg.nbox = 1;
-  for (int i = 0; i < 3; ++i) {
-    mg.nb[i] = i < m->d ? m->box.n[i] + 2 * mg.layers : 1;
-    mg.nbox *= mg.nb[i];
-    mg.G[i] = s->p.body_force[i];
-  }
-  switch (m->lattice) {
-    case VLBM_D2Q9: return step_moving_typed<D2Q9, kBlock>(s, mg);
-    // 78 of the 108 coefficient words staged in LDS: 39,936 bytes per 64 threads
-    case VLBM_D3Q19: return step_moving_typed<D3Q19, 64>(s, mg);
-    default: return hipErrorInvalidValue;   // rejected by the caller
-  }
-}
 
 hipError_t launch_step(SimObj* s) {
   switch (s->mesh->lattice) {

@@ -42,8 +42,8 @@ def test_moving_bytes_per_cell():
 
 def test_moving_basis_bytes():
     """D3Q19 on a 4x3x2 mesh (box 6x5x4 = 120 nodes): 3 words read and 9
-    written per box node, 1 + 27 words written per cell."""
-    assert bench.moving_basis_bytes(3, 24, 120) == 8 * (120 * 12 + 24 * 28)
+    written per box node, 1 + 18 words written per cell."""
+    assert bench.moving_basis_bytes(3, 24, 120) == 8 * (120 * 12 + 24 * 19)
 
 
 def test_more_than_one_gpu_is_refused():

@@ -83,9 +83,9 @@ def test_state_coefficients_made_when_read(name, n, amp):
     mesh moved into (its incoming ones, and the mesh's outgoing ones of the
     new positions) to be made when first read: after 6 steps the mid-link
     momentum of an audit matches the oracle's, the moments match the oracle's
-    output mapping (the mesh momentarily at rest), and the mesh's A matches the
-    static geometry of the final positions; static steps then continue on the
-    re-packed mesh, conserving mass."""
+    output mapping (the mesh momentarily at rest), and the mesh's A, g_i and J
+    match the static geometry of the final positions; static steps then
+    continue on the re-packed mesh, conserving mass."""
     announce(f"moving mesh {name} {n}: state coefficients made when read")
     w, o, s, m = _setup(name, n, amp, None, MOTION, audit_every=0)
     Q, d = lattice.by_name(name).Q, len(n)
@@ -101,9 +101,11 @@ def test_state_coefficients_made_when_read(name, n, amp):
     mg, mo = s.moments(), o.moments()
     assert float(np.max(np.abs(mg["rho"].cpu().numpy() - mo["rho"].ravel()))) <= 1e-12
     assert float(np.max(np.abs(mg["u"].cpu().numpy() - mo["u"].reshape(d, -1)))) <= 1e-12
-    A = m.fields()["A"].cpu().numpy()
-    A_o = o._static_geo().A.reshape(Q, d, -1)
-    assert float(np.max(np.abs(A - A_o))) <= 1e-12
+    f, geo = m.fields(), o._static_geo()
+    A_o = geo.A.reshape(Q, d, -1)
+    assert float(np.max(np.abs(f["A"].cpu().numpy() - A_o))) <= 1e-12
+    assert float(np.max(np.abs(f["g"].cpu().numpy() - geo.g.reshape(d, d, -1)))) <= 1e-12
+    assert float(np.max(np.abs(f["J"].cpu().numpy() - geo.J.ravel()))) <= 1e-12
     s.step(3)
     s.audit_now()
     s.sync()
