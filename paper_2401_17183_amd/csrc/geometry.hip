@@ -37,10 +37,12 @@ struct GeoArgs {
 // x(q) for q outside the real box: periodic axes wrap the index (any number of
 // periods) and add the translation, non-periodic axes read the ghost node
 // layers of the coordinate input.
+template <int D>
 __device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
   int idx[3] = {0, 0, 0};
   double shift[3] = {0, 0, 0};
-  for (int i = 0; i < a.d; ++i) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
     int qi = q[i];
     if (a.box.face[i][0] == VLBM_PERIODIC) {
       const int n = a.box.n[i];
@@ -54,40 +56,33 @@ __device__ inline void coord_at(const GeoArgs& a, const int* q, double* x) {
     }
   }
   const long off = ((long)idx[2] * a.m[1] + idx[1]) * a.m[0] + idx[0];
-  for (int k = 0; k < a.d; ++k) {
-    double v = a.coords[off * a.d + k];
-    for (int i = 0; i < a.d; ++i) v += shift[i] * a.wrap[i][k];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double v = a.coords[off * D + k];
+#pragma unroll
+    for (int i = 0; i < D; ++i) v += shift[i] * a.wrap[i][k];
     x[k] = v;
   }
 }
 
-// Pass 1: one thread per box cell (real cells and `layers` layers around them):
+// Pass 1 for one box cell b (real cells and `layers` layers around them) at
+// index q, from its node x0 and the nodes xp[i] = x(q + e_i), xm[i] = x(q - e_i):
 // D_{+-i} (eq. (distance)), beta_i and g_i (eq. (tangent)), J (eq. (jacobian)),
 // g^i (eq. (covectors)), g^{ij} (eq. (inverse)).
-__global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
-  const int b = blockIdx.x * kBlock + threadIdx.x;
-  if (b >= a.nbox) return;
-  const int d = a.d;
-  int bq[3] = {b % a.nb[0], (b / a.nb[0]) % a.nb[1], b / (a.nb[0] * a.nb[1])};
-  int q[3] = {0, 0, 0};
-  for (int i = 0; i < d; ++i) q[i] = bq[i] - a.layers;
-  double x0[3];
-  coord_at(a, q, x0);
+template <int D>
+__device__ __forceinline__ void basis_cell(const GeoArgs& a, int b, const int* q, const double* x0,
+                                           const double (*xp)[3], const double (*xm)[3]) {
+  constexpr int d = D;
   double gv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   int bad = 0;
+  #pragma unroll
   for (int i = 0; i < d; ++i) {
-    int qp[3] = {q[0], q[1], q[2]};
-    int qm[3] = {q[0], q[1], q[2]};
-    qp[i] += 1;
-    qm[i] -= 1;
-    double xp[3], xm[3];
-    coord_at(a, qp, xp);
-    coord_at(a, qm, xm);
     double Dp[3], Dm[3], df[3];
     double np2 = 0, nm2 = 0, nd2 = 0;
+    #pragma unroll
     for (int k = 0; k < d; ++k) {
-      Dp[k] = xp[k] - x0[k];
-      Dm[k] = xm[k] - x0[k];
+      Dp[k] = xp[i][k] - x0[k];
+      Dm[k] = xm[i][k] - x0[k];
       df[k] = Dp[k] - Dm[k];
       np2 += Dp[k] * Dp[k];
       nm2 += Dm[k] * Dm[k];
@@ -98,11 +93,12 @@ __global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
       nd2 = 1.0;
     }
     const double beta = (sqrt(np2) + sqrt(nm2)) / sqrt(nd2);
+    #pragma unroll
     for (int k = 0; k < d; ++k) gv[i][k] = beta * df[k] * a.inv2dx;
   }
   double J;
   double gc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  if (d == 2) {
+  if constexpr (d == 2) {
     J = gv[0][0] * gv[1][1] - gv[0][1] * gv[1][0];
     gc[0][0] = gv[1][1] / J;
     gc[0][1] = -gv[1][0] / J;
@@ -116,6 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
                            gv[1][0] * gv[2][1] - gv[1][1] * gv[2][0]};
     const double c31[3] = {gv[2][1] * gv[0][2] - gv[2][2] * gv[0][1], gv[2][2] * gv[0][0] - gv[2][0] * gv[0][2],
                            gv[2][0] * gv[0][1] - gv[2][1] * gv[0][0]};
+    #pragma unroll
     for (int k = 0; k < 3; ++k) {
       gc[0][k] = c23[k] / J;
       gc[1][k] = c31[k] / J;
@@ -124,27 +121,62 @@ __global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
   }
   if (!(J > 0.0)) bad |= 2;
   if (bad) atomicOr(a.flag, bad);
+  #pragma unroll
   for (int i = 0; i < d; ++i)
+    #pragma unroll
     for (int k = 0; k < d; ++k) a.gbox[(long)(i * d + k) * a.nbox + b] = gv[i][k];
   // real cell?
   bool real = true;
+  #pragma unroll
   for (int i = 0; i < d; ++i) real = real && q[i] >= 0 && q[i] < a.box.n[i];
   if (!real) return;
   const int cell = q[0] + a.box.n[0] * (q[1] + a.box.n[1] * q[2]);
   const long nc = a.box.ncells;
   a.J[cell] = J;
+  #pragma unroll
   for (int i = 0; i < d; ++i)
+    #pragma unroll
     for (int k = 0; k < d; ++k) {
       a.gco[(i * d + k) * nc + cell] = gc[i][k];
       if (a.g) a.g[(i * d + k) * nc + cell] = gv[i][k];   // null: left to the caller (moving steps)
     }
+  #pragma unroll
   for (int i = 0; i < d; ++i)
+    #pragma unroll
     for (int j = 0; j < d; ++j) {
       double s = 0;
+      #pragma unroll
       for (int k = 0; k < d; ++k) s += gc[i][k] * gc[j][k];
       a.gup[(i * d + j) * nc + cell] = s;
     }
 }
+
+// Pass 1: one thread per box cell, each reading its 2d + 1 nodes; D = a.d
+// (a compile-time dimension keeps the per-node arrays in registers: with the
+// run-time one they went to scratch memory and the kernel took 1.8x as long).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_basis(GeoArgs a) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= a.nbox) return;
+  constexpr int d = D;
+  int bq[3] = {b % a.nb[0], (b / a.nb[0]) % a.nb[1], b / (a.nb[0] * a.nb[1])};
+  int q[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < d; ++i) q[i] = bq[i] - a.layers;
+  double x0[3], xp[3][3], xm[3][3];
+  coord_at<D>(a, q, x0);
+#pragma unroll
+  for (int i = 0; i < d; ++i) {
+    int qp[3] = {q[0], q[1], q[2]};
+    int qm[3] = {q[0], q[1], q[2]};
+    qp[i] += 1;
+    qm[i] -= 1;
+    coord_at<D>(a, qp, xp[i]);
+    coord_at<D>(a, qm, xm[i]);
+  }
+  basis_cell<D>(a, b, q, x0, xp, xm);
+}
+
 
 __device__ inline void sym_eig_range(int d, const double* G /* d*d */, double& lo, double& hi) {
   if (d == 2) {
@@ -292,7 +324,8 @@ hipError_t launch_geometry(MeshObj* m, hipStream_t s, int* dflag, double* partia
   a.flag = dflag;
   a.partial = partial;
   a.gbox = gbox;
-  k_basis<<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  if (a.d == 2) k_basis<2><<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  else k_basis<3><<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (m->lattice) {
@@ -454,7 +487,8 @@ hipError_t launch_basis_of(const MeshObj* m, const double* coords, const double 
   a.flag = dflag;
   a.partial = nullptr;
   a.gbox = gbox;
-  k_basis<<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  if (a.d == 2) k_basis<2><<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  else k_basis<3><<<(a.nbox + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 
