@@ -516,10 +516,14 @@ def run_moving(args, torch, vlbm):
     t0 = time.perf_counter()
     ms = _timed(torch, stream, steps, args.steps)
     wall = time.perf_counter() - t0
-    # the next steps of the same run, with HIP events around each kernel
+    # the next steps of the same run, with HIP events around each kernel, then
+    # as many with the fixed point's iteration counts
     sim.kernel_timing(True)
     steps(args.steps)
     kt = sim.kernel_timing(False)
+    sim.step_stats(True)
+    steps(args.steps)
+    st = sim.step_stats(False)
     sim.sync()
     mo = sim.moments()
     finite = bool(torch.isfinite(mo["u"]).all().item())
@@ -552,6 +556,8 @@ def run_moving(args, torch, vlbm):
                    "cells": cells, "lattice": w["lattice"], "tau": w["tau"], "storage": "f64",
                    "wall_s": round(wall, 3), "finite": finite, "u_max": u_max,
                    "kernels": kernels,
+                   "fp_iters_per_cell_step": round(st["iters_per_cell"], 3),
+                   "fp_wave_max_iters_per_step": round(st["wave_max_iters"], 3),
                    "device_warmup": f"{heat_steps} more untimed steps of the same run (>= {DEVICE_WARMUP_S:g} s)"},
         # the kernel of the step with the longest average duration
         "roofline": {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
