@@ -217,7 +217,10 @@ int vlbm_step(vlbm_sim s, int64_t nsteps);
  *   A-^i_a(q, t) = [e_a(q, t) - e_a(q - c_a, t - 1)] . g^i(q, t)
  * (eq. (delta-flux) takes A+ + A-); before its first moving step the mesh is
  * taken as at rest.  The geometry of t + 1 (eqs. (distance) to (gamma)) is
- * computed on the device every step.  Mass and the mid-link Euclidean
+ * computed on the device every step, and the fused step computes each cell's
+ * A+ and A- from g_i of the times t - 1, t and t + 1 (no coefficient array
+ * goes through HBM); the coefficients of the state at t + 1 (audits, output
+ * mapping, a static step that follows) are computed when first needed.  Mass and the mid-link Euclidean
  * momentum with each e_a at the time the particle has it are conserved; the
  * audits report that momentum, the output mapping treats the mesh as
  * momentarily at rest.  FP64 storage, BGK, D2Q9 / D3Q19, periodic axes only,
