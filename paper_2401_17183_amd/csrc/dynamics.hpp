@@ -24,10 +24,13 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   // g^{ij} carries a low word when the words are narrower than the arithmetic
   static constexpr bool LO = sizeof(AT) < sizeof(T);
   // a moving mesh staged in LDS keeps the incoming coefficients of its first
-  // KR directions in registers: for D3Q19 the other 78 words take 39,936 bytes
-  // per 64 threads, so four blocks (one wavefront per SIMD) share a CU's
-  // 160 KiB, where all 108 words in LDS left room for two
-  static constexpr int KR = (L::MOVING && STRIDE) ? 10 : 0;
+  // KR directions in registers.  D3Q19: with all 108 words in LDS two 64-thread
+  // blocks fit a CU's 160 KiB; with 10 directions kept (78 words, 39,936
+  // bytes per block) four, one wavefront per SIMD; keeping 16 (60 words,
+  // 30,720 bytes, 510 VGPRs and no spills) reads fewer words from LDS in each
+  // fixed-point iteration and measured 8 % faster than 10 (14: 476 VGPRs, 1 %
+  // slower than 16; 18 spills)
+  static constexpr int KR = (L::MOVING && STRIDE) ? 16 : 0;
   static_assert(KR < L::Q, "more kept directions than the lattice has");
   // LDS words per thread: the outgoing coefficients, then the incoming ones
   // of the directions after the first KR

@@ -73,7 +73,7 @@ hipError_t launch_step_moving(SimObj* s, const double* gprev, const double* gcur
   }
   switch (m->lattice) {
     case VLBM_D2Q9: return step_moving_typed<D2Q9, kBlock>(s, mg);
-    // 78 of the 108 coefficient words staged in LDS: 39,936 bytes per 64 threads
+    // 60 of the 108 coefficient words staged in LDS: 30,720 bytes per 64 threads
     case VLBM_D3Q19: return step_moving_typed<D3Q19, 64>(s, mg);
     default: return hipErrorInvalidValue;   // rejected by the caller
   }

@@ -356,7 +356,7 @@ __device__ __forceinline__ void step_cell(const StepArgs<P, S, T>& a, int cell, 
   cell_coords(a.box, cell, x, y, z);
   // FP32 geometry stages A in LDS (55 KB per 256-thread block for D3Q19); so
   // do D3Q39 in FP64 (its 114 A words cannot live in registers) and a moving
-  // 3-D mesh in FP64 (outgoing and incoming coefficients, 108 words, 30 of
+  // 3-D mesh in FP64 (outgoing and incoming coefficients, 108 words, 48 of
   // them kept in registers)
   constexpr int ST = (sizeof(S) == 4 || L::Q > 21 || (L::MOVING && D == 3)) ? BLOCK : 0;
   __shared__ S sA[ST ? CellGeo<L, T, S, ST>::LDS_WORDS * BLOCK : 1];
