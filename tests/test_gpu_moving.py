@@ -1,7 +1,9 @@
 """Steps on a moving mesh (vlbm_step_moving) against the moving-mesh oracle:
 FP64 populations within 1e-12 on deforming and rotating periodic meshes, the
 audits' mass and mid-link momentum against the oracle's and their balance,
-the reduction to the static step, and the calls it rejects."""
+the state's coefficients made when first read, the reduction to the static
+step, the calls it rejects, and the benchmarked configuration at full size
+(balances every step, reduction to the static step)."""
 import numpy as np
 import pytest
 
