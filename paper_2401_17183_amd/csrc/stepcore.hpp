@@ -165,8 +165,15 @@ __device__ __forceinline__ CellGeo<L, T, S, ST> load_pack(const S* __restrict__ 
 #pragma unroll
     for (int i = 0; i < L::D; ++i) {
       const S v = load_stream(gw + (Pack<L>::A + (a - 1) * L::D + i) * kGeoTile);
-      if constexpr (ST == 0) g.Areg[a][i] = v;
-      else lds[((a - 1) * L::D + i) * ST] = v;
+      constexpr int KA = CellGeo<L, T, S, ST>::KA;
+      if constexpr (ST == 0) {
+        g.Areg[a][i] = v;
+      } else if constexpr (KA > 0) {
+        if (a <= KA) g.Areg[a - 1][i] = v;
+        else lds[((a - 1 - KA) * L::D + i) * ST] = v;
+      } else {
+        lds[((a - 1) * L::D + i) * ST] = v;
+      }
     }
   if constexpr (ST == 0)
 #pragma unroll
