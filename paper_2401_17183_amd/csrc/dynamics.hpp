@@ -32,11 +32,15 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   // slower than 16; 18 spills)
   static constexpr int KR = (L::MOVING && STRIDE) ? 16 : 0;
   static_assert(KR < L::Q, "more kept directions than the lattice has");
-  // a static mesh with FP64 words staged in LDS (D3Q39) keeps the outgoing
-  // coefficients of its first KA directions in registers: the other 105 words
-  // take 53,760 bytes per 64 threads, so three blocks share a CU's 160 KiB
-  // (all 114 in LDS: two); 454 VGPRs, measured 33 % faster
-  static constexpr int KA = (!L::MOVING && STRIDE && sizeof(AT) == 8) ? 3 : 0;
+  // a static D3Q39 mesh keeps the outgoing coefficients of its first KA
+  // directions in registers where that fits more blocks into a CU's 160 KiB
+  // of LDS: FP64 words, 105 of 114 in LDS take 53,760 bytes per 64 threads,
+  // three blocks instead of two (454 VGPRs, measured 33 % faster); FP32 words
+  // with FP32 arithmetic, 26,880 bytes, six blocks instead of five (238
+  // VGPRs, 7 % faster).  FP32 words with FP64 arithmetic have no registers
+  // to spare.
+  static constexpr int KA =
+      (!L::MOVING && STRIDE && (sizeof(AT) == 8 || (L::Q > 21 && sizeof(T) == 4))) ? 3 : 0;
   // LDS words per thread: the outgoing coefficients, then the incoming ones
   // of the directions after the first KR
   static constexpr int LDS_WORDS = (L::Q - 1 - KA) * L::D + (L::MOVING ? (L::Q - 1 - KR) * L::D : 0);
