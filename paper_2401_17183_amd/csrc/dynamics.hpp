@@ -37,10 +37,14 @@ template <class L, class T, class AT = T, int STRIDE = 0> struct CellGeo {
   // of LDS: FP64 words, 105 of 114 in LDS take 53,760 bytes per 64 threads,
   // three blocks instead of two (454 VGPRs, measured 33 % faster); FP32 words
   // with FP32 arithmetic, 26,880 bytes, six blocks instead of five (238
-  // VGPRs, 7 % faster).  FP32 words with FP64 arithmetic have no registers
-  // to spare.
+  // VGPRs, 7 % faster).  D3Q19 with FP32 arithmetic (FP32C, FP16S, BF16S)
+  // keeps one direction: 52,224 bytes per 256 threads, three blocks per CU
+  // with the kernel held to three wavefronts per SIMD (164 VGPRs; 16-bit
+  // storage 9 % faster, FP32C unchanged at its HBM limit).  FP32 words with
+  // FP64 arithmetic have no registers to spare.
   static constexpr int KA =
-      (!L::MOVING && STRIDE && (sizeof(AT) == 8 || (L::Q > 21 && sizeof(T) == 4))) ? 3 : 0;
+      (!L::MOVING && STRIDE && (sizeof(AT) == 8 || (L::Q > 21 && sizeof(T) == 4))) ? 3
+      : (!L::MOVING && STRIDE && L::Q == 19 && sizeof(T) == 4) ? 1 : 0;
   // LDS words per thread: the outgoing coefficients, then the incoming ones
   // of the directions after the first KR
   static constexpr int LDS_WORDS = (L::Q - 1 - KA) * L::D + (L::MOVING ? (L::Q - 1 - KR) * L::D : 0);

@@ -8,7 +8,7 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// FP32 geometry: two waves per SIMD (see VLBM_STEP_ATTR).
+// FP32 geometry: two or three waves per SIMD (see VLBM_STEP_ATTR).
 // FF = 0 when the mesh has no far-field links, else 2 (wave-uniform run-time
 // test, which keeps the far-field variant free of spills).
 // GEN: general collision matrix (its own instantiation, always with FF = 2).

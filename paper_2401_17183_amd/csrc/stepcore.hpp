@@ -11,12 +11,14 @@
 
 namespace vlbm {
 
-// Two resident waves per SIMD: the LDS staging of A (55 KB per 256-thread
-// block for D3Q19 FP32) allows two blocks per CU, and the register budget is
-// held to that occupancy.
-#ifndef VLBM_STEP_ATTR
-#define VLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 8)))
-#endif
+// Resident waves per SIMD that the register budget is held to: two where the
+// LDS staging of A (55 KB per 256-thread block for D3Q19 FP32) allows two
+// blocks per CU; three for D3Q19 with FP32 arithmetic, whose LDS holds three
+// blocks once one direction stays in registers (CellGeo::KA).
+template <class L, class S, class T> constexpr int step_min_waves() {
+  return (L::Q == 19 && sizeof(S) == 4 && sizeof(T) == 4) ? 3 : 2;
+}
+#define VLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(step_min_waves<L, S, T>(), 8)))
 
 // P: population storage tag (PopCodec); S: geometry storage type; T: arithmetic type.
 template <class P, class S, class T> struct StepArgs {
