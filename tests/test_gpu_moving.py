@@ -26,7 +26,10 @@ def announce(msg):
 
 MOTION = dict(breathe=0.3, omega=0.01, period=12.0)
 CASES = [("D2Q9", (12, 10), 0.2, None), ("D2Q9", (12, 10), 0.2, (2e-4, -1e-4)),
-         ("D3Q19", (7, 6, 5), 0.1, None), ("D3Q19", (7, 6, 5), 0.1, (2e-4, -1e-4, 5e-5))]
+         ("D3Q19", (7, 6, 5), 0.1, None), ("D3Q19", (7, 6, 5), 0.1, (2e-4, -1e-4, 5e-5)),
+         # rows longer than a block (two x-chunks) and a ragged last y-band of the
+         # moving step's block order (bands of 16 rows: 16 + 4)
+         ("D3Q19", (70, 20, 6), 0.1, None), ("D2Q9", (300, 20), 0.2, None)]
 
 
 def _setup(name, n, amp, G, motion, seed=3, audit_every=1):
@@ -124,6 +127,28 @@ def test_state_coefficients_made_when_read(name, n, amp):
     s.close()
     A = m.fields()["A"].cpu().numpy()
     assert float(np.max(np.abs(A - o._static_geo().A.reshape(Q, d, -1)))) <= 1e-12
+    m.close()
+
+
+def test_kernel_timing_of_moving_steps():
+    """vlbm_kernel_timing records one fused step and one geometry launch per
+    moving step, with positive durations, and nothing once it is off."""
+    v = _vlbm()
+    announce("moving mesh kernel timing")
+    w = W.wavy_periodic("D3Q19", (7, 6, 5), 0.1)
+    w["tau"] = 0.7
+    m = v.Mesh.from_workload(w)
+    s = v.Sim(m, v.make_params(0.7, precision="fp64"))
+    s.kernel_timing(True)
+    for t in range(5):
+        s.step_moving(*W.moving_coords(w, t + 1, **MOTION))
+    kt = s.kernel_timing(False)
+    assert kt["step_launches"] == 5 and kt["basis_launches"] == 5 and kt["rebase_launches"] == 0
+    assert kt["step_ms"] > 0 and kt["basis_ms"] > 0
+    s.step_moving(*W.moving_coords(w, 6, **MOTION))
+    kt = s.kernel_timing(False)
+    assert kt["step_launches"] == 0 and kt["basis_launches"] == 0
+    s.close()
     m.close()
 
 
