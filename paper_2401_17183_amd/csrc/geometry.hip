@@ -367,12 +367,13 @@ __device__ __forceinline__ void project(const double* gi, const double* v, doubl
   }
 }
 
+// Index on the geometry box (`layers` layers around the real cells) of a real cell.
 template <class L>
-__device__ __forceinline__ long box_index(const int* nb, int layers, int cell, const Box& box, int s0, int s1, int s2) {
+__device__ __forceinline__ long box_index(const int* nb, int layers, int cell, const Box& box) {
   const int x = cell % box.n[0];
   const int y = (cell / box.n[0]) % box.n[1];
   const int z = cell / (box.n[0] * box.n[1]);
-  const int b0 = x + layers + s0, b1 = y + (L::D > 1 ? layers : 0) + s1, b2 = z + (L::D > 2 ? layers : 0) + s2;
+  const int b0 = x + layers, b1 = y + (L::D > 1 ? layers : 0), b2 = z + (L::D > 2 ? layers : 0);
   return b0 + (long)nb[0] * (b1 + (long)nb[1] * b2);
 }
 
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_links_state(StateLinkArgs a) {
   const double* __restrict__ gco = a.gco;
   double* __restrict__ Ain = a.Ain;
   double* __restrict__ A = a.A;
-  const long b0 = box_index<L>(a.nb, a.layers, cell, a.box, 0, 0, 0);
+  const long b0 = box_index<L>(a.nb, a.layers, cell, a.box);
   double gq[D * D], gi[D * D];
 #pragma unroll
   for (int w = 0; w < D * D; ++w) {
